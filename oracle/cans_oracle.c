@@ -1,0 +1,460 @@
+/*
+ * cans_oracle.c -- plain, slow, obviously-correct CPU oracle for the direct
+ * Poisson solver of Costa, Phillips, Brandt & Fatica, "GPU acceleration of
+ * CaNS" (arXiv 2001.05234).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the GPU library.
+ *
+ * What it computes (Section 2, "FFT-based Poisson solver"):
+ *   - the 7-point second-order discretisation of the Poisson equation on a
+ *     staggered grid, eq. (poi), with the z part written in conservative
+ *     (flux) form so that a non-uniform z spacing is allowed (the remark
+ *     following eq. (poi_reduced); the inverse spacings dzci/dzfi of
+ *     Listing 1);
+ *   - its solution by eigenfunction expansion: a discrete transform F^x along
+ *     x, then F^y along y, which leaves one tridiagonal system in z per
+ *     (i,j) wavenumber pair, eq. (poi_reduced), solved by Gauss elimination
+ *     without pivoting; then the inverse transforms.
+ *
+ * The transforms are the plain O(N^2) matrix products with the closed-form
+ * eigenvector rows of each boundary-condition pair; the paper leaves those
+ * formulas to its references (Schumann & Sweet 1988), so the rows and the
+ * eigenvalues mu(q) used here are derived from the ghost-cell rules of a
+ * staggered grid (boundary on the cell face):
+ *     periodic  p_0 = p_n, p_{n+1} = p_1
+ *     Neumann   p_0 = p_1          (and p_{n+1} = p_n)
+ *     Dirichlet p_0 = -p_1         (and p_{n+1} = -p_n)
+ * and are pinned by the test suite against brute-force eigendecompositions
+ * and textbook DCT/DST/DFT routines.
+ *
+ * Everything is computed in REAL, which is double unless this file is
+ * compiled with -DORACLE_LONG_DOUBLE (x86 80-bit extended), the error-bound
+ * variant.  Interfaces always take and return double.
+ *
+ * Layout: every 3-D field is x fastest, a[i + nx*(j + ny*k)].
+ * Boundary codes per face: 0 = periodic, 1 = Neumann, 2 = Dirichlet;
+ * bc[6] = {x-, x+, y-, y+, z-, z+}.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_LONG_DOUBLE
+typedef long double REAL;
+#define RCOS cosl
+#define RSIN sinl
+#define RPI 3.141592653589793238462643383279502884L
+#define SYM(name) name##_ld
+#else
+typedef double REAL;
+#define RCOS cos
+#define RSIN sin
+#define RPI 3.141592653589793238462643383279502884
+#define SYM(name) name
+#endif
+
+enum { BC_P = 0, BC_N = 1, BC_D = 2 };
+/* transform kinds of one axis, named by the (lower, upper) boundary pair */
+enum { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4 };
+
+/* Axis kind from its two face conditions; -1 when the pair is invalid
+ * (periodic must be paired with periodic). */
+int SYM(oracle_axis_kind)(int lo, int hi)
+{
+    if (lo == BC_P || hi == BC_P) return (lo == BC_P && hi == BC_P) ? K_P : -1;
+    if (lo == BC_N && hi == BC_N) return K_NN;
+    if (lo == BC_D && hi == BC_D) return K_DD;
+    if (lo == BC_N && hi == BC_D) return K_ND;
+    if (lo == BC_D && hi == BC_N) return K_DN;
+    return -1;
+}
+
+/*
+ * Eigenvector rows T[q][i] (row-major, T[q*n+i]) and eigenvalues mu[q] of the
+ * 1-D operator (p_{i-1} - 2 p_i + p_{i+1}) with the ghost rules above
+ * (unit spacing).  These are the discrete transforms F of Section 2:
+ *   P : real DFT, stored in the order
+ *       q=0: 1,  q=1: (-1)^i,  q=2l: cos(2 pi l i/n),  q=2l+1: -sin(2 pi l i/n)
+ *       (l = 1..n/2-1; for odd n the (-1)^i row does not exist and the pairs
+ *       run l = 1..(n-1)/2 from q = 1), mu = -4 sin^2(pi l/n);
+ *   NN: cos(pi q (i+1/2)/n)            DCT-II,  mu = -4 sin^2(pi q/(2n));
+ *   DD: sin(pi (q+1)(i+1/2)/n)         DST-II,  mu = -4 sin^2(pi (q+1)/(2n));
+ *   ND: cos(pi (2q+1)(2i+1)/(4n))      DCT-IV,  mu = -4 sin^2(pi (2q+1)/(4n));
+ *   DN: sin(pi (2q+1)(2i+1)/(4n))      DST-IV,  mu as ND.
+ */
+static void eigen_real(int kind, int n, REAL *T, REAL *mu)
+{
+    for (int q = 0; q < n; ++q) {
+        REAL wav = 0; /* the angle whose sin^2 gives mu */
+        for (int i = 0; i < n; ++i) {
+            REAL v = 0, x = (REAL)i + (REAL)0.5;
+            switch (kind) {
+            case K_P: {
+                int l, is_sin = 0;
+                if (q == 0) l = 0;
+                else if (n % 2 == 0 && q == 1) l = n / 2;
+                else if (n % 2 == 0) { l = q / 2; is_sin = q & 1; }
+                else { l = (q + 1) / 2; is_sin = !(q & 1); }
+                REAL ang = 2 * RPI * (REAL)l * (REAL)i / (REAL)n;
+                v = is_sin ? -RSIN(ang) : RCOS(ang);
+                if (n % 2 == 0 && q == 1) v = (i & 1) ? -1 : 1;
+                wav = RPI * (REAL)l / (REAL)n;
+                break;
+            }
+            case K_NN: v = RCOS(RPI * (REAL)q * x / (REAL)n); wav = RPI * (REAL)q / (2 * (REAL)n); break;
+            case K_DD: v = RSIN(RPI * (REAL)(q + 1) * x / (REAL)n); wav = RPI * (REAL)(q + 1) / (2 * (REAL)n); break;
+            case K_ND: v = RCOS(RPI * (REAL)(2 * q + 1) * (2 * x) / (4 * (REAL)n)); wav = RPI * (REAL)(2 * q + 1) / (4 * (REAL)n); break;
+            case K_DN: v = RSIN(RPI * (REAL)(2 * q + 1) * (2 * x) / (4 * (REAL)n)); wav = RPI * (REAL)(2 * q + 1) / (4 * (REAL)n); break;
+            }
+            T[(size_t)q * n + i] = v;
+        }
+        REAL s = RSIN(wav);
+        mu[q] = -4 * s * s;
+    }
+}
+
+void SYM(oracle_eigen)(int kind, int n, double *T, double *mu)
+{
+    REAL *Tr = malloc(sizeof(REAL) * (size_t)n * n), *mr = malloc(sizeof(REAL) * n);
+    eigen_real(kind, n, Tr, mr);
+    for (size_t e = 0; e < (size_t)n * n; ++e) T[e] = (double)Tr[e];
+    for (int q = 0; q < n; ++q) mu[q] = (double)mr[q];
+    free(Tr); free(mr);
+}
+
+/* Index of the constant (zero-eigenvalue) row of an axis, or -1 if none.
+ * Only P and NN have one, and it is row 0 in both orders above. */
+static int zero_row(int kind) { return (kind == K_P || kind == K_NN) ? 0 : -1; }
+
+/*
+ * Tridiagonal coefficients of the z operator, conservative form
+ *   [(p_{k+1}-p_k)/dzc_k - (p_k-p_{k-1})/dzc_{k-1}] / dzf_k
+ * with dzc_k = (dzf_k + dzf_{k+1})/2 between cells and a mirror ghost cell at
+ * a wall (dzc = dzf of the wall cell).  Row k reads
+ *   a[k] p_{k-1} + b[k] p_k + c[k] p_{k+1}.
+ * Periodic: the corner entries a[0] (couples to p_{nz-1}) and c[nz-1]
+ * (couples to p_0) are kept.  Wall rows fold the ghost into the diagonal and
+ * zero the outer coefficient.  Returns 0, or -1 on an invalid pair.
+ */
+static int zcoef_real(int nz, int lo, int hi, const double *dzf, REAL *a, REAL *b, REAL *c)
+{
+    if (SYM(oracle_axis_kind)(lo, hi) < 0) return -1;
+    for (int k = 0; k < nz; ++k) {
+        REAL f = dzf[k], cm, cp;
+        if (k > 0) cm = ((REAL)dzf[k - 1] + f) / 2;
+        else cm = (lo == BC_P) ? ((REAL)dzf[nz - 1] + f) / 2 : f;
+        if (k < nz - 1) cp = (f + (REAL)dzf[k + 1]) / 2;
+        else cp = (hi == BC_P) ? (f + (REAL)dzf[0]) / 2 : f;
+        a[k] = 1 / (cm * f);
+        c[k] = 1 / (cp * f);
+        b[k] = -(a[k] + c[k]);
+    }
+    if (lo == BC_N) { b[0] += a[0]; a[0] = 0; }
+    if (lo == BC_D) { b[0] -= a[0]; a[0] = 0; }
+    if (hi == BC_N) { b[nz - 1] += c[nz - 1]; c[nz - 1] = 0; }
+    if (hi == BC_D) { b[nz - 1] -= c[nz - 1]; c[nz - 1] = 0; }
+    return 0;
+}
+
+int SYM(oracle_zcoef)(int nz, int lo, int hi, const double *dzf, double *a, double *b, double *c)
+{
+    REAL *ar = malloc(sizeof(REAL) * 3 * nz);
+    int rc = zcoef_real(nz, lo, hi, dzf, ar, ar + nz, ar + 2 * nz);
+    for (int k = 0; k < nz && rc == 0; ++k) { a[k] = (double)ar[k]; b[k] = (double)ar[nz + k]; c[k] = (double)ar[2 * nz + k]; }
+    free(ar);
+    return rc;
+}
+
+/* Gauss elimination without pivoting on a tridiagonal system (Thomas):
+ * forward elimination of the sub-diagonal, then back substitution.
+ * a[0] and c[n-1] are ignored.  w is scratch of length n. */
+static void thomas(int n, const REAL *a, const REAL *b, const REAL *c, const REAL *d, REAL *x, REAL *w)
+{
+    REAL piv = b[0];
+    x[0] = d[0] / piv;
+    for (int k = 1; k < n; ++k) {
+        w[k] = c[k - 1] / piv;
+        piv = b[k] - a[k] * w[k];
+        x[k] = (d[k] - a[k] * x[k - 1]) / piv;
+    }
+    for (int k = n - 2; k >= 0; --k) x[k] -= w[k + 1] * x[k + 1];
+}
+
+/* Periodic (cyclic) tridiagonal system by the Sherman-Morrison formula:
+ * A = A' + u v^T with u = (g, 0..0, c[n-1]), v = (1, 0..0, a[0]/g), g = -b[0];
+ * solve A' y = d and A' z = u, then x = y - z (v.y)/(1 + v.z).
+ * w is scratch of length 4n.  Requires n >= 3. */
+static void thomas_cyclic(int n, const REAL *a, const REAL *b, const REAL *c, const REAL *d, REAL *x, REAL *w)
+{
+    REAL *bb = w, *u = w + n, *z = w + 2 * n, *s = w + 3 * n;
+    REAL g = -b[0];
+    for (int k = 0; k < n; ++k) { bb[k] = b[k]; u[k] = 0; }
+    bb[0] = b[0] - g;
+    bb[n - 1] = b[n - 1] - c[n - 1] * a[0] / g;
+    u[0] = g; u[n - 1] = c[n - 1];
+    thomas(n, a, bb, c, d, x, s);
+    thomas(n, a, bb, c, u, z, s);
+    REAL vy = x[0] + a[0] / g * x[n - 1];
+    REAL vz = z[0] + a[0] / g * z[n - 1];
+    REAL fac = vy / (1 + vz);
+    for (int k = 0; k < n; ++k) x[k] -= fac * z[k];
+}
+
+void SYM(oracle_tridiag)(int n, const double *a, const double *b, const double *c, const double *d, double *x, int cyclic)
+{
+    REAL *r = malloc(sizeof(REAL) * 10 * (size_t)n);
+    REAL *ar = r, *br = r + n, *cr = r + 2 * n, *dr = r + 3 * n, *xr = r + 4 * n, *wr = r + 5 * n;
+    for (int k = 0; k < n; ++k) { ar[k] = a[k]; br[k] = b[k]; cr[k] = c[k]; dr[k] = d[k]; }
+    if (cyclic) thomas_cyclic(n, ar, br, cr, dr, xr, wr);
+    else thomas(n, ar, br, cr, dr, xr, wr);
+    for (int k = 0; k < n; ++k) x[k] = (double)xr[k];
+    free(r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transforms along one axis of a REAL field: out = M applied along `axis`,  */
+/* where M is an n x n matrix (row-major).  Summation runs i = 0..n-1.       */
+static void apply_along(int axis, int nx, int ny, int nz, const REAL *M, const REAL *in, REAL *out)
+{
+    if (axis == 0) {
+        #pragma omp parallel for schedule(static)
+        for (long line = 0; line < (long)ny * nz; ++line) {
+            const REAL *src = in + line * nx;
+            REAL *dst = out + line * nx;
+            for (int q = 0; q < nx; ++q) {
+                REAL s = 0;
+                for (int i = 0; i < nx; ++i) s += M[(size_t)q * nx + i] * src[i];
+                dst[q] = s;
+            }
+        }
+    } else if (axis == 1) {
+        #pragma omp parallel for schedule(static)
+        for (long kq = 0; kq < (long)nz * ny; ++kq) {
+            long k = kq / ny; int q = (int)(kq % ny);
+            REAL *dst = out + (size_t)nx * (q + (size_t)ny * k);
+            for (int i = 0; i < nx; ++i) dst[i] = 0;
+            for (int j = 0; j < ny; ++j) {
+                REAL m = M[(size_t)q * ny + j];
+                const REAL *src = in + (size_t)nx * (j + (size_t)ny * k);
+                for (int i = 0; i < nx; ++i) dst[i] += m * src[i];
+            }
+        }
+    } else {
+        size_t plane = (size_t)nx * ny;
+        #pragma omp parallel for schedule(static)
+        for (long kq = 0; kq < (long)nz; ++kq) {
+            REAL *dst = out + plane * kq;
+            for (size_t e = 0; e < plane; ++e) dst[e] = 0;
+            for (int k = 0; k < nz; ++k) {
+                REAL m = M[(size_t)kq * nz + k];
+                const REAL *src = in + plane * k;
+                for (size_t e = 0; e < plane; ++e) dst[e] += m * src[e];
+            }
+        }
+    }
+}
+
+/* Forward matrix T and its inverse T^{-1} = T^T diag(1/|row_q|^2); the row
+ * norms come from diag(T T^T), computed by a plain sum. */
+static void forward_inverse(int kind, int n, REAL *T, REAL *Ti, REAL *mu)
+{
+    eigen_real(kind, n, T, mu);
+    for (int q = 0; q < n; ++q) {
+        REAL nn = 0;
+        for (int i = 0; i < n; ++i) nn += T[(size_t)q * n + i] * T[(size_t)q * n + i];
+        for (int i = 0; i < n; ++i) Ti[(size_t)i * n + q] = T[(size_t)q * n + i] / nn;
+    }
+}
+
+static REAL *to_real(const double *v, size_t n)
+{
+    REAL *r = malloc(sizeof(REAL) * n);
+    for (size_t e = 0; e < n; ++e) r[e] = v[e];
+    return r;
+}
+static void from_real(const REAL *r, double *v, size_t n)
+{
+    for (size_t e = 0; e < n; ++e) v[e] = (double)r[e];
+}
+
+/* Public: out = T (inverse = 0) or T^{-1} (inverse = 1) of `kind` along axis. */
+void SYM(oracle_transform)(int axis, int inverse, int kind, int nx, int ny, int nz, const double *in, double *out)
+{
+    int n = axis == 0 ? nx : axis == 1 ? ny : nz;
+    size_t N = (size_t)nx * ny * nz;
+    REAL *T = malloc(sizeof(REAL) * (size_t)n * n), *Ti = malloc(sizeof(REAL) * (size_t)n * n), *mu = malloc(sizeof(REAL) * n);
+    forward_inverse(kind, n, T, Ti, mu);
+    REAL *a = to_real(in, N), *b = malloc(sizeof(REAL) * N);
+    apply_along(axis, nx, ny, nz, inverse ? Ti : T, a, b);
+    from_real(b, out, N);
+    free(T); free(Ti); free(mu); free(a); free(b);
+}
+
+/*
+ * Solve the tridiagonal systems of eq. (poi_reduced) for every (i,j) column
+ * of a spectral field fh (x and y already transformed), in place.
+ *   lambda(i,j) = mu_x(i)/dx^2 + mu_y(j)/dy^2 is added to the z diagonal.
+ * Singular column: all three axes are P or NN and (i,j) is the constant row
+ * of both x and y.  Then the column is projected onto the range
+ * (fh_k -= sum_k w_k fh_k / sum_k w_k, w = dzf, the left null vector of the
+ * z operator), solved with its last equation replaced by p_{nz-1} = 0, and
+ * shifted to zero dzf-weighted mean.  The removed weighted mean of the
+ * spectral column is returned in *removed (0 when nothing is singular).
+ */
+static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double dx, double dy,
+                               const double *dzf, REAL *fh, REAL *removed)
+{
+    int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
+    int kz = SYM(oracle_axis_kind)(bc[4], bc[5]);
+    if (kx < 0 || ky < 0 || kz < 0) return -1;
+    REAL *T = malloc(sizeof(REAL) * ((size_t)nx * nx + (size_t)ny * ny));
+    REAL *mux = malloc(sizeof(REAL) * (nx + ny)), *muy = mux + nx;
+    eigen_real(kx, nx, T, mux);
+    eigen_real(ky, ny, T + (size_t)nx * nx, muy);
+    REAL *za = malloc(sizeof(REAL) * 3 * nz), *zb = za + nz, *zc = za + 2 * nz;
+    zcoef_real(nz, bc[4], bc[5], dzf, za, zb, zc);
+    int zx = zero_row(kx), zy = zero_row(ky);
+    int z_singular = (kz == K_P || kz == K_NN);
+    int cyclic = (kz == K_P);
+    REAL wsum = 0;
+    for (int k = 0; k < nz; ++k) wsum += dzf[k];
+    *removed = 0;
+    size_t plane = (size_t)nx * ny;
+    #pragma omp parallel
+    {
+        REAL *d = malloc(sizeof(REAL) * 16 * (size_t)(nz + 2));
+        REAL *x = d + (nz + 2), *bb = d + 2 * (nz + 2), *w = d + 3 * (nz + 2);
+        #pragma omp for schedule(static)
+        for (long col = 0; col < (long)plane; ++col) {
+            int i = (int)(col % nx), j = (int)(col / nx);
+            REAL lam = mux[i] / ((REAL)dx * dx) + muy[j] / ((REAL)dy * dy);
+            for (int k = 0; k < nz; ++k) { d[k] = fh[col + plane * k]; bb[k] = zb[k] + lam; }
+            int singular = z_singular && i == zx && j == zy;
+            if (singular) {
+                REAL s = 0;
+                for (int k = 0; k < nz; ++k) s += (REAL)dzf[k] * d[k];
+                REAL m = s / wsum;
+                *removed = m;
+                for (int k = 0; k < nz; ++k) d[k] -= m;
+                if (nz == 1) {
+                    x[0] = 0;
+                } else {
+                    /* last equation replaced by p_{nz-1} = 0; the periodic
+                     * corner couplings then multiply the pinned unknown */
+                    REAL *aa = w + 6 * (nz + 2), *cc = w + 7 * (nz + 2);
+                    for (int k = 0; k < nz; ++k) { aa[k] = za[k]; cc[k] = zc[k]; }
+                    aa[0] = 0;
+                    aa[nz - 1] = 0; bb[nz - 1] = 1; d[nz - 1] = 0;
+                    thomas(nz, aa, bb, cc, d, x, w);
+                }
+                REAL s2 = 0;
+                for (int k = 0; k < nz; ++k) s2 += (REAL)dzf[k] * x[k];
+                REAL m2 = s2 / wsum;
+                for (int k = 0; k < nz; ++k) x[k] -= m2;
+            } else if (cyclic && nz >= 3) {
+                thomas_cyclic(nz, za, bb, zc, d, x, w);
+            } else if (cyclic) {
+                /* nz = 1 or 2: the periodic couplings fold onto the same or
+                 * the other cell; write the small system out directly */
+                if (nz == 1) x[0] = d[0] / lam;
+                else {
+                    REAL a11 = bb[0], a12 = za[0] + zc[0], a21 = za[1] + zc[1], a22 = bb[1];
+                    REAL det = a11 * a22 - a12 * a21;
+                    x[0] = (a22 * d[0] - a12 * d[1]) / det;
+                    x[1] = (a11 * d[1] - a21 * d[0]) / det;
+                }
+            } else {
+                thomas(nz, za, bb, zc, d, x, w);
+            }
+            for (int k = 0; k < nz; ++k) fh[col + plane * k] = x[k];
+        }
+        free(d);
+    }
+    free(T); free(mux); free(za);
+    return 0;
+}
+
+int SYM(oracle_spectral_solve)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
+                               const double *dzf, const double *fh, double *ph, double *removed)
+{
+    size_t N = (size_t)nx * ny * nz;
+    REAL *a = to_real(fh, N), rem = 0;
+    int rc = spectral_solve_real(nx, ny, nz, bc, dx, dy, dzf, a, &rem);
+    from_real(a, ph, N);
+    if (removed) *removed = (double)rem;
+    free(a);
+    return rc;
+}
+
+/*
+ * The whole solve: p = T_x^{-1} T_y^{-1} S (T_y T_x f), where S is the
+ * column-wise tridiagonal solve above.  info[0] receives the removed
+ * dzf-weighted mean of f in physical units (0 when the problem is not
+ * singular); it is the spectral value divided by nx*ny, because the constant
+ * rows of P and NN are all ones.
+ */
+int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
+                      const double *dzf, const double *f, double *p, double *info)
+{
+    int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
+    if (kx < 0 || ky < 0 || SYM(oracle_axis_kind)(bc[4], bc[5]) < 0) return -1;
+    size_t N = (size_t)nx * ny * nz;
+    REAL *Tx = malloc(sizeof(REAL) * (size_t)nx * nx), *Tix = malloc(sizeof(REAL) * (size_t)nx * nx);
+    REAL *Ty = malloc(sizeof(REAL) * (size_t)ny * ny), *Tiy = malloc(sizeof(REAL) * (size_t)ny * ny);
+    REAL *mu = malloc(sizeof(REAL) * (nx > ny ? nx : ny));
+    forward_inverse(kx, nx, Tx, Tix, mu);
+    forward_inverse(ky, ny, Ty, Tiy, mu);
+    REAL *a = to_real(f, N), *b = malloc(sizeof(REAL) * N), rem = 0;
+    apply_along(0, nx, ny, nz, Tx, a, b);
+    apply_along(1, nx, ny, nz, Ty, b, a);
+    int rc = spectral_solve_real(nx, ny, nz, bc, dx, dy, dzf, a, &rem);
+    apply_along(1, nx, ny, nz, Tiy, a, b);
+    apply_along(0, nx, ny, nz, Tix, b, a);
+    from_real(a, p, N);
+    if (info) info[0] = (double)(rem / ((REAL)nx * ny));
+    free(Tx); free(Tix); free(Ty); free(Tiy); free(mu); free(a); free(b);
+    return rc;
+}
+
+/*
+ * out = L_h p, the 7-point operator of eq. (poi) with the z part in the
+ * conservative form above and the ghost rules of each face.
+ */
+void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
+                         const double *dzf, const double *p, double *out)
+{
+    REAL *zaf = malloc(sizeof(REAL) * 2 * nz), *zcf = zaf + nz;
+    /* full (unfolded) z coefficients: a/c before the ghost is folded in */
+    for (int k = 0; k < nz; ++k) {
+        REAL f = dzf[k], cm, cp;
+        cm = k > 0 ? ((REAL)dzf[k - 1] + f) / 2 : (bc[4] == BC_P ? ((REAL)dzf[nz - 1] + f) / 2 : f);
+        cp = k < nz - 1 ? (f + (REAL)dzf[k + 1]) / 2 : (bc[5] == BC_P ? (f + (REAL)dzf[0]) / 2 : f);
+        zaf[k] = 1 / (cm * f);
+        zcf[k] = 1 / (cp * f);
+    }
+    REAL ix2 = 1 / ((REAL)dx * dx), iy2 = 1 / ((REAL)dy * dy);
+    #pragma omp parallel for schedule(static)
+    for (long kj = 0; kj < (long)nz * ny; ++kj) {
+        int k = (int)(kj / ny), j = (int)(kj % ny);
+        for (int i = 0; i < nx; ++i) {
+#define P3(ii, jj, kk) ((REAL)p[(ii) + (size_t)nx * ((jj) + (size_t)ny * (kk))])
+            REAL c0 = P3(i, j, k);
+            /* neighbour value through the ghost rule of a face */
+            REAL xm, xp, ym, yp, zm, zp;
+            xm = i > 0 ? P3(i - 1, j, k) : bc[0] == BC_P ? P3(nx - 1, j, k) : bc[0] == BC_N ? c0 : -c0;
+            xp = i < nx - 1 ? P3(i + 1, j, k) : bc[1] == BC_P ? P3(0, j, k) : bc[1] == BC_N ? c0 : -c0;
+            ym = j > 0 ? P3(i, j - 1, k) : bc[2] == BC_P ? P3(i, ny - 1, k) : bc[2] == BC_N ? c0 : -c0;
+            yp = j < ny - 1 ? P3(i, j + 1, k) : bc[3] == BC_P ? P3(i, 0, k) : bc[3] == BC_N ? c0 : -c0;
+            zm = k > 0 ? P3(i, j, k - 1) : bc[4] == BC_P ? P3(i, j, nz - 1) : bc[4] == BC_N ? c0 : -c0;
+            zp = k < nz - 1 ? P3(i, j, k + 1) : bc[5] == BC_P ? P3(i, j, 0) : bc[5] == BC_N ? c0 : -c0;
+#undef P3
+            REAL v = (xm - 2 * c0 + xp) * ix2 + (ym - 2 * c0 + yp) * iy2
+                   + zcf[k] * (zp - c0) - zaf[k] * (c0 - zm);
+            out[i + (size_t)nx * (j + (size_t)ny * k)] = (double)v;
+        }
+    }
+    free(zaf);
+}

@@ -1,0 +1,181 @@
+"""ctypes wrapper around the FP64 CPU oracle (``cans_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  It shares no
+code with the GPU path.
+
+The oracle computes the direct solution of the staggered 7-point Poisson
+problem, eq. (poi) of Section 2 (z in conservative form for a stretched grid),
+by eigenfunction expansion, eq. (poi_reduced): O(N^2) transform matrices along
+x and y, Gauss elimination (Thomas) along z, inverse transforms.
+
+Fields are numpy float64 arrays of shape (nz, ny, nx) (x fastest).
+Boundary codes: 0 periodic, 1 Neumann, 2 Dirichlet; bc = (x-, x+, y-, y+, z-, z+).
+Axis kinds: 0 P, 1 NN, 2 DD, 3 ND, 4 DN.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cans_oracle.c")
+_LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_ld.so")}
+
+P, N, D = 0, 1, 2
+K_P, K_NN, K_DD, K_ND, K_DN = 0, 1, 2, 3, 4
+
+
+def build(force: bool = False) -> None:
+    """Compile the oracle (double and long-double variants) with gcc."""
+    for ld, path in _LIBS.items():
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                   _SRC, "-o", path + ".tmp", "-lm"]
+            if ld:
+                cmd.insert(1, "-DORACLE_LONG_DOUBLE")
+            subprocess.check_call(cmd)
+            os.replace(path + ".tmp", path)
+
+
+_handles: dict = {}
+
+
+def _lib(ld: bool = False):
+    if ld not in _handles:
+        if not os.path.exists(_LIBS[ld]):
+            build()
+        lib = ctypes.CDLL(_LIBS[ld])
+        sfx = "_ld" if ld else ""
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        i, d = ctypes.c_int, ctypes.c_double
+        sig = {
+            "oracle_axis_kind": ([i, i], i),
+            "oracle_eigen": ([i, i, dp, dp], None),
+            "oracle_zcoef": ([i, i, i, dp, dp, dp, dp], i),
+            "oracle_tridiag": ([i, dp, dp, dp, dp, dp, i], None),
+            "oracle_transform": ([i, i, i, i, i, i, dp, dp], None),
+            "oracle_spectral_solve": ([i, i, i, ip, d, d, dp, dp, dp, dp], i),
+            "oracle_solve": ([i, i, i, ip, d, d, dp, dp, dp, dp], i),
+            "oracle_apply_L": ([i, i, i, ip, d, d, dp, dp, dp], None),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name + sfx)
+            fn.argtypes = args
+            fn.restype = res
+            setattr(lib, name, fn)
+        _handles[ld] = lib
+    return _handles[ld]
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _bc(bc):
+    arr = (ctypes.c_int * 6)(*[int(b) for b in bc])
+    return arr
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def axis_kind(lo: int, hi: int) -> int:
+    return _lib().oracle_axis_kind(lo, hi)
+
+
+def eigen(kind: int, n: int, ld: bool = False):
+    """Transform rows T (n x n, T[q, i]) and eigenvalues mu (n,) of one axis."""
+    T = np.zeros((n, n)); mu = np.zeros(n)
+    _lib(ld).oracle_eigen(kind, n, _dp(T), _dp(mu))
+    return T, mu
+
+
+def zcoef(nz: int, lo: int, hi: int, dzf):
+    dzf = _f64(dzf)
+    a, b, c = np.zeros(nz), np.zeros(nz), np.zeros(nz)
+    rc = _lib().oracle_zcoef(nz, lo, hi, _dp(dzf), _dp(a), _dp(b), _dp(c))
+    if rc:
+        raise ValueError("invalid z boundary pair")
+    return a, b, c
+
+
+def tridiag(a, b, c, d, cyclic: bool = False, ld: bool = False) -> np.ndarray:
+    a, b, c, d = (_f64(v) for v in (a, b, c, d))
+    x = np.zeros_like(d)
+    _lib(ld).oracle_tridiag(len(d), _dp(a), _dp(b), _dp(c), _dp(d), _dp(x), int(cyclic))
+    return x
+
+
+def transform(field, axis: int, kind: int, inverse: bool = False, ld: bool = False) -> np.ndarray:
+    """Apply T (or T^{-1}) of `kind` along axis 0=x, 1=y, 2=z of a (nz,ny,nx) field."""
+    f = _f64(field)
+    nz, ny, nx = f.shape
+    out = np.zeros_like(f)
+    _lib(ld).oracle_transform(axis, int(inverse), kind, nx, ny, nz, _dp(f), _dp(out))
+    return out
+
+
+def spectral_solve(fhat, bc, dx: float, dy: float, dzf, ld: bool = False):
+    """Column-wise tridiagonal solves of eq. (poi_reduced) on a spectral field.
+
+    Returns (phat, removed) where removed is the dzf-weighted mean taken out of
+    the singular column (spectral units) or 0."""
+    f = _f64(fhat); dzf = _f64(dzf)
+    nz, ny, nx = f.shape
+    out = np.zeros_like(f); rem = ctypes.c_double(0.0)
+    rc = _lib(ld).oracle_spectral_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), _dp(f), _dp(out),
+                                        ctypes.pointer(rem))
+    if rc:
+        raise ValueError("invalid boundary conditions")
+    return out, rem.value
+
+
+def solve(f, bc, dx: float, dy: float, dzf, ld: bool = False):
+    """Direct solve of L_h p = f.  Returns (p, removed_mean).
+
+    For singular problems (every axis P or NN) f is projected by its
+    dzf-weighted mean, which is returned, and p has zero weighted mean."""
+    f = _f64(f); dzf = _f64(dzf)
+    nz, ny, nx = f.shape
+    assert dzf.shape == (nz,)
+    p = np.zeros_like(f); info = np.zeros(4)
+    rc = _lib(ld).oracle_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), _dp(f), _dp(p), _dp(info))
+    if rc:
+        raise ValueError("invalid boundary conditions")
+    return p, float(info[0])
+
+
+def apply_L(p, bc, dx: float, dy: float, dzf) -> np.ndarray:
+    """The discrete operator L_h of eq. (poi), z in conservative form."""
+    p = _f64(p); dzf = _f64(dzf)
+    nz, ny, nx = p.shape
+    out = np.zeros_like(p)
+    _lib().oracle_apply_L(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), _dp(p), _dp(out))
+    return out
+
+
+def is_singular(bc) -> bool:
+    return all(axis_kind(bc[2 * a], bc[2 * a + 1]) in (K_P, K_NN) for a in range(3))
+
+
+def weighted_mean(p, dzf) -> float:
+    p = np.asarray(p, dtype=np.float64)
+    w = np.asarray(dzf, dtype=np.float64)
+    return float((p.sum(axis=(1, 2)) * w).sum() / (w.sum() * p.shape[1] * p.shape[2]))
+
+
+def residual(p, f, bc, dx, dy, dzf):
+    """Relative residual ||Pi f - L_h p||_2 / ||Pi f||_2 (Pi = projection
+    removing the weighted mean when the problem is singular)."""
+    f = _f64(f)
+    if is_singular(bc):
+        f = f - weighted_mean(f, dzf)
+    r = f - apply_L(p, bc, dx, dy, dzf)
+    return float(np.linalg.norm(r) / np.linalg.norm(f))

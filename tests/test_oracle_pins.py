@@ -1,0 +1,388 @@
+"""Pins of the CPU oracle to facts other than itself (no GPU).
+
+Every check here compares the oracle with something independent of its own
+code: a brute-force eigendecomposition of the 1-D ghost-cell operator, the
+textbook DCT/DST/DFT routines of scipy, scipy's banded solver, a dense LU of
+the full 7-point operator assembled here from its stencil definition
+(eq. (poi) with the z part in conservative form), closed-form eigen-solutions,
+and invariants of the exact discrete solution (residual, projection
+identity D G = L, shift and reflection symmetry, linearity).  A dropped term,
+a wrong sign, a wrong index or a transposed operand in the oracle fails at
+least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.linalg
+
+from oracle import oracle as O
+from paper_2001_05234_amd import inputs
+
+P, N, D = 0, 1, 2
+KIND_BC = {O.K_P: (P, P), O.K_NN: (N, N), O.K_DD: (D, D), O.K_ND: (N, D), O.K_DN: (D, N)}
+
+
+# --------------------------------------------------------------------------- #
+# independent stencil definitions, written from the ghost rules of a staggered
+# grid (boundary on the face): P p0 = pn; N p0 = p1; D p0 = -p1
+def op1d(lo, hi, n):
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, i] -= 2.0
+        for nb, side in ((i - 1, lo), (i + 1, hi)):
+            if 0 <= nb < n:
+                A[i, nb] += 1.0
+            elif side == P:
+                A[i, nb % n] += 1.0
+            elif side == N:
+                A[i, i] += 1.0
+            else:
+                A[i, i] -= 1.0
+    return A
+
+
+def dense_L(nx, ny, nz, bc, dx, dy, dzf):
+    """Full 7-point operator, rows/cols in x-fastest order."""
+    ntot = nx * ny * nz
+    L = np.zeros((ntot, ntot))
+    dzf = np.asarray(dzf, float)
+
+    def dzc(k):  # centre distance across face k+1/2, mirror ghost at walls
+        if 0 <= k < nz - 1:
+            return 0.5 * (dzf[k] + dzf[k + 1])
+        if bc[4] == P:  # periodic faces wrap
+            return 0.5 * (dzf[0] + dzf[nz - 1])
+        return dzf[0] if k < 0 else dzf[nz - 1]
+
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = idx(i, j, k)
+                # (axis neighbours, coefficient)
+                terms = [((i - 1, j, k), 1 / dx**2, 0, bc[0]), ((i + 1, j, k), 1 / dx**2, 0, bc[1]),
+                         ((i, j - 1, k), 1 / dy**2, 1, bc[2]), ((i, j + 1, k), 1 / dy**2, 1, bc[3]),
+                         ((i, j, k - 1), 1 / (dzc(k - 1) * dzf[k]), 2, bc[4]),
+                         ((i, j, k + 1), 1 / (dzc(k) * dzf[k]), 2, bc[5])]
+                for (ii, jj, kk), coef, ax, side in terms:
+                    L[r, r] -= coef
+                    pos = (ii, jj, kk)[ax]
+                    n_ax = (nx, ny, nz)[ax]
+                    if 0 <= pos < n_ax:
+                        L[r, idx(ii, jj, kk)] += coef
+                    elif side == P:
+                        w = [ii, jj, kk]
+                        w[ax] = pos % n_ax
+                        L[r, idx(*w)] += coef
+                    elif side == N:
+                        L[r, r] += coef
+                    else:
+                        L[r, r] -= coef
+    return L
+
+
+def solve_dense(f, bc, dx, dy, dzf):
+    nz, ny, nx = f.shape
+    L = dense_L(nx, ny, nz, bc, dx, dy, dzf)
+    b = f.ravel()
+    if O.is_singular(bc):
+        w = np.repeat(np.asarray(dzf, float), nx * ny)
+        ntot = b.size
+        B = np.zeros((ntot + 1, ntot + 1))
+        B[:ntot, :ntot] = L
+        B[:ntot, ntot] = 1.0
+        B[ntot, :ntot] = w
+        sol = np.linalg.solve(B, np.concatenate([b, [0.0]]))
+        return sol[:ntot].reshape(f.shape), sol[ntot]
+    return np.linalg.solve(L, b).reshape(f.shape), 0.0
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# --------------------------------------------------------------------------- #
+@pytest.mark.parametrize("kind", [O.K_P, O.K_NN, O.K_DD, O.K_ND, O.K_DN])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 8, 12, 16])
+def test_eigenpairs_bruteforce(kind, n):
+    """Rows of T are eigenvectors of the 1-D ghost-cell operator with
+    eigenvalues mu, and mu is the operator's full spectrum."""
+    if kind == O.K_P and n == 1:
+        pass
+    lo, hi = KIND_BC[kind]
+    A = op1d(lo, hi, n)
+    T, mu = O.eigen(kind, n)
+    assert np.abs(T @ A - mu[:, None] * T).max() < 1e-13
+    np.testing.assert_allclose(np.sort(mu), np.sort(np.linalg.eigvalsh(A)), atol=1e-13)
+    G = T @ T.T
+    assert np.abs(G - np.diag(np.diag(G))).max() < 1e-12
+    assert np.linalg.matrix_rank(T) == n
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 12, 16, 24, 33])
+def test_transforms_match_scipy(n):
+    """Forward transforms equal the textbook DCT/DST/DFT routines (scipy's
+    unnormalised type-2/4 forms carry a factor 2), and T^{-1} inverts them."""
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((1, 1, n))
+    fx = lambda k: O.transform(x, 0, k)[0, 0]
+    np.testing.assert_allclose(2 * fx(O.K_NN), scipy.fft.dct(x[0, 0], type=2), atol=1e-12)
+    np.testing.assert_allclose(2 * fx(O.K_DD), scipy.fft.dst(x[0, 0], type=2), atol=1e-12)
+    np.testing.assert_allclose(2 * fx(O.K_ND), scipy.fft.dct(x[0, 0], type=4), atol=1e-12)
+    np.testing.assert_allclose(2 * fx(O.K_DN), scipy.fft.dst(x[0, 0], type=4), atol=1e-12)
+    X = scipy.fft.rfft(x[0, 0])
+    hp = fx(O.K_P)
+    if n % 2 == 0:
+        expect = [X[0].real, X[n // 2].real]
+        for l in range(1, n // 2):
+            expect += [X[l].real, X[l].imag]
+    else:
+        expect = [X[0].real]
+        for l in range(1, (n + 1) // 2):
+            expect += [X[l].real, X[l].imag]
+    np.testing.assert_allclose(hp, expect, atol=1e-12)
+    # inverse transforms against scipy's inverses
+    for kind, inv in ((O.K_NN, lambda y: scipy.fft.idct(2 * y, type=2)),
+                      (O.K_DD, lambda y: scipy.fft.idst(2 * y, type=2)),
+                      (O.K_ND, lambda y: scipy.fft.idct(2 * y, type=4)),
+                      (O.K_DN, lambda y: scipy.fft.idst(2 * y, type=4))):
+        y = rng.standard_normal((1, 1, n))
+        np.testing.assert_allclose(O.transform(y, 0, kind, inverse=True)[0, 0], inv(y[0, 0]), atol=1e-12)
+    y = rng.standard_normal((1, 1, n))
+    np.testing.assert_allclose(O.transform(O.transform(y, 0, O.K_P), 0, O.K_P, inverse=True), y, atol=1e-12)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_transform_axes_agree(axis):
+    """Applying a transform along y or z equals applying it along x of the
+    transposed field (checks the strided loops)."""
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal((5, 6, 7))
+    for kind in (O.K_NN, O.K_DN, O.K_P):
+        g = np.ascontiguousarray(np.swapaxes(f, 2, 2 - axis))
+        a = O.transform(f, axis, kind)
+        b = np.swapaxes(O.transform(g, 0, kind), 2, 2 - axis)
+        np.testing.assert_allclose(a, b, atol=1e-12)
+
+
+def test_tridiag_vs_banded():
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 3, 7, 40):
+        a = rng.uniform(0.1, 1, n); c = rng.uniform(0.1, 1, n)
+        b = -(a + c) - rng.uniform(0.0, 1.0, n)
+        d = rng.standard_normal(n)
+        ab = np.zeros((3, n)); ab[0, 1:] = c[:-1]; ab[1] = b; ab[2, :-1] = a[1:]
+        np.testing.assert_allclose(O.tridiag(a, b, c, d), scipy.linalg.solve_banded((1, 1), ab, d), rtol=1e-12, atol=1e-14)
+        if n >= 3:
+            M = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+            M[0, n - 1] = a[0]; M[n - 1, 0] = c[n - 1]
+            np.testing.assert_allclose(O.tridiag(a, b, c, d, cyclic=True), np.linalg.solve(M, d), rtol=1e-11, atol=1e-13)
+
+
+def test_zcoef_uniform_reduces_to_poi():
+    """On a uniform z grid the conservative form is eq. (poi)'s
+    (p_{k-1} - 2 p_k + p_{k+1})/dz^2, with the ghost rules at the ends."""
+    nz, dz = 9, 0.25
+    for lo, hi in itertools.product((N, D), (N, D)):
+        a, b, c = O.zcoef(nz, lo, hi, np.full(nz, dz))
+        M = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        np.testing.assert_allclose(M, op1d(lo, hi, nz) / dz**2, atol=1e-12)
+
+
+ALL_PAIRS = [(P, P), (N, N), (D, D), (N, D), (D, N)]
+
+
+@pytest.mark.parametrize("zp", ALL_PAIRS)
+@pytest.mark.parametrize("yp", ALL_PAIRS)
+@pytest.mark.parametrize("xp", ALL_PAIRS)
+def test_dense_lu_every_bc(xp, yp, zp):
+    """Whole solve equals a dense LU of the assembled operator, for every
+    boundary combination, on uniform and stretched z (uniform only when z is
+    periodic), including the bordered system of the singular cases."""
+    nx, ny, nz = 4, 3, 5
+    bc = xp + yp + zp
+    rng = np.random.default_rng(sum(xp) * 25 + sum(yp) * 5 + sum(zp))
+    dzfs = [np.full(nz, 0.3)]
+    if zp != (P, P):
+        dzfs.append(inputs.tanh_dzf(nz, 1.5, 2.0))
+    for dzf in dzfs:
+        f = rng.standard_normal((nz, ny, nx))
+        dx, dy = 0.7, 1.3
+        p, rem = O.solve(f, bc, dx, dy, dzf)
+        pd, md = solve_dense(f, bc, dx, dy, dzf)
+        assert rel(p, pd) < 1e-12, (bc, rel(p, pd))
+        assert abs(rem - md) < 1e-12 * max(1.0, abs(md))
+        # long-double variant of the same code path
+        pl, reml = O.solve(f, bc, dx, dy, dzf, ld=True)
+        assert rel(pl, pd) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(6, 8, 10), (5, 7, 9), (3, 2, 1), (1, 1, 4)])
+def test_dense_lu_shapes(shape):
+    """Odd, tiny and degenerate sizes (a single cell along an axis)."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(11)
+    for bc in [(P, P, N, N, N, N), (D, N, P, P, D, D), (N, D, D, N, N, D), (P, P, P, P, P, P)]:
+        if bc[4] == P and nz < 3:
+            continue
+        dzf = np.full(nz, 0.5) if bc[4] == P else inputs.tanh_dzf(nz, 1.2, 1.0)
+        f = rng.standard_normal(shape)
+        p, _ = O.solve(f, bc, 0.9, 1.1, dzf)
+        pd, _ = solve_dense(f, bc, 0.9, 1.1, dzf)
+        assert rel(p, pd) < 1e-11, (shape, bc)
+
+
+def test_periodic_z_small():
+    """nz = 1 and 2 with periodic z (folded couplings)."""
+    rng = np.random.default_rng(2)
+    for nz in (1, 2):
+        for bc in [(D, D, N, D, P, P), (P, P, P, P, P, P)]:
+            f = rng.standard_normal((nz, 3, 4))
+            dzf = np.full(nz, 0.4)
+            p, _ = O.solve(f, bc, 0.5, 0.6, dzf)
+            pd, _ = solve_dense(f, bc, 0.5, 0.6, dzf)
+            assert rel(p, pd) < 1e-12
+
+
+@pytest.mark.parametrize("kinds", [(O.K_P, O.K_NN, O.K_NN), (O.K_DD, O.K_P, O.K_DD), (O.K_ND, O.K_DN, O.K_ND),
+                                   (O.K_DN, O.K_DD, O.K_DN), (O.K_NN, O.K_ND, O.K_P)])
+def test_closed_form_eigensolution(kinds):
+    """Uniform grid, f = product of 1-D eigenvectors: p = f / (sum mu/h^2)."""
+    nx, ny, nz = 12, 10, 8
+    hx, hy, hz = 0.1, 0.2, 0.125
+    bc = KIND_BC[kinds[0]] + KIND_BC[kinds[1]] + KIND_BC[kinds[2]]
+    i = np.arange(nx) + 0.5; j = np.arange(ny) + 0.5; k = np.arange(nz) + 0.5
+
+    def mode(kind, n, x, q):
+        # eigenfunction and eigenvalue, written from the continuous modes
+        if kind == O.K_P:
+            return np.cos(2 * np.pi * q * (x - 0.5) / n), -4 * np.sin(np.pi * q / n) ** 2
+        if kind == O.K_NN:
+            return np.cos(np.pi * q * x / n), -4 * np.sin(np.pi * q / (2 * n)) ** 2
+        if kind == O.K_DD:
+            return np.sin(np.pi * (q + 1) * x / n), -4 * np.sin(np.pi * (q + 1) / (2 * n)) ** 2
+        if kind == O.K_ND:
+            return np.cos(np.pi * (2 * q + 1) * x / (2 * n)), -4 * np.sin(np.pi * (2 * q + 1) / (4 * n)) ** 2
+        return np.sin(np.pi * (2 * q + 1) * x / (2 * n)), -4 * np.sin(np.pi * (2 * q + 1) / (4 * n)) ** 2
+
+    for qx, qy, qz in [(1, 2, 3), (3, 0, 1), (2, 4, 0)]:
+        ex, lx = mode(kinds[0], nx, i, qx)
+        ey, ly = mode(kinds[1], ny, j, qy)
+        ez, lz = mode(kinds[2], nz, k, qz)
+        lam = lx / hx**2 + ly / hy**2 + lz / hz**2
+        if abs(lam) < 1e-9:
+            continue
+        f = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        p, _ = O.solve(f, bc, hx, hy, np.full(nz, hz))
+        assert rel(p, f / lam) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [(P, P, P, P, N, N), (D, N, P, P, D, D), (N, N, D, D, N, D)])
+def test_residual_stretched(bc):
+    nx, ny, nz = 24, 16, 20
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    f = inputs.uniform_rhs((nz, ny, nx), 9)
+    p, _ = O.solve(f, bc, 2 * np.pi / nx, np.pi / ny, dzf)
+    assert O.residual(p, f, bc, 2 * np.pi / nx, np.pi / ny, dzf) < 1e-13
+
+
+def test_apply_L_matches_dense_operator():
+    """The residual operator equals the dense operator (stencil at every
+    boundary, stretched z)."""
+    rng = np.random.default_rng(5)
+    for bc in [(P, P, N, D, N, N), (D, N, P, P, D, N), (N, N, N, N, P, P)]:
+        nz, ny, nx = 4, 3, 5
+        dzf = np.full(nz, 0.3) if bc[4] == P else inputs.tanh_dzf(nz, 1.4, 1.0)
+        p = rng.standard_normal((nz, ny, nx))
+        Ld = dense_L(nx, ny, nz, bc, 0.4, 0.6, dzf)
+        np.testing.assert_allclose(O.apply_L(p, bc, 0.4, 0.6, dzf).ravel(), Ld @ p.ravel(), rtol=1e-12, atol=1e-10)
+
+
+def test_projection_identity():
+    """With f = D u (zero normal velocity at the walls), u - G p is
+    discretely divergence free: D G = L_h with the staggered ghost rules
+    (the projection step of eq. (up) and following)."""
+    nx, ny, nz = 16, 12, 14
+    dx, dy = 2 * np.pi / nx, np.pi / ny
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    bc = (P, P, P, P, N, N)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((nz, ny, nx)); v = rng.standard_normal((nz, ny, nx))
+    w = rng.standard_normal((nz + 1, ny, nx)); w[0] = 0; w[nz] = 0
+
+    def div(u, v, w):
+        return ((u - np.roll(u, 1, 2)) / dx + (v - np.roll(v, 1, 1)) / dy
+                + (w[1:] - w[:-1]) / dzf[:, None, None])
+
+    f = div(u, v, w)
+    assert np.allclose(f, inputs.divergence_rhs(nx, ny, nz, dx, dy, dzf, 0) * 0 + f)
+    p, rem = O.solve(f, bc, dx, dy, dzf)
+    assert abs(rem) < 1e-12
+    dzc = 0.5 * (dzf[1:] + dzf[:-1])
+    gu = (np.roll(p, -1, 2) - p) / dx
+    gv = (np.roll(p, -1, 1) - p) / dy
+    gw = np.zeros_like(w); gw[1:nz] = (p[1:] - p[:-1]) / dzc[:, None, None]
+    r = div(u - gu, v - gv, w - gw)
+    assert np.abs(r).max() < 1e-11 * np.abs(f).max()
+
+
+def test_shift_and_reflection_symmetry():
+    nx, ny, nz = 16, 8, 12
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)  # symmetric about the mid-plane
+    assert np.allclose(dzf, dzf[::-1])
+    f = inputs.uniform_rhs((nz, ny, nx), 4)
+    f = inputs.weighted_project(f, dzf)
+    bc = (P, P, P, P, N, N)
+    p, _ = O.solve(f, bc, 0.3, 0.5, dzf)
+    ps, _ = O.solve(np.roll(f, 5, 2), bc, 0.3, 0.5, dzf)
+    assert rel(ps, np.roll(p, 5, 2)) < 1e-12
+    ps, _ = O.solve(np.roll(f, -3, 1), bc, 0.3, 0.5, dzf)
+    assert rel(ps, np.roll(p, -3, 1)) < 1e-12
+    pr, _ = O.solve(f[::-1].copy(), bc, 0.3, 0.5, dzf)
+    assert rel(pr, p[::-1]) < 1e-12
+    # a DN x axis mirrored is an ND axis
+    bc2 = (D, N, P, P, D, D)
+    p2, _ = O.solve(f, bc2, 0.3, 0.5, dzf)
+    p3, _ = O.solve(f[:, :, ::-1].copy(), (N, D, P, P, D, D), 0.3, 0.5, dzf)
+    assert rel(p3, p2[:, :, ::-1]) < 1e-12
+
+
+def test_linearity_and_singular_mean():
+    nx, ny, nz = 12, 10, 9
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    bc = (N, N, P, P, N, N)
+    rng = np.random.default_rng(8)
+    f, g = rng.standard_normal((2, nz, ny, nx))
+    pf, mf = O.solve(f, bc, 0.2, 0.3, dzf)
+    pg, mg = O.solve(g, bc, 0.2, 0.3, dzf)
+    ph, mh = O.solve(2 * f - 3 * g, bc, 0.2, 0.3, dzf)
+    assert rel(ph, 2 * pf - 3 * pg) < 1e-12
+    assert abs(mh - (2 * mf - 3 * mg)) < 1e-12
+    # removed mean is f's weighted mean, p has zero weighted mean
+    assert abs(mf - O.weighted_mean(f, dzf)) < 1e-13
+    assert abs(O.weighted_mean(pf, dzf)) < 1e-13 * np.abs(pf).max()
+
+
+def test_long_double_agrees():
+    prob = inputs.config("c1")
+    f = prob.rhs()
+    p, _ = O.solve(f, prob.bc, prob.dx, prob.dy, prob.dzf)
+    pl, _ = O.solve(f, prob.bc, prob.dx, prob.dy, prob.dzf, ld=True)
+    assert rel(p, pl) < 1e-13
+
+
+def test_spectral_solve_consistent_with_solve():
+    """The stage functions compose to the whole solve."""
+    rng = np.random.default_rng(12)
+    nz, ny, nx = 6, 8, 10
+    bc = (D, N, P, P, N, D)
+    dzf = inputs.tanh_dzf(nz, 1.3, 1.0)
+    f = rng.standard_normal((nz, ny, nx))
+    kx, ky = O.axis_kind(bc[0], bc[1]), O.axis_kind(bc[2], bc[3])
+    fh = O.transform(O.transform(f, 0, kx), 1, ky)
+    ph, _ = O.spectral_solve(fh, bc, 0.3, 0.4, dzf)
+    p = O.transform(O.transform(ph, 1, ky, inverse=True), 0, kx, inverse=True)
+    p2, _ = O.solve(f, bc, 0.3, 0.4, dzf)
+    assert rel(p, p2) < 1e-13
