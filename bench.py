@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the direct Poisson solver on one MI355X.
+
+A step is one whole solve of L_h p = f (eq. (poi), Section 2) on the
+1024 x 512 x 384 channel slab (periodic x and y, Neumann walls in z on a
+tanh-stretched grid, rhs = divergence of a seeded random staggered
+velocity): FP32 transforms, FP64 z elimination and FP64 iterative refinement
+to a relative residual of 1e-10, including the final residual check.  The
+plain FP64 solve of the same rhs is timed beside it.  Inputs sit in HBM
+before the timed region.
+
+Printed: one JSON line with grid points per second, the roofline position of
+the dominant kernel (algorithmic bytes / its HIP-event-timed duration), and
+the CPU oracle's rate on a bounded sample of the same grid.
+
+    python bench.py [--steps K] [--warmup W] [--config c3] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Poisson grid pts/s, FP64 vs FP32+refine at 1e-10 residual; achieved HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+# kernels of one refinement-mode solve: debug stage, name, algorithmic bytes
+# per grid point (each reads and writes the field once in its precision)
+KERNELS32 = [
+    (1, "x_fwd (f64 in, f32 out)", 12),
+    (2, "y_fwd f32", 8),
+    (3, "z_solve (f64 arithmetic, f32 io)", 8),
+    (4, "y_inv f32", 8),
+    (5, "x_inv (f32 in, f64 out)", 12),
+    (6, "residual+x_fwd (p, f f64 in; f32 out)", 20),
+    (7, "x_inv+update (f32 + p in, p out)", 20),
+]
+KERNELS64 = [
+    (1, "x_fwd f64", 16),
+    (2, "y_fwd f64", 16),
+    (3, "z_solve f64", 16),
+    (4, "y_inv f64", 16),
+    (5, "x_inv f64", 16),
+]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_solves(plan, fd, pd, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.solve(fd, pd)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    s.record()
+    for _ in range(steps):
+        plan.solve(fd, pd)
+    e.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return s.elapsed_time(e) / steps, wall
+
+
+def time_stage(plan, stage, a, b, reps, torch):
+    """Average duration of one kernel launch, HIP events on the launch stream."""
+    plan.debug_stage(stage, a, b)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        plan.debug_stage(stage, a, b)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def copy_gbs(torch, nbytes):
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(10):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 10
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(pr, f, nz_sample):
+    """The oracle, as it stands, on the first nz_sample z-levels of the grid
+    (full x-y planes: the same per-point work, O(nx + ny) transform
+    multiply-adds plus the z elimination)."""
+    import numpy as np
+
+    from oracle import oracle
+    fs = np.ascontiguousarray(f[:nz_sample])
+    dzs = np.ascontiguousarray(pr.dzf[:nz_sample])
+    t0 = time.perf_counter()
+    oracle.solve(fs, pr.bc, pr.dx, pr.dy, dzs)
+    dt = time.perf_counter() - t0
+    pts = fs.size
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return {"value": pts / dt, "unit": "grid pts/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle solve (O(N^2) transforms + Thomas) of the first {nz_sample} of "
+                      f"{pr.nz} z-levels of the {pr.nx}x{pr.ny}x{pr.nz} grid, {pts} points, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--cpu-sample-levels", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solve-only", action="store_true", help="time the refine solve only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver has no multi-GPU path in this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2001_05234_amd import capi, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    capi.load()
+    pr = inputs.config(args.config)
+    say(f"[bench] generating {args.config} rhs {pr.nx}x{pr.ny}x{pr.nz}")
+    f = pr.rhs()
+    fd = torch.from_numpy(f).cuda()
+    pd = torch.zeros_like(fd)
+    npts = pr.npts
+
+    say("[bench] fp32+refine plan")
+    plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
+                     tol=1e-10, max_iter=4)
+    ms, wall = time_solves(plan, fd, pd, args.steps, args.warmup, torch)
+    info = plan.info()
+    say(f"[bench] refine: {ms:.3f} ms/solve, info {info}")
+    if not info["converged"]:
+        raise SystemExit("refinement did not reach 1e-10")
+    out = {
+        "metric": METRIC, "value": npts / (ms * 1e-3), "unit": "grid pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {pr.nx}x{pr.ny}x{pr.nz} channel slab, bc P/P/N, tanh z a=1.5, "
+                               f"rhs = divergence of seeded N(0,1) staggered velocity; FP32 transforms, FP64 "
+                               f"Thomas + residual, refined to rel. residual 1e-10",
+                   "grid_points": npts, "corrections": info["iterations"],
+                   "residual": info["residual"], "wall_s": wall},
+    }
+    if args.solve_only:
+        print(json.dumps(out), flush=True)
+        return
+
+    # per-kernel durations of the refinement path (HIP events on the stream)
+    a32 = torch.zeros_like(fd)
+    times = {}
+    for stage, name, bpp in KERNELS32:
+        if stage == 6:
+            plan.debug_stage(0, fd, pd)
+        if stage in (1, 6):
+            t = time_stage(plan, stage, fd, pd, args.kernel_reps, torch)
+        else:
+            t = time_stage(plan, stage, fd, a32, args.kernel_reps, torch)
+        times[stage] = t
+        say(f"[bench]   {name:42s} {t:8.3f} ms  {bpp * npts / (t * 1e-3) / 1e9:8.1f} GB/s")
+    nr = info["iterations"]
+    counts = {1: 1, 2: 1 + nr, 3: 1 + nr, 4: 1 + nr, 5: 1, 6: nr + 1, 7: nr}
+    dom = max(times, key=lambda s: counts[s] * times[s])
+    dname, dbpp = [(n, b) for s, n, b in KERNELS32 if s == dom][0]
+    achieved = dbpp * npts / (times[dom] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "algorithmic_bytes_per_point": dbpp, "kernel_ms": times[dom]}
+    out["kernels_ms"] = {n: round(times[s], 4) for s, n, _ in KERNELS32}
+    plan.close()
+    del a32
+
+    # plain FP64 solve of the same rhs
+    say("[bench] fp64 plan")
+    plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64")
+    ms64, _ = time_solves(plan64, fd, pd, max(1, args.steps // 2), 2, torch)
+    k64 = {}
+    b = torch.zeros_like(fd)
+    for stage, name, bpp in KERNELS64:
+        k64[name] = round(time_stage(plan64, stage, fd, b, max(1, args.kernel_reps // 2), torch), 4)
+    out["fp64"] = {"value": npts / (ms64 * 1e-3), "unit": "grid pts/s", "ms_per_step": ms64, "kernels_ms": k64}
+    say(f"[bench] fp64: {ms64:.3f} ms/solve {k64}")
+    plan64.close()
+    del b
+    out["copy_GBps"] = copy_gbs(torch, 1 << 30)
+
+    if not args.no_cpu_baseline:
+        say("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(pr, f, min(args.cpu_sample_levels, pr.nz))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

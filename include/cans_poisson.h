@@ -1,0 +1,189 @@
+/*
+ * cans_poisson.h -- C ABI of the MI355X (gfx950) direct Poisson solver.
+ *
+ * The library solves the second-order finite-difference Poisson equation on a
+ * staggered Cartesian grid, eq. (poi) of Costa et al., "GPU acceleration of
+ * CaNS" (arXiv 2001.05234), Section 2, by eigenfunction expansion
+ * (eq. (poi_reduced)): a real-to-real transform along x, then along y, chosen
+ * by the boundary conditions of each axis (real DFT for periodic, DCT-II for
+ * Neumann-Neumann, DST-II for Dirichlet-Dirichlet, DCT-IV / DST-IV for the
+ * mixed pairs), one tridiagonal solve along z per (kx, ky) pair by Gauss
+ * elimination without pivoting, then the inverse transforms.  x and y are
+ * uniform; z may be stretched (the remark after eq. (poi_reduced)), in which
+ * case the z operator is taken in conservative form
+ *     [(p_{k+1}-p_k)/dzc_k - (p_k-p_{k-1})/dzc_{k-1}] / dzf_k,
+ *     dzc_k = (dzf_k + dzf_{k+1})/2, mirror ghost cell at a wall.
+ * Boundary conditions are homogeneous and located on the cell faces
+ * (staggered): periodic p_0 = p_n; Neumann p_0 = p_1; Dirichlet p_0 = -p_1.
+ *
+ * Layout of every field: double, x fastest, element (i,j,k) at
+ * i + nx*(j + ny*k), i.e. a C array [nz][ny][nx].
+ *
+ * All functions return CANS_OK (0) or a negative cans_status.  Nothing throws
+ * across this interface.  Device pointers are HIP device memory of the
+ * device that was current when the plan was created.
+ */
+#ifndef CANS_POISSON_H
+#define CANS_POISSON_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* boundary condition of one face */
+enum cans_bc {
+    CANS_BC_PERIODIC = 0,
+    CANS_BC_NEUMANN = 1,
+    CANS_BC_DIRICHLET = 2
+};
+
+enum cans_status {
+    CANS_OK = 0,
+    CANS_ERR_INVALID_ARG = -1,  /* bad size, spacing, pointer or boundary pair */
+    CANS_ERR_UNSUPPORTED = -2,  /* valid problem this build does not handle
+                                   (odd, > 4096 or non-{2,3,5}-smooth x/y length,
+                                   periodic z that is stretched or shorter
+                                   than 3 cells) */
+    CANS_ERR_ALLOC = -3,        /* device or host allocation failed */
+    CANS_ERR_HIP = -4,          /* HIP runtime or launch error */
+    CANS_ERR_ALIAS = -5         /* rhs == p where the mode forbids it */
+};
+
+/* arithmetic of the transforms (the z elimination is always FP64) */
+enum cans_precision {
+    CANS_PREC_FP64 = 0,         /* everything FP64 */
+    CANS_PREC_FP32_REFINE = 1   /* FP32 transforms, FP64 z elimination, FP64
+                                   residual and iterative refinement */
+};
+
+/* how the transform along an axis is evaluated */
+enum cans_xform_mode {
+    CANS_XFORM_AUTO = 0,
+    CANS_XFORM_FFT = 1,         /* LDS radix FFT with fused pre/post twiddles */
+    CANS_XFORM_DENSE = 2        /* dense matrix product on the matrix cores
+                                   (FP32_REFINE only; x axis only) */
+};
+
+typedef struct cans_opts {
+    int precision;      /* enum cans_precision, default FP64 */
+    int xform_x;        /* enum cans_xform_mode for x, default AUTO */
+    int xform_y;        /* enum cans_xform_mode for y, default AUTO */
+    double tol;         /* FP32_REFINE: stop when the relative residual
+                           ||Pi f - L p||_2 / ||Pi f||_2 <= tol; default 1e-10 */
+    int max_iter;       /* FP32_REFINE: most refinement steps enqueued per
+                           solve (0..16); default 4 */
+} cans_opts;
+
+#define CANS_HISTORY 17
+
+typedef struct cans_info {
+    int iterations;         /* refinement corrections applied (0 for FP64) */
+    int converged;          /* 1 if the residual test passed (always 1 for FP64) */
+    double residual;        /* last relative residual measured (FP32_REFINE);
+                               -1 when not measured (FP64) */
+    double history[CANS_HISTORY]; /* relative residual before each correction
+                                     and after the last; unused entries -1 */
+    double removed_mean;    /* singular problems (every axis periodic or
+                               Neumann-Neumann): dzf-weighted mean of the rhs
+                               removed to make it compatible; else 0 */
+} cans_info;
+
+typedef struct cans_plan_s *cans_plan_t;
+
+/* Fill *opts with the defaults listed above. */
+void cans_default_opts(cans_opts *opts);
+
+/*
+ * Build a plan for an nx x ny x nz grid (Section 2, eqs. (poi) and
+ * (poi_reduced)).
+ *   bc[6]  = {x-, x+, y-, y+, z-, z+}, enum cans_bc; periodic must be paired
+ *            with periodic on the same axis.
+ *   dx, dy = uniform spacings (> 0).
+ *   dz     = host array of nz cell widths dzf (> 0), copied into the plan; a
+ *            periodic z must be uniform.
+ *   nx, ny even, at most 4096, with nx/2, ny/2 products of 2, 3 and 5;
+ *   nz >= 1 (>= 3 if periodic).
+ * The plan owns its tables and device workspace (allocated on the current
+ * device).  One solve may be in flight per plan at a time.
+ */
+int cans_poisson_plan(cans_plan_t *out, int nx, int ny, int nz, const int bc[6],
+                      double dx, double dy, const double *dz);
+
+/* As cans_poisson_plan, with options (NULL = defaults). */
+int cans_poisson_plan_ex(cans_plan_t *out, int nx, int ny, int nz, const int bc[6],
+                         double dx, double dy, const double *dz, const cans_opts *opts);
+
+/*
+ * Enqueue one solve of L_h p = rhs on `stream` and return; no host
+ * synchronisation.  rhs and p are device arrays of nx*ny*nz doubles owned by
+ * the caller, alive until the stream work completes.  FP64 mode allows
+ * rhs == p (in place); FP32_REFINE re-reads rhs and returns CANS_ERR_ALIAS
+ * for rhs == p.  For a singular problem the rhs is projected on the range
+ * (its dzf-weighted mean removed) and p is returned with zero dzf-weighted
+ * mean.  Errors here are enqueue-time errors only; convergence is reported by
+ * cans_poisson_get_info.
+ */
+int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream);
+
+/* Copy the last solve's cans_info to *out.  Synchronises with the device, so
+ * it is meant to be called after the solve's stream has been synchronised. */
+int cans_poisson_get_info(cans_plan_t plan, cans_info *out);
+
+/* Release the plan and its device memory.  NULL is ignored. */
+void cans_poisson_destroy(cans_plan_t plan);
+
+/* Static text for a status code. */
+const char *cans_status_string(int code);
+
+/* Bytes of device workspace the plan holds. */
+size_t cans_poisson_workspace_bytes(cans_plan_t plan);
+
+/*
+ * Run one stage of a plan on device arrays of nx*ny*nz doubles (test and
+ * timing hook).  FP64 plans (`in` and `out` may be equal):
+ *   1 forward x transform      T_x along x
+ *   2 forward y transform      T_y along y
+ *   3 z solve on spectral data  (columns of eq. (poi_reduced)), rhs scaled by
+ *                               1/(s_x s_y)
+ *   4 inverse y transform      B_y along y
+ *   5 inverse x transform      B_x along x
+ * T is the unnormalised transform: real DFT (rows 1, (-1)^i, cos, -sin of
+ * each wavenumber), DCT-II, DST-II, DCT-IV, DST-IV for P, NN, DD, ND, DN;
+ * B satisfies B T = s I with s = n for P, NN, DD and s = n/2 for ND, DN.  Stages 1..5 composed equal one FP64 solve.
+ * FP32_REFINE plans run single kernels on the plan's internal FP32 field:
+ *   0 clear the refinement state (needed before 6 after a finished solve),
+ *   1 in -> field (forward x), 2 / 4 forward / inverse y, 3 z solve,
+ *   5 field -> out (inverse x), 6 residual of p = out for rhs = in fused with
+ *   the forward x transform, 7 out += inverse x of the field.
+ */
+int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, double *out,
+                             hipStream_t stream);
+
+/* ----------------------------------------------------------------------- */
+/* Batched solves: many independent problems of different sizes and
+ * boundary conditions enqueued as one unit. */
+typedef struct cans_desc {
+    int nx, ny, nz;
+    int bc[6];
+    double dx, dy;
+    const double *dz;   /* host, nz cell widths */
+} cans_desc;
+
+/* Build one plan holding `count` problems (each validated as above). */
+int cans_poisson_plan_batched(cans_plan_t *out, int count, const cans_desc *descs,
+                              const cans_opts *opts);
+
+/* Solve every problem of a batched plan: rhs[i], p[i] are device arrays of
+ * problem i.  Enqueued on `stream` without host synchronisation. */
+int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, double *const *p,
+                               hipStream_t stream);
+
+/* Info of problem `index` of a batched plan (after a stream sync). */
+int cans_poisson_get_info_batched(cans_plan_t plan, int index, cans_info *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CANS_POISSON_H */

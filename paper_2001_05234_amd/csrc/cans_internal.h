@@ -1,0 +1,80 @@
+// cans_internal.h -- plan layout and kernel launchers shared by the host
+// plan code and the HIP kernels (not part of the public ABI).
+#pragma once
+
+#include <vector>
+
+#include "../../include/cans_poisson.h"
+#include "zsolve_core.h"
+
+namespace cans {
+
+// device-side info record of one problem (doubles)
+enum InfoSlot {
+    I_REMOVED = 0,   // removed weighted mean of the rhs (singular problems)
+    I_MEANP = 1,     // weighted mean of p measured by the last residual pass
+    I_ITERS = 2,     // corrections applied
+    I_CONV = 3,      // 1 when the residual test passed
+    I_LAST = 4,      // last relative residual
+    I_HIST = 5,      // CANS_HISTORY entries
+    I_SIZE = I_HIST + CANS_HISTORY
+};
+
+constexpr int kThreads = 256;  // threads per block of the transform kernels
+
+struct Axis {
+    int kind = 0;
+    int n = 0;
+    double h = 1;
+    int s = 1;                 // B T = s I
+    XGeom gx64{}, gx32{};      // tile geometry as an x transform (FP64 / FP32)
+    XGeom gy64{}, gy32{};      // tile geometry as a y transform
+    double *d_lam = nullptr;   // mu(q)/h^2 in the transform's row order
+    cx<double> *d_tw64 = nullptr;
+    cx<float> *d_tw32 = nullptr;
+};
+
+struct Problem {
+    int nx = 0, ny = 0, nz = 0;
+    int bc[6] = {0, 0, 0, 0, 0, 0};
+    Axis ax, ay;
+    std::vector<double> dzf;
+    double wsum = 0;
+    int cyclic = 0, singular = 0;
+    double scale = 1;
+    double *d_za = nullptr, *d_zb = nullptr, *d_zc = nullptr;
+    double *d_zaf = nullptr, *d_zcf = nullptr, *d_dzf = nullptr;
+    // workspace
+    double *wc = nullptr, *wd = nullptr, *wz = nullptr;
+    float *a32 = nullptr;          // FP32 spectral field (refine mode)
+    double *partials = nullptr;    // residual block sums
+    int nres_blocks = 0;
+    double *d_info = nullptr;
+    int *d_flag = nullptr;         // [0] refinement finished
+    size_t npts() const { return (size_t)nx * ny * nz; }
+};
+
+// ---- launchers (kernels.hip) ----------------------------------------------
+// x transform of nlines contiguous lines; dir 1 forward, 0 inverse.
+// Tin/Tout: double or float; epi 0 store, 1 update p += v - info[I_MEANP].
+int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s);
+int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s);
+// (also leaves FP64 block sums of dzf*in in pb.partials for launch_mean_rhs)
+int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *done, hipStream_t s);
+int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipStream_t s);
+int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, const int *done,
+                    hipStream_t s);
+int launch_zsolve_f64(const Problem &pb, double *data, double *removed, hipStream_t s);
+int launch_zsolve_32(const Problem &pb, float *data, double *removed, const int *done, hipStream_t s);
+// refinement: residual fused with the forward x transform (FP32 out), and the
+// residual norm alone; then the reduction that decides convergence.
+int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float *out, const int *done,
+                      hipStream_t s);
+int launch_resid_norm(const Problem &pb, const double *f, const double *p, const int *done, hipStream_t s);
+int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipStream_t s);
+int launch_reset(const Problem &pb, hipStream_t s);
+int launch_mean_rhs(const Problem &pb, hipStream_t s);
+
+int resid_blocks(const Problem &pb);
+
+}  // namespace cans

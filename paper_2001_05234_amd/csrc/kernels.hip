@@ -1,0 +1,438 @@
+// kernels.hip -- gfx950 kernels of the direct Poisson solver (Section 2,
+// eqs. (poi) and (poi_reduced)): LDS-tiled real-to-real transforms along x
+// (contiguous lines) and y (tiles of adjacent x columns, coalesced rows, no
+// global transpose), the FP64 column-wise tridiagonal solve along z (one lane
+// per column, adjacent columns in adjacent lanes), and the FP64 residual /
+// norm kernels of iterative refinement.
+#include <hip/hip_runtime.h>
+
+#include "cans_internal.h"
+
+namespace cans {
+
+struct BlockSync {
+    __device__ void operator()() const { __syncthreads(); }
+};
+
+#define CANS_KIND_SWITCH(kind, ...)                                  \
+    switch (kind) {                                                  \
+    case K_P: { constexpr int KD = K_P; __VA_ARGS__; } break;        \
+    case K_NN: { constexpr int KD = K_NN; __VA_ARGS__; } break;      \
+    case K_DD: { constexpr int KD = K_DD; __VA_ARGS__; } break;      \
+    case K_ND: { constexpr int KD = K_ND; __VA_ARGS__; } break;      \
+    default: { constexpr int KD = K_DN; __VA_ARGS__; } break;        \
+    }
+
+static int check_launch()
+{
+    return hipGetLastError() == hipSuccess ? CANS_OK : CANS_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block sum of three doubles (fixed order): result in lane 0.
+__device__ void block_sum3(double &a, double &b, double &c)
+{
+    __shared__ double red[3][kThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+        c += __shfl_down(c, off, 64);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0; b = 0; c = 0;
+        for (int i = 0; i < kThreads / 64; ++i) { a += red[0][i]; b += red[1][i]; c += red[2][i]; }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// x transform: a block holds L consecutive x lines (rows j + ny*k).
+// EPI 0: out = v;  EPI 1: out = out + v - info[I_MEANP] (refinement update).
+// `wsum_part` (optional): block partial sums of dzf_k * in, in FP64, so the
+// exact weighted mean of the rhs is known in refinement mode.
+template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
+__global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
+                                                      const cx<T> *__restrict__ tw,
+                                                      const double *__restrict__ info,
+                                                      const int *__restrict__ done,
+                                                      const double *__restrict__ dzf, int ny,
+                                                      double *__restrict__ wsum_part)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *b0 = reinterpret_cast<T *>(smem);
+    T *b1 = b0 + g.n * g.L;
+    const int tid = threadIdx.x, n = g.n;
+    const long line0 = (long)blockIdx.x * g.L;
+    double acc = 0;
+    for (int e = tid; e < n * g.L; e += kThreads) {
+        const int l = e / n, i = e - l * n;
+        const long line = line0 + l;
+        T v = T(0);
+        if (line < nlines) {
+            const Tin x = in[line * n + i];
+            if (wsum_part) acc += dzf[line / ny] * (double)x;
+            v = (T)x;
+        }
+        R(b1, g, i, l) = v;
+    }
+    if (wsum_part) {
+        double z1 = 0, z2 = 0;
+        block_sum3(acc, z1, z2);
+        if (tid == 0) {
+            wsum_part[3 * blockIdx.x] = acc;
+            wsum_part[3 * blockIdx.x + 1] = 0;
+            wsum_part[3 * blockIdx.x + 2] = 0;
+        }
+    }
+    __syncthreads();
+    T *res = tile_transform<KIND, FWD>(tid, kThreads, g, b0, b1, tw, BlockSync());
+    const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
+    for (int e = tid; e < n * g.L; e += kThreads) {
+        const int l = e / n, i = e - l * n;
+        const long line = line0 + l;
+        if (line < nlines) {
+            const size_t idx = (size_t)line * n + i;
+            const T v = R(res, g, i, l);
+            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
+            else out[idx] = (Tout)v;
+        }
+    }
+}
+
+// y transform: block (bx, k) holds columns i0 .. i0+L-1 of plane k, all ny
+// rows; each global row segment of L elements is contiguous.
+template <int KIND, bool FWD, typename T, typename Tio>
+__global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, int nx, int ny, XGeom g,
+                                                      const cx<T> *__restrict__ tw,
+                                                      const int *__restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *b0 = reinterpret_cast<T *>(smem);
+    T *b1 = b0 + g.n * g.L;
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * g.L;
+    const size_t base = (size_t)blockIdx.y * nx * ny;
+    for (int e = tid; e < ny * g.L; e += kThreads) {
+        const int l = e & (g.L - 1), j = e >> g.lgL, i = i0 + l;
+        R(b1, g, j, l) = i < nx ? (T)in[base + (size_t)j * nx + i] : T(0);
+    }
+    __syncthreads();
+    T *res = tile_transform<KIND, FWD>(tid, kThreads, g, b0, b1, tw, BlockSync());
+    for (int e = tid; e < ny * g.L; e += kThreads) {
+        const int l = e & (g.L - 1), j = e >> g.lgL, i = i0 + l;
+        if (i < nx) out[base + (size_t)j * nx + i] = (Tio)R(res, g, j, l);
+    }
+}
+
+// Residual of the current p fused with the forward x transform of it:
+//   r = (f - removed mean) - L_h p   (FP64), out = T_x r (FP32);
+// block partial sums of |r|^2, |f - mean|^2 and sum dzf p.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restrict__ f,
+                                                         const double *__restrict__ p, float *out,
+                                                         long nlines, XGeom g,
+                                                         const cx<float> *__restrict__ tw, LapArgs la,
+                                                         const double *__restrict__ dzf,
+                                                         const double *__restrict__ info,
+                                                         double *__restrict__ partials,
+                                                         const int *__restrict__ done)
+{
+    if (*done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *b0 = reinterpret_cast<float *>(smem);
+    float *b1 = b0 + g.n * g.L;
+    const int tid = threadIdx.x, n = g.n;
+    const long line0 = (long)blockIdx.x * g.L;
+    const double mf = info[I_REMOVED];
+    double srr = 0, sff = 0, spw = 0;
+    for (int e = tid; e < n * g.L; e += kThreads) {
+        const int l = e / n, i = e - l * n;
+        const long line = line0 + l;
+        float v = 0.f;
+        if (line < nlines) {
+            const int j = (int)(line % la.ny), k = (int)(line / la.ny);
+            const size_t idx = (size_t)line * n + i;
+            const double fv = f[idx] - mf;
+            const double r = fv - lap_point(p, i, j, k, la);
+            srr += r * r;
+            sff += fv * fv;
+            spw += dzf[k] * p[idx];
+            v = (float)r;
+        }
+        R(b1, g, i, l) = v;
+    }
+    block_sum3(srr, sff, spw);
+    if (tid == 0) {
+        partials[3 * blockIdx.x + 0] = srr;
+        partials[3 * blockIdx.x + 1] = sff;
+        partials[3 * blockIdx.x + 2] = spw;
+    }
+    float *res = tile_transform<KIND, true>(tid, kThreads, g, b0, b1, tw, BlockSync());
+    for (int e = tid; e < n * g.L; e += kThreads) {
+        const int l = e / n, i = e - l * n;
+        const long line = line0 + l;
+        if (line < nlines) out[(size_t)line * n + i] = R(res, g, i, l);
+    }
+}
+
+// Residual norms only (the check after the last correction).
+__global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restrict__ f,
+                                                         const double *__restrict__ p, long nlines,
+                                                         int lines_per_block, LapArgs la,
+                                                         const double *__restrict__ dzf,
+                                                         const double *__restrict__ info,
+                                                         double *__restrict__ partials,
+                                                         const int *__restrict__ done)
+{
+    if (*done) return;
+    const int n = la.nx;
+    const long line0 = (long)blockIdx.x * lines_per_block;
+    const double mf = info[I_REMOVED];
+    double srr = 0, sff = 0, spw = 0;
+    for (int e = threadIdx.x; e < n * lines_per_block; e += kThreads) {
+        const int l = e / n, i = e - l * n;
+        const long line = line0 + l;
+        if (line < nlines) {
+            const int j = (int)(line % la.ny), k = (int)(line / la.ny);
+            const size_t idx = (size_t)line * n + i;
+            const double fv = f[idx] - mf;
+            const double r = fv - lap_point(p, i, j, k, la);
+            srr += r * r;
+            sff += fv * fv;
+            spw += dzf[k] * p[idx];
+        }
+    }
+    block_sum3(srr, sff, spw);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = srr;
+        partials[3 * blockIdx.x + 1] = sff;
+        partials[3 * blockIdx.x + 2] = spw;
+    }
+}
+
+// Sum the block partials in a fixed order, record the relative residual of
+// check number `check` and decide: converged (<= tol) or out of steps.
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nblk,
+                                                       int check, int max_iter, double tol,
+                                                       double inv_wvol, int singular,
+                                                       double *__restrict__ info, int *__restrict__ flag)
+{
+    if (flag[0]) return;
+    double a = 0, b = 0, c = 0;
+    for (int i = threadIdx.x; i < nblk; i += kThreads) {
+        a += partials[3 * i];
+        b += partials[3 * i + 1];
+        c += partials[3 * i + 2];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        const double rel = b > 0 ? sqrt(a / b) : sqrt(a);
+        info[I_HIST + check] = rel;
+        info[I_LAST] = rel;
+        info[I_MEANP] = singular ? c * inv_wvol : 0.0;
+        info[I_ITERS] = check;
+        if (rel <= tol) {
+            info[I_CONV] = 1;
+            flag[0] = 1;
+        } else if (check >= max_iter) {
+            info[I_CONV] = 0;
+            flag[0] = 1;
+        }
+    }
+}
+
+// Exact FP64 weighted mean of the rhs from the first pass's block sums:
+// info[I_REMOVED] = sum dzf f / (nx ny sum dzf) when singular, else 0.
+__global__ __launch_bounds__(kThreads) void k_mean_rhs(const double *__restrict__ partials, int nblk,
+                                                       double inv_wvol, int singular,
+                                                       double *__restrict__ info)
+{
+    double a = 0, b = 0, c = 0;
+    for (int i = threadIdx.x; i < nblk; i += kThreads) a += partials[3 * i];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) info[I_REMOVED] = singular ? a * inv_wvol : 0.0;
+}
+
+// Start-of-solve state, written by a kernel so the sequence can be captured.
+__global__ void k_reset(double *__restrict__ info, int *__restrict__ flag)
+{
+    const int t = threadIdx.x;
+    if (t < I_SIZE) info[t] = (t >= I_HIST || t == I_LAST) ? -1.0 : 0.0;
+    if (t == 0) flag[0] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zsolve(T *data, ZArgs a, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    const size_t col = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= (size_t)a.nx * a.ny) return;
+    zsolve_column(col, data, a);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+static size_t tile_lds(const XGeom &g, size_t elem) { return 2 * (size_t)g.n * g.L * elem; }
+
+int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s)
+{
+    const XGeom &g = pb.ax.gx64;
+    const long nlines = (long)pb.ny * pb.nz;
+    const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
+    const size_t sh = tile_lds(g, sizeof(double));
+    CANS_KIND_SWITCH(pb.ax.kind,
+        if (fwd) hipLaunchKernelGGL((k_xform_x<KD, true, double, double, double, 0>), grid, dim3(kThreads), sh, s,
+                                    in, out, nlines, g, pb.ax.d_tw64, nullptr, nullptr, nullptr, 1, nullptr);
+        else hipLaunchKernelGGL((k_xform_x<KD, false, double, double, double, 0>), grid, dim3(kThreads), sh, s,
+                                in, out, nlines, g, pb.ax.d_tw64, nullptr, nullptr, nullptr, 1, nullptr));
+    return check_launch();
+}
+
+int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s)
+{
+    const XGeom &g = pb.ay.gy64;
+    const dim3 grid((unsigned)((pb.nx + g.L - 1) / g.L), (unsigned)pb.nz);
+    const size_t sh = tile_lds(g, sizeof(double));
+    CANS_KIND_SWITCH(pb.ay.kind,
+        if (fwd) hipLaunchKernelGGL((k_xform_y<KD, true, double, double>), grid, dim3(kThreads), sh, s,
+                                    in, out, pb.nx, pb.ny, g, pb.ay.d_tw64, nullptr);
+        else hipLaunchKernelGGL((k_xform_y<KD, false, double, double>), grid, dim3(kThreads), sh, s,
+                                in, out, pb.nx, pb.ny, g, pb.ay.d_tw64, nullptr));
+    return check_launch();
+}
+
+int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *done, hipStream_t s)
+{
+    const XGeom &g = pb.ax.gx32;
+    const long nlines = (long)pb.ny * pb.nz;
+    const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
+    const size_t sh = tile_lds(g, sizeof(float));
+    CANS_KIND_SWITCH(pb.ax.kind,
+        hipLaunchKernelGGL((k_xform_x<KD, true, float, double, float, 0>), grid, dim3(kThreads), sh, s,
+                           in, out, nlines, g, pb.ax.d_tw32, nullptr, done, pb.d_dzf, pb.ny, pb.partials));
+    return check_launch();
+}
+
+int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipStream_t s)
+{
+    const XGeom &g = pb.ay.gy32;
+    const dim3 grid((unsigned)((pb.nx + g.L - 1) / g.L), (unsigned)pb.nz);
+    const size_t sh = tile_lds(g, sizeof(float));
+    CANS_KIND_SWITCH(pb.ay.kind,
+        if (fwd) hipLaunchKernelGGL((k_xform_y<KD, true, float, float>), grid, dim3(kThreads), sh, s,
+                                    data, data, pb.nx, pb.ny, g, pb.ay.d_tw32, done);
+        else hipLaunchKernelGGL((k_xform_y<KD, false, float, float>), grid, dim3(kThreads), sh, s,
+                                data, data, pb.nx, pb.ny, g, pb.ay.d_tw32, done));
+    return check_launch();
+}
+
+int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, const int *done,
+                    hipStream_t s)
+{
+    const XGeom &g = pb.ax.gx32;
+    const long nlines = (long)pb.ny * pb.nz;
+    const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
+    const size_t sh = tile_lds(g, sizeof(float));
+    CANS_KIND_SWITCH(pb.ax.kind,
+        if (update) hipLaunchKernelGGL((k_xform_x<KD, false, float, float, double, 1>), grid, dim3(kThreads), sh, s,
+                                       in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, 1, nullptr);
+        else hipLaunchKernelGGL((k_xform_x<KD, false, float, float, double, 0>), grid, dim3(kThreads), sh, s,
+                                in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, 1, nullptr));
+    return check_launch();
+}
+
+static ZArgs zargs(const Problem &pb, double *removed)
+{
+    ZArgs a;
+    a.nx = pb.nx; a.ny = pb.ny; a.nz = pb.nz;
+    a.za = pb.d_za; a.zb = pb.d_zb; a.zc = pb.d_zc;
+    a.lamx = pb.ax.d_lam; a.lamy = pb.ay.d_lam;
+    a.dzf = pb.d_dzf; a.wsum = pb.wsum; a.scale = pb.scale;
+    a.cyclic = pb.cyclic; a.singular = pb.singular;
+    a.wc = pb.wc; a.wd = pb.wd; a.wz = pb.wz;
+    a.removed = removed;
+    return a;
+}
+
+int launch_zsolve_f64(const Problem &pb, double *data, double *removed, hipStream_t s)
+{
+    const size_t plane = (size_t)pb.nx * pb.ny;
+    hipLaunchKernelGGL(k_zsolve<double>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data,
+                       zargs(pb, removed), nullptr);
+    return check_launch();
+}
+
+int launch_zsolve_32(const Problem &pb, float *data, double *removed, const int *done, hipStream_t s)
+{
+    const size_t plane = (size_t)pb.nx * pb.ny;
+    hipLaunchKernelGGL(k_zsolve<float>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data,
+                       zargs(pb, removed), done);
+    return check_launch();
+}
+
+static LapArgs lapargs(const Problem &pb)
+{
+    LapArgs la;
+    la.nx = pb.nx; la.ny = pb.ny; la.nz = pb.nz;
+    for (int i = 0; i < 6; ++i) la.bc[i] = pb.bc[i];
+    la.idx2 = 1.0 / (pb.ax.h * pb.ax.h);
+    la.idy2 = 1.0 / (pb.ay.h * pb.ay.h);
+    la.zaf = pb.d_zaf; la.zcf = pb.d_zcf;
+    return la;
+}
+
+int resid_blocks(const Problem &pb)
+{
+    const long nlines = (long)pb.ny * pb.nz;
+    return (int)((nlines + pb.ax.gx32.L - 1) / pb.ax.gx32.L);
+}
+
+int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float *out, const int *done,
+                      hipStream_t s)
+{
+    const XGeom &g = pb.ax.gx32;
+    const long nlines = (long)pb.ny * pb.nz;
+    const dim3 grid((unsigned)resid_blocks(pb));
+    const size_t sh = tile_lds(g, sizeof(float));
+    CANS_KIND_SWITCH(pb.ax.kind,
+        hipLaunchKernelGGL(k_resid_xfwd<KD>, grid, dim3(kThreads), sh, s, f, p, out, nlines, g,
+                           pb.ax.d_tw32, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done));
+    return check_launch();
+}
+
+int launch_resid_norm(const Problem &pb, const double *f, const double *p, const int *done, hipStream_t s)
+{
+    const long nlines = (long)pb.ny * pb.nz;
+    hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)resid_blocks(pb)), dim3(kThreads), 0, s, f, p, nlines,
+                       pb.ax.gx32.L, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done);
+    return check_launch();
+}
+
+int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipStream_t s)
+{
+    const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb), check, max_iter,
+                       tol, inv_wvol, pb.singular, pb.d_info, pb.d_flag);
+    return check_launch();
+}
+
+int launch_mean_rhs(const Problem &pb, hipStream_t s)
+{
+    const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
+    hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb), inv_wvol,
+                       pb.singular, pb.d_info);
+    return check_launch();
+}
+
+int launch_reset(const Problem &pb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, pb.d_info, pb.d_flag);
+    return check_launch();
+}
+
+}  // namespace cans

@@ -1,0 +1,357 @@
+// plan.hip -- host side of the C ABI: validation, the per-axis tables of the
+// eigenfunction expansion (Section 2: modified wavenumbers, transform
+// twiddles, conservative z coefficients for a stretched z), device
+// workspace, and the order of kernel launches of one solve.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cans_internal.h"
+#include "tables.h"
+
+using namespace cans;
+
+struct cans_plan_s {
+    int device = 0;
+    cans_opts opts{};
+    std::vector<Problem> probs;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+};
+
+namespace {
+
+template <typename T>
+int upload(cans_plan_s *pl, T **dst, const T *src, size_t count)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return CANS_ERR_ALLOC;
+    pl->allocs.push_back(p);
+    pl->bytes += count * sizeof(T);
+    if (src && hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return CANS_ERR_HIP;
+    *dst = static_cast<T *>(p);
+    return CANS_OK;
+}
+
+template <typename T>
+int alloc(cans_plan_s *pl, T **dst, size_t count)
+{
+    return upload<T>(pl, dst, nullptr, count);
+}
+
+#define CANS_TRY(x) do { int rc_ = (x); if (rc_ != CANS_OK) return rc_; } while (0)
+
+int validate(int nx, int ny, int nz, const int *bc, double dx, double dy, const double *dz)
+{
+    if (!bc || !dz || nx < 1 || ny < 1 || nz < 1) return CANS_ERR_INVALID_ARG;
+    if (!(dx > 0) || !(dy > 0) || !std::isfinite(dx) || !std::isfinite(dy)) return CANS_ERR_INVALID_ARG;
+    for (int i = 0; i < 6; ++i)
+        if (bc[i] < 0 || bc[i] > 2) return CANS_ERR_INVALID_ARG;
+    if (axis_kind(bc[0], bc[1]) < 0 || axis_kind(bc[2], bc[3]) < 0 || axis_kind(bc[4], bc[5]) < 0)
+        return CANS_ERR_INVALID_ARG;
+    for (int k = 0; k < nz; ++k)
+        if (!(dz[k] > 0) || !std::isfinite(dz[k])) return CANS_ERR_INVALID_ARG;
+    // even lengths up to 4096 (an FP64 line tile of two LDS buffers fits 64 KiB)
+    if (nx % 2 || ny % 2 || nx > 4096 || ny > 4096) return CANS_ERR_UNSUPPORTED;
+    XGeom g{};
+    if (!factor(nx / 2, g) || !factor(ny / 2, g)) return CANS_ERR_UNSUPPORTED;
+    if (bc[4] == CANS_BC_PERIODIC) {
+        if (nz < 3) return CANS_ERR_UNSUPPORTED;
+        for (int k = 1; k < nz; ++k)
+            if (std::fabs(dz[k] - dz[0]) > 1e-12 * dz[0]) return CANS_ERR_UNSUPPORTED;
+    }
+    return CANS_OK;
+}
+
+int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
+{
+    a.kind = kind;
+    a.n = n;
+    a.h = h;
+    a.s = xform_scale(kind, n);
+    const int M = n / 2;
+    set_tile(a.gx64, n, tile_x(n, 8));
+    set_tile(a.gx32, n, tile_x(n, 4));
+    set_tile(a.gy64, n, tile_y(n, 8));
+    set_tile(a.gy32, n, tile_y(n, 4));
+    for (XGeom *g : {&a.gx64, &a.gx32, &a.gy64, &a.gy32})
+        if (!factor(M, *g)) return CANS_ERR_UNSUPPORTED;
+    std::vector<cx<double>> t64 = twiddles(n);
+    std::vector<cx<float>> t32(t64.size());
+    for (size_t i = 0; i < t64.size(); ++i) t32[i] = mk((float)t64[i].re, (float)t64[i].im);
+    CANS_TRY(upload(pl, &a.d_tw64, t64.data(), t64.size()));
+    CANS_TRY(upload(pl, &a.d_tw32, t32.data(), t32.size()));
+    std::vector<double> lam = lambdas(kind, n, h);
+    CANS_TRY(upload(pl, &a.d_lam, lam.data(), n));
+    return CANS_OK;
+}
+
+int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const int *bc, double dx, double dy,
+                  const double *dz)
+{
+    pb.nx = nx; pb.ny = ny; pb.nz = nz;
+    for (int i = 0; i < 6; ++i) pb.bc[i] = bc[i];
+    pb.dzf.assign(dz, dz + nz);
+    const int kx = axis_kind(bc[0], bc[1]), ky = axis_kind(bc[2], bc[3]), kz = axis_kind(bc[4], bc[5]);
+    CANS_TRY(build_axis(pl, pb.ax, kx, nx, dx));
+    CANS_TRY(build_axis(pl, pb.ay, ky, ny, dy));
+    pb.cyclic = kz == K_P;
+    pb.singular = (kx == K_P || kx == K_NN) && (ky == K_P || ky == K_NN) && (kz == K_P || kz == K_NN);
+    pb.scale = 1.0 / ((double)pb.ax.s * (double)pb.ay.s);
+    long double ws = 0;
+    for (int k = 0; k < nz; ++k) ws += dz[k];
+    pb.wsum = (double)ws;
+    std::vector<double> a, b, c, af, cf;
+    zcoef(nz, bc[4], bc[5], pb.dzf, a, b, c, af, cf);
+    CANS_TRY(upload(pl, &pb.d_za, a.data(), nz));
+    CANS_TRY(upload(pl, &pb.d_zb, b.data(), nz));
+    CANS_TRY(upload(pl, &pb.d_zc, c.data(), nz));
+    CANS_TRY(upload(pl, &pb.d_zaf, af.data(), nz));
+    CANS_TRY(upload(pl, &pb.d_zcf, cf.data(), nz));
+    CANS_TRY(upload(pl, &pb.d_dzf, pb.dzf.data(), nz));
+    // workspace: elimination multipliers and modified rhs (FP64 fields)
+    const size_t N = pb.npts();
+    CANS_TRY(alloc(pl, &pb.wc, N));
+    CANS_TRY(alloc(pl, &pb.wd, N));
+    if (pb.cyclic) CANS_TRY(alloc(pl, &pb.wz, N));
+    if (pl->opts.precision == CANS_PREC_FP32_REFINE) {
+        CANS_TRY(alloc(pl, &pb.a32, N));
+        pb.nres_blocks = resid_blocks(pb);
+        CANS_TRY(alloc(pl, &pb.partials, 3 * (size_t)pb.nres_blocks));
+    }
+    std::vector<double> info(I_SIZE, 0.0);
+    CANS_TRY(upload(pl, &pb.d_info, info.data(), I_SIZE));
+    int zero = 0;
+    CANS_TRY(upload(pl, &pb.d_flag, &zero, 1));
+    return CANS_OK;
+}
+
+int check_opts(const cans_opts &o)
+{
+    if (o.precision != CANS_PREC_FP64 && o.precision != CANS_PREC_FP32_REFINE) return CANS_ERR_INVALID_ARG;
+    if (o.max_iter < 0 || o.max_iter > CANS_HISTORY - 1) return CANS_ERR_INVALID_ARG;
+    if (!(o.tol >= 0) || !std::isfinite(o.tol)) return CANS_ERR_INVALID_ARG;
+    for (int m : {o.xform_x, o.xform_y})
+        if (m != CANS_XFORM_AUTO && m != CANS_XFORM_FFT) return CANS_ERR_UNSUPPORTED;
+    return CANS_OK;
+}
+
+void free_plan(cans_plan_s *pl)
+{
+    for (void *p : pl->allocs) (void)hipFree(p);
+    delete pl;
+}
+
+int solve_fp64(const Problem &pb, const double *rhs, double *p, hipStream_t s)
+{
+    CANS_TRY(launch_x_f64(pb, true, rhs, p, s));
+    CANS_TRY(launch_y_f64(pb, true, p, p, s));
+    CANS_TRY(launch_zsolve_f64(pb, p, pb.d_info + I_REMOVED, s));
+    CANS_TRY(launch_y_f64(pb, false, p, p, s));
+    CANS_TRY(launch_x_f64(pb, false, p, p, s));
+    return CANS_OK;
+}
+
+// FP32 transforms, FP64 z elimination (the removed mean of a singular rhs
+// is reduced in FP64 from the rhs itself); then up to max_iter corrections
+// e = A^{-1} r with r = Pi f - L p in FP64, p <- p + e - mean(p).  Each step
+// starts with a residual check; a finished flag on the device makes the
+// remaining kernels return at once, so no host synchronisation is needed.
+int solve_refine(const Problem &pb, const cans_opts &o, const double *rhs, double *p, hipStream_t s)
+{
+    const int *done = pb.d_flag;
+    CANS_TRY(launch_reset(pb, s));
+    CANS_TRY(launch_x_fwd_32(pb, rhs, pb.a32, nullptr, s));
+    CANS_TRY(launch_mean_rhs(pb, s));
+    CANS_TRY(launch_y_32(pb, true, pb.a32, nullptr, s));
+    CANS_TRY(launch_zsolve_32(pb, pb.a32, nullptr, nullptr, s));
+    CANS_TRY(launch_y_32(pb, false, pb.a32, nullptr, s));
+    CANS_TRY(launch_x_inv_32(pb, pb.a32, p, false, nullptr, s));
+    for (int it = 0; it < o.max_iter; ++it) {
+        CANS_TRY(launch_resid_xfwd(pb, rhs, p, pb.a32, done, s));
+        CANS_TRY(launch_finalize(pb, it, o.max_iter, o.tol, s));
+        CANS_TRY(launch_y_32(pb, true, pb.a32, done, s));
+        CANS_TRY(launch_zsolve_32(pb, pb.a32, nullptr, done, s));
+        CANS_TRY(launch_y_32(pb, false, pb.a32, done, s));
+        CANS_TRY(launch_x_inv_32(pb, pb.a32, p, true, done, s));
+    }
+    CANS_TRY(launch_resid_norm(pb, rhs, p, done, s));
+    CANS_TRY(launch_finalize(pb, o.max_iter, o.max_iter, o.tol, s));
+    return CANS_OK;
+}
+
+int fill_info(const Problem &pb, int precision, cans_info *out)
+{
+    double h[I_SIZE];
+    if (hipMemcpy(h, pb.d_info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return CANS_ERR_HIP;
+    std::memset(out, 0, sizeof(*out));
+    out->removed_mean = h[I_REMOVED];
+    for (int i = 0; i < CANS_HISTORY; ++i) out->history[i] = -1;
+    if (precision == CANS_PREC_FP64) {
+        out->iterations = 0;
+        out->converged = 1;
+        out->residual = -1;
+        return CANS_OK;
+    }
+    out->iterations = (int)h[I_ITERS];
+    out->converged = (int)h[I_CONV];
+    out->residual = h[I_LAST];
+    for (int i = 0; i < CANS_HISTORY; ++i) out->history[i] = h[I_HIST + i];
+    return CANS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cans_default_opts(cans_opts *o)
+{
+    if (!o) return;
+    o->precision = CANS_PREC_FP64;
+    o->xform_x = CANS_XFORM_AUTO;
+    o->xform_y = CANS_XFORM_AUTO;
+    o->tol = 1e-10;
+    o->max_iter = 4;
+}
+
+const char *cans_status_string(int code)
+{
+    switch (code) {
+    case CANS_OK: return "ok";
+    case CANS_ERR_INVALID_ARG: return "invalid argument";
+    case CANS_ERR_UNSUPPORTED: return "unsupported problem";
+    case CANS_ERR_ALLOC: return "allocation failed";
+    case CANS_ERR_HIP: return "HIP runtime error";
+    case CANS_ERR_ALIAS: return "rhs and p alias";
+    default: return "unknown status";
+    }
+}
+
+int cans_poisson_plan_ex(cans_plan_t *out, int nx, int ny, int nz, const int bc[6], double dx, double dy,
+                         const double *dz, const cans_opts *opts)
+{
+    if (!out) return CANS_ERR_INVALID_ARG;
+    *out = nullptr;
+    cans_desc d;
+    d.nx = nx; d.ny = ny; d.nz = nz;
+    if (bc) for (int i = 0; i < 6; ++i) d.bc[i] = bc[i];
+    d.dx = dx; d.dy = dy; d.dz = dz;
+    if (!bc) return CANS_ERR_INVALID_ARG;
+    return cans_poisson_plan_batched(out, 1, &d, opts);
+}
+
+int cans_poisson_plan(cans_plan_t *out, int nx, int ny, int nz, const int bc[6], double dx, double dy,
+                      const double *dz)
+{
+    return cans_poisson_plan_ex(out, nx, ny, nz, bc, dx, dy, dz, nullptr);
+}
+
+int cans_poisson_plan_batched(cans_plan_t *out, int count, const cans_desc *descs, const cans_opts *opts)
+{
+    if (!out || count < 1 || !descs) return CANS_ERR_INVALID_ARG;
+    *out = nullptr;
+    cans_opts o;
+    cans_default_opts(&o);
+    if (opts) o = *opts;
+    CANS_TRY(check_opts(o));
+    for (int i = 0; i < count; ++i)
+        CANS_TRY(validate(descs[i].nx, descs[i].ny, descs[i].nz, descs[i].bc, descs[i].dx, descs[i].dy,
+                          descs[i].dz));
+    cans_plan_s *pl = new (std::nothrow) cans_plan_s();
+    if (!pl) return CANS_ERR_ALLOC;
+    pl->opts = o;
+    if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return CANS_ERR_HIP; }
+    pl->probs.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const cans_desc &d = descs[i];
+        int rc = build_problem(pl, pl->probs[i], d.nx, d.ny, d.nz, d.bc, d.dx, d.dy, d.dz);
+        if (rc != CANS_OK) { free_plan(pl); return rc; }
+    }
+    *out = pl;
+    return CANS_OK;
+}
+
+int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream)
+{
+    if (!plan || !rhs || !p || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
+    const Problem &pb = plan->probs[0];
+    if (plan->opts.precision == CANS_PREC_FP64) return solve_fp64(pb, rhs, p, stream);
+    if ((const void *)rhs == (const void *)p) return CANS_ERR_ALIAS;
+    return solve_refine(pb, plan->opts, rhs, p, stream);
+}
+
+int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, double *const *p, hipStream_t stream)
+{
+    if (!plan || !rhs || !p) return CANS_ERR_INVALID_ARG;
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        if (!rhs[i] || !p[i]) return CANS_ERR_INVALID_ARG;
+        if (plan->opts.precision != CANS_PREC_FP64 && (const void *)rhs[i] == (const void *)p[i])
+            return CANS_ERR_ALIAS;
+    }
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const Problem &pb = plan->probs[i];
+        int rc = plan->opts.precision == CANS_PREC_FP64 ? solve_fp64(pb, rhs[i], p[i], stream)
+                                                        : solve_refine(pb, plan->opts, rhs[i], p[i], stream);
+        if (rc != CANS_OK) return rc;
+    }
+    return CANS_OK;
+}
+
+int cans_poisson_get_info(cans_plan_t plan, cans_info *out)
+{
+    if (!plan || !out) return CANS_ERR_INVALID_ARG;
+    return fill_info(plan->probs[0], plan->opts.precision, out);
+}
+
+int cans_poisson_get_info_batched(cans_plan_t plan, int index, cans_info *out)
+{
+    if (!plan || !out || index < 0 || index >= (int)plan->probs.size()) return CANS_ERR_INVALID_ARG;
+    return fill_info(plan->probs[index], plan->opts.precision, out);
+}
+
+size_t cans_poisson_workspace_bytes(cans_plan_t plan) { return plan ? plan->bytes : 0; }
+
+int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, double *out, hipStream_t stream)
+{
+    if (!plan || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
+    const Problem &pb = plan->probs[0];
+    if (plan->opts.precision == CANS_PREC_FP32_REFINE) {
+        // single kernels of the refinement path on the plan's FP32 field
+        switch (stage) {
+        case 1: return in ? launch_x_fwd_32(pb, in, pb.a32, nullptr, stream) : CANS_ERR_INVALID_ARG;
+        case 2: return launch_y_32(pb, true, pb.a32, nullptr, stream);
+        case 3: return launch_zsolve_32(pb, pb.a32, nullptr, nullptr, stream);
+        case 4: return launch_y_32(pb, false, pb.a32, nullptr, stream);
+        case 5: return out ? launch_x_inv_32(pb, pb.a32, out, false, nullptr, stream) : CANS_ERR_INVALID_ARG;
+        case 0: return launch_reset(pb, stream);
+        case 6:
+            if (!in || !out) return CANS_ERR_INVALID_ARG;
+            return launch_resid_xfwd(pb, in, out, pb.a32, pb.d_flag, stream);
+        case 7: return out ? launch_x_inv_32(pb, pb.a32, out, true, nullptr, stream) : CANS_ERR_INVALID_ARG;
+        default: return CANS_ERR_INVALID_ARG;
+        }
+    }
+    if (!in || !out) return CANS_ERR_INVALID_ARG;
+    switch (stage) {
+    case 1: return launch_x_f64(pb, true, in, out, stream);
+    case 2: return launch_y_f64(pb, true, in, out, stream);
+    case 3:
+        if (in != out && hipMemcpyAsync(out, in, pb.npts() * sizeof(double), hipMemcpyDeviceToDevice, stream) !=
+                             hipSuccess)
+            return CANS_ERR_HIP;
+        return launch_zsolve_f64(pb, out, pb.d_info + I_REMOVED, stream);
+    case 4: return launch_y_f64(pb, false, in, out, stream);
+    case 5: return launch_x_f64(pb, false, in, out, stream);
+    default: return CANS_ERR_INVALID_ARG;
+    }
+}
+
+void cans_poisson_destroy(cans_plan_t plan)
+{
+    if (plan) free_plan(plan);
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// tables.h -- host-side tables of the eigenfunction expansion (Section 2):
+// the boundary pair of each axis, the FFT radix plan and tile shape, the
+// modified wavenumbers mu(q) of each transform row, the transform twiddles,
+// and the conservative z coefficients of a stretched z.  Computed in long
+// double and rounded once.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "../../include/cans_poisson.h"
+#include "xform_core.h"
+
+namespace cans {
+
+inline int axis_kind(int lo, int hi)
+{
+    if (lo == CANS_BC_PERIODIC || hi == CANS_BC_PERIODIC)
+        return (lo == CANS_BC_PERIODIC && hi == CANS_BC_PERIODIC) ? K_P : -1;
+    if (lo == CANS_BC_NEUMANN && hi == CANS_BC_NEUMANN) return K_NN;
+    if (lo == CANS_BC_DIRICHLET && hi == CANS_BC_DIRICHLET) return K_DD;
+    if (lo == CANS_BC_NEUMANN && hi == CANS_BC_DIRICHLET) return K_ND;
+    if (lo == CANS_BC_DIRICHLET && hi == CANS_BC_NEUMANN) return K_DN;
+    return -1;
+}
+
+// Radix plan of an M-point FFT: 8s first, then the remaining power of two,
+// then 3s and 5s.  Returns false if M has another prime factor.
+inline bool factor(int M, XGeom &g)
+{
+    int r = M, nst = 0;
+    int rads[kMaxStages];
+    while (r % 8 == 0 && nst < kMaxStages) { rads[nst++] = 8; r /= 8; }
+    if (r % 4 == 0 && nst < kMaxStages) { rads[nst++] = 4; r /= 4; }
+    if (r % 2 == 0 && nst < kMaxStages) { rads[nst++] = 2; r /= 2; }
+    while (r % 3 == 0 && nst < kMaxStages) { rads[nst++] = 3; r /= 3; }
+    while (r % 5 == 0 && nst < kMaxStages) { rads[nst++] = 5; r /= 5; }
+    if (r != 1) return false;
+    g.nst = nst;
+    int s = 1;
+    for (int i = 0; i < nst; ++i) { g.rad[i] = rads[i]; g.str[i] = s; s *= rads[i]; }
+    return true;
+}
+
+inline int pow2floor(long v)
+{
+    int p = 1;
+    while ((long)p * 2 <= v) p *= 2;
+    return p;
+}
+
+inline void set_tile(XGeom &g, int n, int L)
+{
+    g.n = n;
+    g.M = n / 2;
+    g.L = L;
+    g.lgL = 0;
+    while ((1 << g.lgL) < L) ++g.lgL;
+}
+
+// modified wavenumber mu(q) of row q (unit spacing)
+inline long double mu_row(int kind, int n, int q)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double th;
+    switch (kind) {
+    case K_P: {
+        const int l = q == 0 ? 0 : (q == 1 ? n / 2 : q / 2);
+        th = pi * l / n;
+        break;
+    }
+    case K_NN: th = pi * q / (2.0L * n); break;
+    case K_DD: th = pi * (q + 1) / (2.0L * n); break;
+    default: th = pi * (2 * q + 1) / (4.0L * n); break;
+    }
+    const long double s = sinl(th);
+    return -4.0L * s * s;
+}
+
+
+// Tile shapes: x lines hold ~2048 (FP64) / 4096 (FP32) reals per tile; y
+// tiles keep their two LDS buffers within 64 KiB.
+inline int tile_x(int n, int elem) { return std::min(64, pow2floor(std::max(1, (elem == 8 ? 2048 : 4096) / n))); }
+inline int tile_y(int n, int elem)
+{
+    return std::min(elem == 8 ? 16 : 32, pow2floor(std::max<long>(1, 65536 / (2L * n * elem))));
+}
+
+// Twiddles of an n-point transform (layout in xform_core.h).
+inline std::vector<cx<double>> twiddles(int n)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const int M = n / 2;
+    std::vector<cx<double>> t(tw_size(M));
+    auto put = [&](int idx, long double ang) { t[idx] = mk((double)cosl(ang), (double)sinl(ang)); };
+    for (int j = 0; j < M; ++j) put(tw_fft(M) + j, -2 * pi * j / M);
+    for (int k = 0; k < M; ++k) put(tw_split(M) + k, -2 * pi * k / n);
+    for (int q = 0; q <= M; ++q) put(tw_qw(M) + q, pi * q / (2.0L * n));
+    for (int m = 0; m < M; ++m) put(tw_pre4(M) + m, -pi * (4 * m + 1) / (4.0L * n));
+    for (int k = 0; k < M; ++k) put(tw_post4(M) + k, -pi * k / n);
+    return t;
+}
+
+// mu(q)/h^2 for every row q of an axis
+inline std::vector<double> lambdas(int kind, int n, double h)
+{
+    std::vector<double> lam(n);
+    for (int q = 0; q < n; ++q) lam[q] = (double)(mu_row(kind, n, q) / ((long double)h * h));
+    return lam;
+}
+
+// Conservative z coefficients of cells 0..nz-1.  Folded (a, b, c): wall
+// ghost rules applied to the diagonal, for the tridiagonal solve.  Unfolded
+// (af, cf): bare face couplings with ghost spacing at walls, for the
+// residual stencil.
+inline void zcoef(int nz, int lo, int hi, const std::vector<double> &dzf, std::vector<double> &a,
+                  std::vector<double> &b, std::vector<double> &c, std::vector<double> &af,
+                  std::vector<double> &cf)
+{
+    a.assign(nz, 0); b.assign(nz, 0); c.assign(nz, 0); af.assign(nz, 0); cf.assign(nz, 0);
+    for (int k = 0; k < nz; ++k) {
+        const long double f = dzf[k];
+        long double cm, cp;
+        if (k > 0) cm = (dzf[k - 1] + f) / 2;
+        else cm = lo == CANS_BC_PERIODIC ? (dzf[nz - 1] + f) / 2 : f;
+        if (k < nz - 1) cp = (f + dzf[k + 1]) / 2;
+        else cp = hi == CANS_BC_PERIODIC ? (f + dzf[0]) / 2 : f;
+        const long double ak = 1 / (cm * f), ck = 1 / (cp * f);
+        af[k] = (double)ak;
+        cf[k] = (double)ck;
+        a[k] = (double)ak;
+        c[k] = (double)ck;
+        b[k] = (double)-(ak + ck);
+    }
+    // wall rows: Neumann p_ghost = p, Dirichlet p_ghost = -p
+    if (lo == CANS_BC_NEUMANN) { b[0] = (double)((long double)b[0] + af[0]); a[0] = 0; }
+    if (lo == CANS_BC_DIRICHLET) { b[0] = (double)((long double)b[0] - af[0]); a[0] = 0; }
+    if (hi == CANS_BC_NEUMANN) { b[nz - 1] = (double)((long double)b[nz - 1] + cf[nz - 1]); c[nz - 1] = 0; }
+    if (hi == CANS_BC_DIRICHLET) { b[nz - 1] = (double)((long double)b[nz - 1] - cf[nz - 1]); c[nz - 1] = 0; }
+}
+
+// normalisation s of B T = s I
+inline int xform_scale(int kind, int n) { return (kind == K_ND || kind == K_DN) ? n / 2 : n; }
+
+}  // namespace cans

@@ -1,0 +1,228 @@
+// cans_emu.cpp -- host build of the GPU library's kernel arithmetic, for the
+// CPU test suite.  It runs the same tile transforms (xform_core.h), the same
+// column solve and residual (zsolve_core.h) and the same tables (tables.h)
+// serially on the host, tile by tile with the kernels' tile shapes, so the
+// index math of the HIP path is checked against the oracle without a GPU.
+// Test infrastructure: nothing in the library uses it.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "tables.h"
+#include "zsolve_core.h"
+
+using namespace cans;
+
+namespace {
+
+struct NoSync {
+    void operator()() const {}
+};
+
+template <int KIND, bool FWD, typename T>
+T *run_tile(const XGeom &g, T *b0, T *b1, const cx<T> *tw)
+{
+    return tile_transform<KIND, FWD>(0, 1, g, b0, b1, tw, NoSync());
+}
+
+template <typename T>
+T *dispatch(int kind, bool fwd, const XGeom &g, T *b0, T *b1, const cx<T> *tw)
+{
+#define CASE(K)                                                             \
+    case K: return fwd ? run_tile<K, true>(g, b0, b1, tw) : run_tile<K, false>(g, b0, b1, tw);
+    switch (kind) {
+        CASE(K_P) CASE(K_NN) CASE(K_DD) CASE(K_ND) CASE(K_DN)
+    }
+#undef CASE
+    return nullptr;
+}
+
+template <typename T>
+std::vector<cx<T>> tw_as(int n)
+{
+    std::vector<cx<double>> t = twiddles(n);
+    std::vector<cx<T>> o(t.size());
+    for (size_t i = 0; i < t.size(); ++i) o[i] = mk((T)t[i].re, (T)t[i].im);
+    return o;
+}
+
+// transform along x (axis 0) or y (axis 1) of a (nz, ny, nx) field, in place
+template <typename T>
+int xform(int kind, bool fwd, int axis, int nx, int ny, int nz, std::vector<T> &a)
+{
+    const int n = axis == 0 ? nx : ny;
+    XGeom g{};
+    set_tile(g, n, axis == 0 ? tile_x(n, sizeof(T)) : tile_y(n, sizeof(T)));
+    if (!factor(n / 2, g)) return -2;
+    std::vector<cx<T>> tw = tw_as<T>(n);
+    std::vector<T> buf(2 * (size_t)n * g.L);
+    T *b0 = buf.data(), *b1 = b0 + (size_t)n * g.L;
+    if (axis == 0) {
+        const long nlines = (long)ny * nz;
+        for (long line0 = 0; line0 < nlines; line0 += g.L) {
+            for (int l = 0; l < g.L; ++l)
+                for (int i = 0; i < n; ++i)
+                    R(b1, g, i, l) = line0 + l < nlines ? a[(size_t)(line0 + l) * n + i] : T(0);
+            T *res = dispatch<T>(kind, fwd, g, b0, b1, tw.data());
+            for (int l = 0; l < g.L && line0 + l < nlines; ++l)
+                for (int i = 0; i < n; ++i) a[(size_t)(line0 + l) * n + i] = R(res, g, i, l);
+        }
+    } else {
+        for (int k = 0; k < nz; ++k)
+            for (int i0 = 0; i0 < nx; i0 += g.L) {
+                const size_t base = (size_t)k * nx * ny;
+                for (int j = 0; j < n; ++j)
+                    for (int l = 0; l < g.L; ++l)
+                        R(b1, g, j, l) = i0 + l < nx ? a[base + (size_t)j * nx + i0 + l] : T(0);
+                T *res = dispatch<T>(kind, fwd, g, b0, b1, tw.data());
+                for (int j = 0; j < n; ++j)
+                    for (int l = 0; l < g.L && i0 + l < nx; ++l) a[base + (size_t)j * nx + i0 + l] = R(res, g, j, l);
+            }
+    }
+    return 0;
+}
+
+struct Setup {
+    int nx, ny, nz, bc[6], kx, ky, kz;
+    double dx, dy;
+    std::vector<double> dzf, za, zb, zc, zaf, zcf, lamx, lamy, wc, wd, wz;
+    ZArgs z;
+    LapArgs la;
+};
+
+int setup(Setup &s, int nx, int ny, int nz, const int *bc, double dx, double dy, const double *dz)
+{
+    s.nx = nx; s.ny = ny; s.nz = nz; s.dx = dx; s.dy = dy;
+    for (int i = 0; i < 6; ++i) s.bc[i] = bc[i];
+    s.kx = axis_kind(bc[0], bc[1]); s.ky = axis_kind(bc[2], bc[3]); s.kz = axis_kind(bc[4], bc[5]);
+    if (s.kx < 0 || s.ky < 0 || s.kz < 0) return -1;
+    s.dzf.assign(dz, dz + nz);
+    zcoef(nz, bc[4], bc[5], s.dzf, s.za, s.zb, s.zc, s.zaf, s.zcf);
+    s.lamx = lambdas(s.kx, nx, dx);
+    s.lamy = lambdas(s.ky, ny, dy);
+    const size_t N = (size_t)nx * ny * nz;
+    s.wc.assign(N, 0); s.wd.assign(N, 0); s.wz.assign(N, 0);
+    ZArgs &z = s.z;
+    z.nx = nx; z.ny = ny; z.nz = nz;
+    z.za = s.za.data(); z.zb = s.zb.data(); z.zc = s.zc.data();
+    z.lamx = s.lamx.data(); z.lamy = s.lamy.data();
+    z.dzf = s.dzf.data();
+    long double ws = 0;
+    for (int k = 0; k < nz; ++k) ws += dz[k];
+    z.wsum = (double)ws;
+    z.scale = 1.0 / ((double)xform_scale(s.kx, nx) * (double)xform_scale(s.ky, ny));
+    z.cyclic = s.kz == K_P;
+    z.singular = (s.kx == K_P || s.kx == K_NN) && (s.ky == K_P || s.ky == K_NN) && (s.kz == K_P || s.kz == K_NN);
+    z.wc = s.wc.data(); z.wd = s.wd.data(); z.wz = s.wz.data();
+    z.removed = nullptr;
+    LapArgs &la = s.la;
+    la.nx = nx; la.ny = ny; la.nz = nz;
+    for (int i = 0; i < 6; ++i) la.bc[i] = bc[i];
+    la.idx2 = 1.0 / (dx * dx); la.idy2 = 1.0 / (dy * dy);
+    la.zaf = s.zaf.data(); la.zcf = s.zcf.data();
+    return 0;
+}
+
+template <typename T>
+void solve_pass(Setup &s, std::vector<T> &a, double *removed)
+{
+    xform<T>(s.kx, true, 0, s.nx, s.ny, s.nz, a);
+    xform<T>(s.ky, true, 1, s.nx, s.ny, s.nz, a);
+    s.z.removed = removed;
+    for (size_t col = 0; col < (size_t)s.nx * s.ny; ++col) zsolve_column(col, a.data(), s.z);
+    xform<T>(s.ky, false, 1, s.nx, s.ny, s.nz, a);
+    xform<T>(s.kx, false, 0, s.nx, s.ny, s.nz, a);
+}
+
+}  // namespace
+
+extern "C" {
+
+// One transform along axis 0 (x) or 1 (y), FP64 (prec 64) or FP32 (prec 32).
+int emu_xform(int kind, int fwd, int axis, int prec, int nx, int ny, int nz, const double *in, double *out)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    int rc;
+    if (prec == 64) {
+        std::vector<double> a(in, in + N);
+        rc = xform<double>(kind, fwd != 0, axis, nx, ny, nz, a);
+        std::memcpy(out, a.data(), N * sizeof(double));
+    } else {
+        std::vector<float> a(N);
+        for (size_t e = 0; e < N; ++e) a[e] = (float)in[e];
+        rc = xform<float>(kind, fwd != 0, axis, nx, ny, nz, a);
+        for (size_t e = 0; e < N; ++e) out[e] = a[e];
+    }
+    return rc;
+}
+
+// The column solves on spectral data (in place), as the z kernel does.
+int emu_zsolve(int nx, int ny, int nz, const int *bc, double dx, double dy, const double *dz, double *data,
+               double *removed)
+{
+    Setup s;
+    if (setup(s, nx, ny, nz, bc, dx, dy, dz)) return -1;
+    s.z.removed = removed;
+    for (size_t col = 0; col < (size_t)nx * ny; ++col) zsolve_column(col, data, s.z);
+    return 0;
+}
+
+// Whole solve: FP64 pipeline (max_iter < 0), or FP32 transforms with FP64
+// refinement (the library's refine sequence); info = {removed mean,
+// corrections, converged, last residual, history[max_iter+1]}.
+int emu_solve(int nx, int ny, int nz, const int *bc, double dx, double dy, const double *dz, int max_iter,
+              double tol, const double *f, double *p, double *info)
+{
+    Setup s;
+    if (setup(s, nx, ny, nz, bc, dx, dy, dz)) return -1;
+    const size_t N = (size_t)nx * ny * nz;
+    double removed = 0;
+    if (max_iter < 0) {
+        std::vector<double> a(f, f + N);
+        solve_pass<double>(s, a, &removed);
+        std::memcpy(p, a.data(), N * sizeof(double));
+        info[0] = removed;
+        return 0;
+    }
+    std::vector<float> a(N);
+    for (size_t e = 0; e < N; ++e) a[e] = (float)f[e];
+    solve_pass<float>(s, a, nullptr);
+    for (size_t e = 0; e < N; ++e) p[e] = a[e];
+    const double inv_wvol = 1.0 / (s.z.wsum * nx * ny);
+    if (s.z.singular) {
+        double acc = 0;
+        for (size_t e = 0; e < N; ++e) acc += s.dzf[e / ((size_t)nx * ny)] * f[e];
+        removed = acc * inv_wvol;
+    }
+    info[0] = removed;
+    int it = 0, conv = 0;
+    double rel = -1;
+    for (;; ++it) {
+        double rr = 0, ff = 0, pw = 0;
+        std::vector<double> r(N);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    const size_t e = i + (size_t)nx * (j + (size_t)ny * k);
+                    const double fv = f[e] - removed;
+                    r[e] = fv - lap_point(p, i, j, k, s.la);
+                    rr += r[e] * r[e];
+                    ff += fv * fv;
+                    pw += s.dzf[k] * p[e];
+                }
+        rel = ff > 0 ? std::sqrt(rr / ff) : std::sqrt(rr);
+        info[4 + it] = rel;
+        const double mp = s.z.singular ? pw * inv_wvol : 0.0;
+        if (rel <= tol) { conv = 1; break; }
+        if (it >= max_iter) break;
+        for (size_t e = 0; e < N; ++e) a[e] = (float)r[e];
+        solve_pass<float>(s, a, nullptr);
+        for (size_t e = 0; e < N; ++e) p[e] = p[e] + (double)a[e] - mp;
+    }
+    info[1] = it;
+    info[2] = conv;
+    info[3] = rel;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+"""The library's kernel arithmetic, built for the host and run serially
+(tests/emu), against the oracle -- index math of every transform family,
+radix, tile shape and the z solve, checked without a GPU."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_05234_amd import inputs
+from tests.emu import emu
+
+P, N, D = 0, 1, 2
+PAIRS = [(P, P), (N, N), (D, D), (N, D), (D, N)]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def scale(kind, n):
+    return n // 2 if kind in (O.K_ND, O.K_DN) else n
+
+
+@pytest.mark.parametrize("shape", [(3, 8, 12), (2, 6, 16), (2, 48, 72), (1, 10, 2), (2, 40, 30),
+                                   (1, 4, 256), (1, 256, 4), (2, 18, 20)])
+@pytest.mark.parametrize("kind", range(5))
+def test_transforms_fp64(shape, kind):
+    """Forward T and inverse B (B T = s I) along x and y, every family;
+    lengths cover radices 2, 3, 4, 5, 8, n = 2 and ragged tiles."""
+    rng = np.random.default_rng(sum(shape) + kind)
+    f = rng.standard_normal(shape)
+    nz, ny, nx = shape
+    for axis, n in ((0, nx), (1, ny)):
+        T = O.transform(f, axis, kind)
+        assert rel(emu.xform(f, kind, True, axis), T) < 1e-13
+        Bi = scale(kind, n) * O.transform(f, axis, kind, inverse=True)
+        assert rel(emu.xform(f, kind, False, axis), Bi) < 1e-13
+        assert rel(emu.xform(f, kind, True, axis, prec=32), T) < 2e-6
+
+
+@pytest.mark.parametrize("zp", PAIRS)
+@pytest.mark.parametrize("yp", PAIRS)
+@pytest.mark.parametrize("xp", PAIRS)
+def test_solve_every_bc(xp, yp, zp):
+    bc = xp + yp + zp
+    nx, ny, nz = 12, 10, 7
+    dzf = np.full(nz, 0.3) if zp == (P, P) else inputs.tanh_dzf(nz, 1.5, 2.0)
+    rng = np.random.default_rng(sum(bc))
+    f = rng.standard_normal((nz, ny, nx))
+    po, mo = O.solve(f, bc, 0.3, 0.4, dzf)
+    pe, info = emu.solve(f, bc, 0.3, 0.4, dzf)
+    assert rel(pe, po) < 1e-12
+    assert abs(info[0] - mo) < 1e-12 * max(1, abs(mo))
+    pr, info = emu.solve(f, bc, 0.3, 0.4, dzf, max_iter=6, tol=1e-12)
+    if O.is_singular(bc):
+        pr = pr - O.weighted_mean(pr, dzf)
+        assert abs(info[0] - mo) < 1e-13 * max(1, abs(mo))
+    assert info[2] == 1 and info[3] <= 1e-12
+    assert rel(pr, po) < 1e-10
+
+
+def test_zsolve_stage():
+    rng = np.random.default_rng(4)
+    for bc in [(P, P, N, N, N, N), (D, N, P, P, D, D), (P, P, P, P, P, P), (N, N, N, N, N, D)]:
+        nz, ny, nx = 9, 6, 8
+        dzf = np.full(nz, 0.2) if bc[4] == P else inputs.tanh_dzf(nz, 1.5, 2.0)
+        fh = rng.standard_normal((nz, ny, nx))
+        ph, rem = O.spectral_solve(fh, bc, 0.3, 0.5, dzf)
+        kx, ky = O.axis_kind(bc[0], bc[1]), O.axis_kind(bc[2], bc[3])
+        pe, reme = emu.zsolve(fh, bc, 0.3, 0.5, dzf)
+        s = scale(kx, nx) * scale(ky, ny)
+        assert rel(pe * s, ph) < 1e-12
+        assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
+
+
+def test_c1_refine_converges():
+    pr = inputs.config("c1")
+    f = pr.rhs()
+    po, _ = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+    p, info = emu.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, max_iter=4, tol=1e-10)
+    assert info[2] == 1 and info[1] == 1
+    assert rel(p - O.weighted_mean(p, pr.dzf), po) < 1e-11
+    # the update keeps the weighted mean pinned to FP64 accuracy
+    assert abs(O.weighted_mean(p, pr.dzf)) < 1e-14 * np.abs(po).max()

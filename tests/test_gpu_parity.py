@@ -1,0 +1,219 @@
+"""GPU parity of the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Tolerances: FP64 path ||p - p_oracle|| / ||p_oracle|| <= 1e-12; FP32 transforms
+with FP64 refinement: relative residual <= 1e-10 (the convergence target) and
+parity <= 1e-8 (error/residual ratio measured about 1-10 on these grids).
+Singular problems are compared after removing the dzf-weighted mean of both
+fields (their solution is unique up to a constant).
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_05234_amd import capi, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P, N, D = 0, 1, 2
+PAIRS = [(P, P), (N, N), (D, D), (N, D), (D, N)]
+TOL64 = 1e-12
+TOL_REF = 1e-8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def demean(p, bc, dzf):
+    return p - O.weighted_mean(p, dzf) if O.is_singular(bc) else p
+
+
+def gpu_solve(f, bc, dx, dy, dzf, precision="fp64", tol=1e-10, max_iter=4, inplace=False):
+    nz, ny, nx = f.shape
+    plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf, precision=precision, tol=tol, max_iter=max_iter)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    if inplace:
+        plan.solve(fd, fd)
+        pd = fd
+    else:
+        pd = torch.zeros_like(fd)
+        plan.solve(fd, pd)
+    torch.cuda.synchronize()
+    out = pd.cpu().numpy()
+    info = plan.info()
+    plan.close()
+    return out, info
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    capi.load()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("bc", [(P, P, P, P, N, N), (D, N, P, P, D, D), (N, D, N, N, N, D),
+                                (D, D, D, N, P, P), (N, N, D, D, D, N)])
+def test_stage_parity(bc):
+    """Each stage of the FP64 pipeline against the oracle's stage."""
+    nx, ny, nz = 24, 20, 10
+    dzf = np.full(nz, 0.1) if bc[4] == P else inputs.tanh_dzf(nz, 1.5, 2.0)
+    dx, dy = 0.25, 0.3
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((nz, ny, nx))
+    kx, ky = O.axis_kind(bc[0], bc[1]), O.axis_kind(bc[2], bc[3])
+    sx = nx // 2 if kx in (O.K_ND, O.K_DN) else nx
+    sy = ny // 2 if ky in (O.K_ND, O.K_DN) else ny
+    say("stage parity", bc)
+    plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf)
+    a = torch.from_numpy(f).cuda()
+    b = torch.zeros_like(a)
+
+    def stage(s, x):
+        plan.debug_stage(s, torch.from_numpy(np.ascontiguousarray(x)).cuda(), b)
+        torch.cuda.synchronize()
+        return b.cpu().numpy()
+
+    s1 = O.transform(f, 0, kx)
+    assert rel(stage(1, f), s1) < 1e-13
+    s2 = O.transform(s1, 1, ky)
+    assert rel(stage(2, s1), s2) < 1e-13
+    s3, _ = O.spectral_solve(s2, bc, dx, dy, dzf)
+    assert rel(stage(3, s2) * (sx * sy), s3) < 1e-12
+    s4 = O.transform(s3, 1, ky, inverse=True)
+    assert rel(stage(4, s3), sy * s4) < 1e-13
+    s5 = O.transform(s4, 0, kx, inverse=True)
+    assert rel(stage(5, s4), sx * s5) < 1e-13
+    plan.close()
+    del a
+
+
+@pytest.mark.parametrize("zp", PAIRS)
+@pytest.mark.parametrize("yp", PAIRS)
+@pytest.mark.parametrize("xp", PAIRS)
+def test_fp64_every_bc(xp, yp, zp):
+    """All 125 boundary combinations, uniform and stretched z."""
+    bc = xp + yp + zp
+    nx, ny, nz = 16, 12, 10
+    rng = np.random.default_rng(sum(bc) + 7)
+    f = rng.standard_normal((nz, ny, nx))
+    for dzf in ([np.full(nz, 0.1)] + ([] if zp == (P, P) else [inputs.tanh_dzf(nz, 1.5, 2.0)])):
+        say("fp64 bc", bc, "stretched" if dzf[0] != dzf[1] else "uniform")
+        po, mo = O.solve(f, bc, 0.2, 0.3, dzf)
+        pg, info = gpu_solve(f, bc, 0.2, 0.3, dzf)
+        assert rel(pg, po) < TOL64
+        assert abs(info["removed_mean"] - mo) < 1e-12 * max(1.0, abs(mo))
+
+
+@pytest.mark.parametrize("shape", [(1, 2, 2), (1, 2, 4), (5, 6, 10), (3, 40, 72), (2, 2, 512), (4, 512, 2),
+                                   (7, 30, 50), (1, 96, 128), (3, 24, 1024)])
+def test_fp64_shapes(shape):
+    """Degenerate, ragged-tile and long-line shapes (radices 2..8, 3, 5)."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(nx + ny + nz)
+    f = rng.standard_normal(shape)
+    for bc in [(P, P, N, N, N, N), (D, N, P, P, D, D), (N, D, D, D, N, D)]:
+        dzf = inputs.tanh_dzf(nz, 1.2, 1.0)
+        say("fp64 shape", shape, bc)
+        po, _ = O.solve(f, bc, 0.3, 0.7, dzf)
+        pg, _ = gpu_solve(f, bc, 0.3, 0.7, dzf)
+        assert rel(pg, po) < TOL64
+
+
+def test_periodic_z_cyclic():
+    rng = np.random.default_rng(9)
+    for bc in [(D, D, N, D, P, P), (P, P, P, P, P, P), (N, N, P, P, P, P)]:
+        f = rng.standard_normal((12, 10, 8))
+        say("cyclic z", bc)
+        po, _ = O.solve(f, bc, 0.3, 0.2, np.full(12, 0.25))
+        pg, _ = gpu_solve(f, bc, 0.3, 0.2, np.full(12, 0.25))
+        assert rel(pg, po) < TOL64
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_fp64_config_full(name):
+    pr = inputs.config(name)
+    f = pr.rhs()
+    say("fp64 config", name)
+    po, mo = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+    pg, info = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+    assert rel(pg, po) < TOL64
+    assert abs(info["removed_mean"] - mo) < 1e-13
+    assert abs(O.weighted_mean(pg, pr.dzf)) < 1e-14 * np.abs(po).max()
+    assert O.residual(pg, f, pr.bc, pr.dx, pr.dy, pr.dzf) < 1e-12
+
+
+def test_fp64_inplace_and_deterministic():
+    pr = inputs.config("c1")
+    f = pr.rhs()
+    say("fp64 in place")
+    p1, _ = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+    p2, _ = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, inplace=True)
+    assert np.array_equal(p1, p2)
+
+
+@pytest.mark.parametrize("zp", PAIRS)
+@pytest.mark.parametrize("xp", PAIRS)
+def test_refine_bc(xp, zp):
+    """FP32 transforms + FP64 refinement, the boundary pairs in x and z (y
+    runs through the same kernels as x)."""
+    for yp in ((P, P), (D, N)):
+        bc = xp + yp + zp
+        nx, ny, nz = 32, 24, 16
+        dzf = np.full(nz, 1 / nz) if zp == (P, P) else inputs.tanh_dzf(nz, 1.5, 2.0)
+        rng = np.random.default_rng(sum(bc) + 11)
+        f = rng.standard_normal((nz, ny, nx))
+        say("refine bc", bc)
+        po, mo = O.solve(f, bc, 1 / nx, 1 / ny, dzf)
+        pg, info = gpu_solve(f, bc, 1 / nx, 1 / ny, dzf, precision="fp32_refine", tol=1e-10, max_iter=6)
+        assert info["converged"] and info["residual"] <= 1e-10, info
+        assert O.residual(pg, f, bc, 1 / nx, 1 / ny, dzf) <= 1.5e-10
+        assert rel(demean(pg, bc, dzf), po) < TOL_REF
+        assert abs(info["removed_mean"] - mo) < 1e-13 * max(1, abs(mo))
+
+
+def test_refine_alias_rejected():
+    pr = inputs.config("c1")
+    plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine")
+    a = torch.zeros(pr.nz, pr.ny, pr.nx, dtype=torch.float64, device="cuda")
+    with pytest.raises(capi.CansError) as e:
+        plan.solve(a, a)
+    assert e.value.code == -5
+    plan.close()
+
+
+def test_refine_not_converged_reported():
+    """max_iter = 0 and an unreachable tolerance: reported, not raised."""
+    pr = inputs.config("c1")
+    f = pr.rhs()
+    say("refine not converged")
+    pg, info = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine", tol=1e-30, max_iter=0)
+    assert not info["converged"] and info["iterations"] == 0
+    assert 1e-9 < info["residual"] < 1e-5
+    pg, info = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine", tol=1e-30, max_iter=2)
+    assert not info["converged"] and info["iterations"] == 2 and len(info["history"]) == 3
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_refine_config_full(name):
+    pr = inputs.config(name)
+    f = pr.rhs()
+    say("refine config", name)
+    po, _ = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+    pg, info = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine")
+    say("  info", info)
+    assert info["converged"] and info["residual"] <= 1e-10
+    assert O.residual(pg, f, pr.bc, pr.dx, pr.dy, pr.dzf) <= 1.5e-10
+    assert rel(demean(pg, pr.bc, pr.dzf), po) < TOL_REF
+    # the refinement keeps the zero mode pinned in FP64
+    assert abs(O.weighted_mean(pg, pr.dzf)) < 1e-13 * np.abs(po).max()

@@ -1,0 +1,102 @@
+"""Host-only checks of the HIP library (no GPU, no compute calls): it loads,
+exports every function the public header declares, and rejects invalid or
+unsupported problems before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2001_05234_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*(cans_[a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_header_symbol():
+    lib = capi.load()
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(capi.EXPORTS) == names
+
+
+def test_status_strings():
+    lib = capi.load()
+    for code, text in capi.STATUS.items():
+        assert lib.cans_status_string(code).decode() == text
+
+
+def _plan(nx, ny, nz, bc, dx=1.0, dy=1.0, dz=None, opts=None):
+    lib = capi.load()
+    h = ctypes.c_void_p()
+    dz = np.full(max(nz, 1), 0.5) if dz is None else np.asarray(dz, dtype=np.float64)
+    rc = lib.cans_poisson_plan_ex(ctypes.byref(h), nx, ny, nz, (ctypes.c_int * 6)(*bc), dx, dy,
+                                  dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(opts) if opts is not None else None)
+    return rc
+
+
+@pytest.mark.parametrize("args,code", [
+    ((8, 8, 8, (0, 1, 0, 0, 1, 1)), -1),      # periodic paired with Neumann
+    ((8, 8, 8, (0, 0, 0, 0, 3, 1)), -1),      # unknown boundary code
+    ((0, 8, 8, (0, 0, 0, 0, 1, 1)), -1),      # empty axis
+    ((8, 8, 0, (0, 0, 0, 0, 1, 1)), -1),
+    ((7, 8, 8, (0, 0, 0, 0, 1, 1)), -2),      # odd length
+    ((8, 14, 8, (0, 0, 0, 0, 1, 1)), -2),     # 7 is not a supported radix
+    ((8, 8, 2, (0, 0, 0, 0, 0, 0)), -2),      # periodic z shorter than 3
+    ((8192, 8, 4, (0, 0, 0, 0, 1, 1)), -2),   # longer than one LDS tile
+])
+def test_plan_validation(args, code):
+    assert _plan(*args) == code
+
+
+def test_plan_validation_spacing():
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), dx=0.0) == -1
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), dy=-1.0) == -1
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), dz=[0.1, 0.2, -0.1, 0.3]) == -1
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), dz=[0.1, 0.2, np.nan, 0.3]) == -1
+    # periodic z must be uniform
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 0, 0), dz=[0.1, 0.2, 0.1, 0.3]) == -2
+
+
+def test_options_validation():
+    o = capi.default_opts()
+    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4
+    o.max_iter = 99
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.precision = 7
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.tol = -1.0
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+
+
+def test_null_arguments():
+    lib = capi.load()
+    assert lib.cans_poisson_solve(None, None, None, None) == -1
+    assert lib.cans_poisson_get_info(None, None) == -1
+    assert lib.cans_poisson_debug_stage(None, 1, None, None, None) == -1
+    assert lib.cans_poisson_workspace_bytes(None) == 0
+    lib.cans_poisson_destroy(None)
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The library and its binding never import, include or load the oracle."""
+    pkg = os.path.join(ROOT, "paper_2001_05234_amd")
+    pat = re.compile(r"(^\s*(import|from)\s+oracle)|(#include\s+.*oracle)|(liboracle)", re.M)
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not pat.search(text), fn
