@@ -124,9 +124,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--kernel-reps", type=int, default=10)
-    ap.add_argument("--cpu-sample-levels", type=int, default=48)
+    ap.add_argument("--cpu-sample-levels", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solve-only", action="store_true", help="time the refine solve only (profiling runs)")
+    ap.add_argument("--fp64-only", action="store_true", help="time the FP64 solve only (profiling runs)")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="1 GiB device-to-device copies only (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path in this build "
@@ -139,6 +142,9 @@ def main():
     from paper_2001_05234_amd import capi, inputs
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.copy_only:
+        print(json.dumps({"copy_GBps": copy_gbs(torch, 1 << 30), "bytes_per_copy": 2 * (1 << 30)}), flush=True)
+        return
     capi.load()
     pr = inputs.config(args.config)
     say(f"[bench] generating {args.config} rhs {pr.nx}x{pr.ny}x{pr.nz}")
@@ -147,6 +153,11 @@ def main():
     pd = torch.zeros_like(fd)
     npts = pr.npts
 
+    if args.fp64_only:
+        plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64")
+        ms64, _ = time_solves(plan64, fd, pd, args.steps, args.warmup, torch)
+        print(json.dumps({"fp64_ms_per_step": ms64, "value": npts / (ms64 * 1e-3)}), flush=True)
+        return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
                      tol=1e-10, max_iter=4)
