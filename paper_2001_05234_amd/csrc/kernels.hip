@@ -275,6 +275,79 @@ __global__ __launch_bounds__(256) void k_zsolve(T *data, ZArgs a, const int *__r
     zsolve_column(col, data, a);
 }
 
+static ZArgs zargs(const Problem &pb, double *removed);
+
+// Partitioned column solve: 64 columns per block (lane = column), one z
+// segment per wave, everything in registers and LDS (see zsolve_core.h).
+template <typename T, int MMAX>
+__global__ __launch_bounds__(1024) void k_zsolve_part(T *data, ZArgs a, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    __shared__ double coef[6][16][64];
+    __shared__ double red[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, S = blockDim.x >> 6;
+    const size_t col = (size_t)blockIdx.x * 64 + lane;
+    const ZSeg sg = zseg(a.nz, S, w);
+    ZLane<MMAX> L;
+    zp_load(L, data, a, col, sg);
+    const bool sblock = a.singular && blockIdx.x == 0;
+    if (sblock) {  // project the singular column on the range of its operator
+        const double s = L.sing ? zp_wsum(L, a, sg) : 0.0;
+        if (lane == 0) red[w] = s;
+        __syncthreads();
+        double tot = 0;
+        for (int q = 0; q < S; ++q) tot += red[q];
+        const double m = tot / a.wsum;
+        if (L.sing) zp_shift(L, sg, m);
+        if (L.sing && w == 0 && a.removed) *a.removed = m;
+        __syncthreads();
+    }
+    double out[6];
+    zp_reduce(L, a, sg, out);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) coef[q][w][lane] = out[q];
+    __syncthreads();
+    if (w == 0) {
+        zp_interface(
+            S, [&](int s, int q) -> double & { return coef[q][s][lane]; },
+            [&](int s) -> double & { return coef[4][s][lane]; },
+            [&](int s) -> double & { return coef[5][s][lane]; });
+    }
+    __syncthreads();
+    const double xL = w > 0 ? coef[5][w - 1][lane] : 0.0;
+    const double xR = w < S - 1 ? coef[4][w + 1][lane] : 0.0;
+    zp_finish(L, a, sg, xL, xR);
+    if (sblock) {  // zero weighted mean of the singular column
+        const double s = L.sing ? zp_wsum(L, a, sg) : 0.0;
+        if (lane == 0) red[w] = s;
+        __syncthreads();
+        double tot = 0;
+        for (int q = 0; q < S; ++q) tot += red[q];
+        if (L.sing) zp_shift(L, sg, tot / a.wsum);
+    }
+    zp_store(L, data, a, col, sg);
+}
+
+template <typename T>
+static int launch_zsolve(const Problem &pb, T *data, double *removed, const int *done, hipStream_t s)
+{
+    const size_t plane = (size_t)pb.nx * pb.ny;
+    const int mm = pb.cyclic ? 0 : zpart_mmax(pb.nz);
+    ZArgs za = zargs(pb, removed);
+    if (mm == 0) {
+        hipLaunchKernelGGL(k_zsolve<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data, za, done);
+        return check_launch();
+    }
+    const int S = (pb.nz + mm - 1) / mm;
+    const dim3 grid((unsigned)((plane + 63) / 64)), block(64 * S);
+    switch (mm) {
+    case 8: hipLaunchKernelGGL((k_zsolve_part<T, 8>), grid, block, 0, s, data, za, done); break;
+    case 16: hipLaunchKernelGGL((k_zsolve_part<T, 16>), grid, block, 0, s, data, za, done); break;
+    default: hipLaunchKernelGGL((k_zsolve_part<T, 24>), grid, block, 0, s, data, za, done); break;
+    }
+    return check_launch();
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 static size_t tile_lds(const XGeom &g, size_t elem) { return 2 * (size_t)g.n * g.L * elem; }
@@ -361,18 +434,12 @@ static ZArgs zargs(const Problem &pb, double *removed)
 
 int launch_zsolve_f64(const Problem &pb, double *data, double *removed, hipStream_t s)
 {
-    const size_t plane = (size_t)pb.nx * pb.ny;
-    hipLaunchKernelGGL(k_zsolve<double>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data,
-                       zargs(pb, removed), nullptr);
-    return check_launch();
+    return launch_zsolve<double>(pb, data, removed, nullptr, s);
 }
 
 int launch_zsolve_32(const Problem &pb, float *data, double *removed, const int *done, hipStream_t s)
 {
-    const size_t plane = (size_t)pb.nx * pb.ny;
-    hipLaunchKernelGGL(k_zsolve<float>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data,
-                       zargs(pb, removed), done);
-    return check_launch();
+    return launch_zsolve<float>(pb, data, removed, done, s);
 }
 
 static LapArgs lapargs(const Problem &pb)

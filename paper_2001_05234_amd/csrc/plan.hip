@@ -112,11 +112,14 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     CANS_TRY(upload(pl, &pb.d_zaf, af.data(), nz));
     CANS_TRY(upload(pl, &pb.d_zcf, cf.data(), nz));
     CANS_TRY(upload(pl, &pb.d_dzf, pb.dzf.data(), nz));
-    // workspace: elimination multipliers and modified rhs (FP64 fields)
+    // workspace of the plain elimination (periodic z, or nz beyond the
+    // register-resident partitioned solve): multipliers and modified rhs
     const size_t N = pb.npts();
-    CANS_TRY(alloc(pl, &pb.wc, N));
-    CANS_TRY(alloc(pl, &pb.wd, N));
-    if (pb.cyclic) CANS_TRY(alloc(pl, &pb.wz, N));
+    if (pb.cyclic || zpart_mmax(nz) == 0) {
+        CANS_TRY(alloc(pl, &pb.wc, N));
+        CANS_TRY(alloc(pl, &pb.wd, N));
+        if (pb.cyclic) CANS_TRY(alloc(pl, &pb.wz, N));
+    }
     if (pl->opts.precision == CANS_PREC_FP32_REFINE) {
         CANS_TRY(alloc(pl, &pb.a32, N));
         pb.nres_blocks = resid_blocks(pb);

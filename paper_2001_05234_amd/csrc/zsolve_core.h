@@ -174,3 +174,211 @@ CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
 }
 
 }  // namespace cans
+
+namespace cans {
+
+// ---------------------------------------------------------------------------
+// Partitioned column solve (no workspace).  A block owns 64 adjacent columns
+// (lane = column) and splits z into S segments (wave = segment), each of
+// m <= MMAX levels held in registers.  Within a segment, with the outside
+// neighbours xL = x_{k0-1} and xR = x_{k1}:
+//   top-down elimination   ->  x_{k1-1} + C xL + E xR = F
+//   bottom-up elimination  ->  x_{k0}   + A xL + B xR = D
+// The 2S end unknowns (u_s = x_{k0}, v_s = x_{k1-1}) satisfy
+//   u_s + A_s v_{s-1} + B_s u_{s+1} = D_s,   v_s + C_s v_{s-1} + E_s u_{s+1} = F_s,
+// a block-tridiagonal system with 2x2 blocks whose coupling matrices have one
+// non-zero column each; it is eliminated in one pass over the segments and
+// back-substituted.  Each segment then re-runs its top-down sweep with xL
+// known (reusing the stored reciprocal pivots) and back-substitutes from xR.
+// Gauss elimination without pivoting throughout (diagonally dominant), FP64.
+
+// 1/x as v_rcp_f64 refined by two Newton steps on the device.
+CANS_HD double rcp64(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+struct ZSeg {
+    int k0, m;
+};
+
+CANS_HD ZSeg zseg(int nz, int S, int w)
+{
+    const int base = nz / S, rem = nz % S;
+    ZSeg s;
+    s.k0 = w * base + (w < rem ? w : rem);
+    s.m = base + (w < rem ? 1 : 0);
+    return s;
+}
+
+// row coefficients of level k for a lane; the singular lane pins its last
+// row to x = 0
+CANS_HD void zrow(const ZArgs &a, int k, double lam, bool sing, double &ak, double &bk, double &ck)
+{
+    ak = a.za[k];
+    bk = a.zb[k] + lam;
+    ck = a.zc[k];
+    if (sing && k == a.nz - 1) { ak = 0.0; bk = 1.0; ck = 0.0; }
+}
+
+template <int MMAX>
+struct ZLane {
+    double f[MMAX];   // rhs, later the forward-swept rhs, later x
+    double r[MMAX];   // reciprocal pivots of the top-down sweep
+    double lam;
+    bool sing, valid;
+};
+
+// load the segment's rhs (scaled) and the column's lambda
+template <int MMAX, typename T>
+CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, ZSeg sg)
+{
+    const size_t plane = (size_t)a.nx * a.ny;
+    L.valid = col < plane;
+    L.sing = a.singular && col == 0;
+    L.lam = L.valid ? a.lamx[col % a.nx] + a.lamy[col / a.nx] : -1.0;
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t)
+        if (t < sg.m) L.f[t] = L.valid ? a.scale * (double)data[col + plane * (sg.k0 + t)] : 0.0;
+}
+
+// weighted partial sum of this segment (singular lane only)
+template <int MMAX>
+CANS_HD double zp_wsum(const ZLane<MMAX> &L, const ZArgs &a, ZSeg sg)
+{
+    double s = 0;
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t)
+        if (t < sg.m) s += a.dzf[sg.k0 + t] * L.f[t];
+    return s;
+}
+
+template <int MMAX>
+CANS_HD void zp_shift(ZLane<MMAX> &L, ZSeg sg, double m)
+{
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t)
+        if (t < sg.m) L.f[t] -= m;
+}
+
+// step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F
+template <int MMAX>
+CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
+{
+    // the pinned row of the singular lane carries rhs 0
+    if (L.sing && sg.k0 + sg.m == a.nz) L.f[sg.m - 1] = 0.0;
+    double cp = 0, d = 0, g = 0;
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t) {
+        if (t < sg.m) {
+            double ak, bk, ck;
+            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            const double rr = rcp64(t == 0 ? bk : bk - ak * cp);
+            L.r[t] = rr;
+            d = (t == 0 ? L.f[t] : L.f[t] - ak * d) * rr;
+            g = (t == 0 ? ak : -ak * g) * rr;
+            cp = ck * rr;
+        }
+    }
+    out[2] = g;   // C
+    out[4] = cp;  // E
+    out[5] = d;   // F
+    double ep = 0, dd = 0, h = 0;
+#pragma unroll
+    for (int t = MMAX - 1; t >= 0; --t) {
+        if (t < sg.m) {
+            double ak, bk, ck;
+            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            const bool last = (t == sg.m - 1);
+            const double rr = rcp64(last ? bk : bk - ck * ep);
+            dd = (last ? L.f[t] : L.f[t] - ck * dd) * rr;
+            h = (last ? ck : -ck * h) * rr;
+            ep = ak * rr;
+        }
+    }
+    out[0] = ep;  // A
+    out[1] = h;   // B
+    out[3] = dd;  // D
+}
+
+// step 2: the reduced system of one column over its S segments.
+// c(s, q) addresses coefficient q of segment s; u(s), v(s) receive the ends.
+template <typename Coef, typename OutU, typename OutV>
+CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo)
+{
+    double g2p = 0, y2p = 0;
+    for (int s = 0; s < S; ++s) {
+        const double A = c(s, 0), B = c(s, 1), C = c(s, 2), D = c(s, 3), E = c(s, 4), F = c(s, 5);
+        const double inv = rcp64(1.0 - A * g2p);
+        const double y1 = (D - A * y2p) * inv;
+        const double y2 = (F - C * y2p) + C * g2p * y1;
+        const double g1 = B * inv;
+        const double g2 = E + C * g2p * g1;
+        c(s, 0) = y1; c(s, 1) = y2; c(s, 2) = g1; c(s, 3) = g2;
+        g2p = g2;
+        y2p = y2;
+    }
+    double un = 0;
+    for (int s = S - 1; s >= 0; --s) {
+        const double u = c(s, 0) - c(s, 2) * un;
+        const double v = c(s, 1) - c(s, 3) * un;
+        uo(s) = u;
+        vo(s) = v;
+        un = u;
+    }
+}
+
+// step 3: x of the segment from its outside neighbours xL, xR
+template <int MMAX>
+CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, double xR)
+{
+    double d = xL;
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t) {
+        if (t < sg.m) {
+            double ak, bk, ck;
+            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            d = (L.f[t] - ak * d) * L.r[t];
+            L.f[t] = d;
+        }
+    }
+    double x = xR;
+#pragma unroll
+    for (int t = MMAX - 1; t >= 0; --t) {
+        if (t < sg.m) {
+            double ak, bk, ck;
+            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            x = L.f[t] - ck * L.r[t] * x;
+            L.f[t] = x;
+        }
+    }
+}
+
+template <int MMAX, typename T>
+CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col, ZSeg sg)
+{
+    if (!L.valid) return;
+    const size_t plane = (size_t)a.nx * a.ny;
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t)
+        if (t < sg.m) data[col + plane * (sg.k0 + t)] = (T)L.f[t];
+}
+
+// register depth for nz with at most 16 segments (0 when nz > 384: the
+// plain elimination with a workspace is used then, and for periodic z)
+inline int zpart_mmax(int nz)
+{
+    for (int mm : {8, 16, 24})
+        if ((nz + mm - 1) / mm <= 16) return mm;
+    return 0;
+}
+
+}  // namespace cans

@@ -38,6 +38,7 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.emu_xform.argtypes = [i, i, i, i, i, i, i, dp, dp]
         L.emu_zsolve.argtypes = [i, i, i, ip, d, d, dp, dp, dp]
+        L.emu_zsolve_part.argtypes = [i, i, i, ip, d, d, dp, dp, dp]
         L.emu_solve.argtypes = [i, i, i, ip, d, d, dp, i, d, dp, dp, dp]
         _lib = L
     return _lib
@@ -62,6 +63,19 @@ def zsolve(fhat, bc, dx, dy, dzf):
     dzf = np.ascontiguousarray(dzf, dtype=np.float64)
     rem = ctypes.c_double(0)
     rc = lib().emu_zsolve(nx, ny, nz, (ctypes.c_int * 6)(*bc), dx, dy, _p(dzf), _p(d), ctypes.pointer(rem))
+    assert rc == 0
+    return d, rem.value
+
+
+def zsolve_part(fhat, bc, dx, dy, dzf):
+    """The partitioned (register-resident) z kernel; None where it does not apply."""
+    d = np.array(fhat, dtype=np.float64, copy=True)
+    nz, ny, nx = d.shape
+    dzf = np.ascontiguousarray(dzf, dtype=np.float64)
+    rem = ctypes.c_double(0)
+    rc = lib().emu_zsolve_part(nx, ny, nz, (ctypes.c_int * 6)(*bc), dx, dy, _p(dzf), _p(d), ctypes.pointer(rem))
+    if rc == -2:
+        return None
     assert rc == 0
     return d, rem.value
 

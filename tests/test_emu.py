@@ -74,6 +74,31 @@ def test_zsolve_stage():
         assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
 
 
+@pytest.mark.parametrize("nz", [1, 2, 5, 8, 9, 17, 31, 64, 96, 100, 256, 384])
+def test_zsolve_partitioned(nz):
+    """Register-resident partitioned z solve (segments per wave, reduced
+    interface system) against the oracle's column solves, including the
+    singular column and ragged column blocks."""
+    rng = np.random.default_rng(nz)
+    for bc in [(P, P, N, N, N, N), (D, N, P, P, D, D), (N, N, N, N, N, D), (P, P, P, P, D, N)]:
+        ny, nx = 6, 22
+        dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+        fh = rng.standard_normal((nz, ny, nx))
+        ph, rem = O.spectral_solve(fh, bc, 0.3, 0.5, dzf)
+        kx, ky = O.axis_kind(bc[0], bc[1]), O.axis_kind(bc[2], bc[3])
+        res = emu.zsolve_part(fh, bc, 0.3, 0.5, dzf)
+        assert res is not None
+        pe, reme = res
+        s = scale(kx, nx) * scale(ky, ny)
+        e = rel(pe * s, ph)
+        if e >= 1e-12:  # conditioning: judge both FP64 results against long double
+            phl, _ = O.spectral_solve(fh, bc, 0.3, 0.5, dzf, ld=True)
+            assert rel(pe * s, phl) < 2 * rel(ph, phl), (nz, bc, e)
+        assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
+    # periodic z and nz > 384 use the plain elimination
+    assert emu.zsolve_part(fh, (P, P, N, N, P, P), 0.3, 0.5, np.full(nz, 0.1)) is None
+
+
 def test_c1_refine_converges():
     pr = inputs.config("c1")
     f = pr.rhs()
