@@ -49,10 +49,25 @@ __device__ void block_sum3(double &a, double &b, double &c)
 }
 
 // ---------------------------------------------------------------------------
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// runs a contiguous range of tiles (neighbouring y tiles share cache lines).
+__device__ inline unsigned xcd_remap(unsigned b, unsigned nblk)
+{
+    const unsigned q = nblk / 8, r = nblk % 8, x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// z level of line `line` (rows j + ny*k) inside a tile starting at line0
+__device__ inline int line_level(long line, long line0, int k0, int j0, int ny)
+{
+    const long d = line - line0;
+    return (j0 + d < ny) ? k0 : (int)(line / ny);
+}
+
 // x transform: a block holds L consecutive x lines (rows j + ny*k).
 // EPI 0: out = v;  EPI 1: out = out + v - info[I_MEANP] (refinement update).
-// `wsum_part` (optional): block partial sums of dzf_k * in, in FP64, so the
-// exact weighted mean of the rhs is known in refinement mode.
+// `wsum_part` (optional, forward only): block partial sums of dzf_k * in in
+// FP64, so the exact weighted mean of the rhs is known in refinement mode.
 template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
 __global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
                                                       const cx<T> *__restrict__ tw,
@@ -63,70 +78,61 @@ __global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, 
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *b0 = reinterpret_cast<T *>(smem);
-    T *b1 = b0 + g.n * g.L;
-    const int tid = threadIdx.x, n = g.n;
+    const Tile<AX_X, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
+    const int n = g.n;
     const long line0 = (long)blockIdx.x * g.L;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     double acc = 0;
-    for (int e = tid; e < n * g.L; e += kThreads) {
-        const int l = e / n, i = e - l * n;
+    auto src = [&](int e, int l) -> T {
         const long line = line0 + l;
-        T v = T(0);
+        if (line >= nlines) return T(0);
+        const Tin x = in[line * n + e];
+        if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
+        return (T)x;
+    };
+    const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
+    auto put = [&](int q, int l, T v) {
+        const long line = line0 + l;
         if (line < nlines) {
-            const Tin x = in[line * n + i];
-            if (wsum_part) acc += dzf[line / ny] * (double)x;
-            v = (T)x;
+            const size_t idx = (size_t)line * n + q;
+            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
+            else out[idx] = (Tout)v;
         }
-        R(b1, g, i, l) = v;
-    }
+    };
+    tile_transform<KIND, FWD, AX_X, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
     if (wsum_part) {
         double z1 = 0, z2 = 0;
         block_sum3(acc, z1, z2);
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             wsum_part[3 * blockIdx.x] = acc;
             wsum_part[3 * blockIdx.x + 1] = 0;
             wsum_part[3 * blockIdx.x + 2] = 0;
         }
     }
-    __syncthreads();
-    T *res = tile_transform<KIND, FWD>(tid, kThreads, g, b0, b1, tw, BlockSync());
-    const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
-    for (int e = tid; e < n * g.L; e += kThreads) {
-        const int l = e / n, i = e - l * n;
-        const long line = line0 + l;
-        if (line < nlines) {
-            const size_t idx = (size_t)line * n + i;
-            const T v = R(res, g, i, l);
-            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
-            else out[idx] = (Tout)v;
-        }
-    }
 }
 
-// y transform: block (bx, k) holds columns i0 .. i0+L-1 of plane k, all ny
+// y transform: tile (t, k) holds columns i0 .. i0+L-1 of plane k, all ny
 // rows; each global row segment of L elements is contiguous.
 template <int KIND, bool FWD, typename T, typename Tio>
-__global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, int nx, int ny, XGeom g,
+__global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, int nx, int ny, int ntx, XGeom g,
                                                       const cx<T> *__restrict__ tw,
                                                       const int *__restrict__ done)
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *b0 = reinterpret_cast<T *>(smem);
-    T *b1 = b0 + g.n * g.L;
-    const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * g.L;
-    const size_t base = (size_t)blockIdx.y * nx * ny;
-    for (int e = tid; e < ny * g.L; e += kThreads) {
-        const int l = e & (g.L - 1), j = e >> g.lgL, i = i0 + l;
-        R(b1, g, j, l) = i < nx ? (T)in[base + (size_t)j * nx + i] : T(0);
-    }
-    __syncthreads();
-    T *res = tile_transform<KIND, FWD>(tid, kThreads, g, b0, b1, tw, BlockSync());
-    for (int e = tid; e < ny * g.L; e += kThreads) {
-        const int l = e & (g.L - 1), j = e >> g.lgL, i = i0 + l;
-        if (i < nx) out[base + (size_t)j * nx + i] = (Tio)R(res, g, j, l);
-    }
+    const Tile<AX_Y, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = (int)(t % ntx) * g.L;
+    const size_t base = (size_t)(t / ntx) * nx * ny;
+    auto src = [&](int e, int l) -> T {
+        const int i = i0 + l;
+        return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+    };
+    auto put = [&](int q, int l, T v) {
+        const int i = i0 + l;
+        if (i < nx) out[base + (size_t)q * nx + i] = (Tio)v;
+    };
+    tile_transform<KIND, FWD, AX_Y, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
 }
 
 // Residual of the current p fused with the forward x transform of it:
@@ -144,39 +150,35 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
 {
     if (*done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    float *b0 = reinterpret_cast<float *>(smem);
-    float *b1 = b0 + g.n * g.L;
-    const int tid = threadIdx.x, n = g.n;
+    const Tile<AX_X, float> tile{reinterpret_cast<cx<float> *>(smem), g.L, g.RS, g.psh};
+    const int n = g.n, ny = la.ny;
     const long line0 = (long)blockIdx.x * g.L;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mf = info[I_REMOVED];
     double srr = 0, sff = 0, spw = 0;
-    for (int e = tid; e < n * g.L; e += kThreads) {
-        const int l = e / n, i = e - l * n;
+    auto src = [&](int e, int l) -> float {
         const long line = line0 + l;
-        float v = 0.f;
-        if (line < nlines) {
-            const int j = (int)(line % la.ny), k = (int)(line / la.ny);
-            const size_t idx = (size_t)line * n + i;
-            const double fv = f[idx] - mf;
-            const double r = fv - lap_point(p, i, j, k, la);
-            srr += r * r;
-            sff += fv * fv;
-            spw += dzf[k] * p[idx];
-            v = (float)r;
-        }
-        R(b1, g, i, l) = v;
-    }
+        if (line >= nlines) return 0.f;
+        const int k = line_level(line, line0, k0, j0, ny);
+        const int j = (int)(line - (long)k * ny);
+        const size_t idx = (size_t)line * n + e;
+        const double fv = f[idx] - mf;
+        const double r = fv - lap_point(p, e, j, k, la);
+        srr += r * r;
+        sff += fv * fv;
+        spw += dzf[k] * p[idx];
+        return (float)r;
+    };
+    auto put = [&](int q, int l, float v) {
+        const long line = line0 + l;
+        if (line < nlines) out[(size_t)line * n + q] = v;
+    };
+    tile_transform<KIND, true, AX_X, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
     block_sum3(srr, sff, spw);
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         partials[3 * blockIdx.x + 0] = srr;
         partials[3 * blockIdx.x + 1] = sff;
         partials[3 * blockIdx.x + 2] = spw;
-    }
-    float *res = tile_transform<KIND, true>(tid, kThreads, g, b0, b1, tw, BlockSync());
-    for (int e = tid; e < n * g.L; e += kThreads) {
-        const int l = e / n, i = e - l * n;
-        const long line = line0 + l;
-        if (line < nlines) out[(size_t)line * n + i] = R(res, g, i, l);
     }
 }
 
@@ -350,32 +352,33 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
 
 // ---------------------------------------------------------------------------
 // launchers
-static size_t tile_lds(const XGeom &g, size_t elem) { return 2 * (size_t)g.n * g.L * elem; }
+static size_t tile_lds(int axis, const XGeom &g, size_t elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
 
 int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s)
 {
     const XGeom &g = pb.ax.gx64;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
-    const size_t sh = tile_lds(g, sizeof(double));
+    const size_t sh = tile_lds(AX_X, g, sizeof(double));
     CANS_KIND_SWITCH(pb.ax.kind,
         if (fwd) hipLaunchKernelGGL((k_xform_x<KD, true, double, double, double, 0>), grid, dim3(kThreads), sh, s,
-                                    in, out, nlines, g, pb.ax.d_tw64, nullptr, nullptr, nullptr, 1, nullptr);
+                                    in, out, nlines, g, pb.ax.d_tw64, nullptr, nullptr, nullptr, pb.ny, nullptr);
         else hipLaunchKernelGGL((k_xform_x<KD, false, double, double, double, 0>), grid, dim3(kThreads), sh, s,
-                                in, out, nlines, g, pb.ax.d_tw64, nullptr, nullptr, nullptr, 1, nullptr));
+                                in, out, nlines, g, pb.ax.d_tw64, nullptr, nullptr, nullptr, pb.ny, nullptr));
     return check_launch();
 }
 
 int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s)
 {
     const XGeom &g = pb.ay.gy64;
-    const dim3 grid((unsigned)((pb.nx + g.L - 1) / g.L), (unsigned)pb.nz);
-    const size_t sh = tile_lds(g, sizeof(double));
+    const int ntx = (pb.nx + g.L - 1) / g.L;
+    const dim3 grid((unsigned)(ntx * pb.nz));
+    const size_t sh = tile_lds(AX_Y, g, sizeof(double));
     CANS_KIND_SWITCH(pb.ay.kind,
         if (fwd) hipLaunchKernelGGL((k_xform_y<KD, true, double, double>), grid, dim3(kThreads), sh, s,
-                                    in, out, pb.nx, pb.ny, g, pb.ay.d_tw64, nullptr);
+                                    in, out, pb.nx, pb.ny, ntx, g, pb.ay.d_tw64, nullptr);
         else hipLaunchKernelGGL((k_xform_y<KD, false, double, double>), grid, dim3(kThreads), sh, s,
-                                in, out, pb.nx, pb.ny, g, pb.ay.d_tw64, nullptr));
+                                in, out, pb.nx, pb.ny, ntx, g, pb.ay.d_tw64, nullptr));
     return check_launch();
 }
 
@@ -384,7 +387,7 @@ int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *
     const XGeom &g = pb.ax.gx32;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
-    const size_t sh = tile_lds(g, sizeof(float));
+    const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         hipLaunchKernelGGL((k_xform_x<KD, true, float, double, float, 0>), grid, dim3(kThreads), sh, s,
                            in, out, nlines, g, pb.ax.d_tw32, nullptr, done, pb.d_dzf, pb.ny, pb.partials));
@@ -394,13 +397,14 @@ int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *
 int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipStream_t s)
 {
     const XGeom &g = pb.ay.gy32;
-    const dim3 grid((unsigned)((pb.nx + g.L - 1) / g.L), (unsigned)pb.nz);
-    const size_t sh = tile_lds(g, sizeof(float));
+    const int ntx = (pb.nx + g.L - 1) / g.L;
+    const dim3 grid((unsigned)(ntx * pb.nz));
+    const size_t sh = tile_lds(AX_Y, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ay.kind,
         if (fwd) hipLaunchKernelGGL((k_xform_y<KD, true, float, float>), grid, dim3(kThreads), sh, s,
-                                    data, data, pb.nx, pb.ny, g, pb.ay.d_tw32, done);
+                                    data, data, pb.nx, pb.ny, ntx, g, pb.ay.d_tw32, done);
         else hipLaunchKernelGGL((k_xform_y<KD, false, float, float>), grid, dim3(kThreads), sh, s,
-                                data, data, pb.nx, pb.ny, g, pb.ay.d_tw32, done));
+                                data, data, pb.nx, pb.ny, ntx, g, pb.ay.d_tw32, done));
     return check_launch();
 }
 
@@ -410,12 +414,12 @@ int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, 
     const XGeom &g = pb.ax.gx32;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
-    const size_t sh = tile_lds(g, sizeof(float));
+    const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         if (update) hipLaunchKernelGGL((k_xform_x<KD, false, float, float, double, 1>), grid, dim3(kThreads), sh, s,
-                                       in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, 1, nullptr);
+                                       in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, pb.ny, nullptr);
         else hipLaunchKernelGGL((k_xform_x<KD, false, float, float, double, 0>), grid, dim3(kThreads), sh, s,
-                                in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, 1, nullptr));
+                                in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, pb.ny, nullptr));
     return check_launch();
 }
 
@@ -465,7 +469,7 @@ int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float
     const XGeom &g = pb.ax.gx32;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)resid_blocks(pb));
-    const size_t sh = tile_lds(g, sizeof(float));
+    const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         hipLaunchKernelGGL(k_resid_xfwd<KD>, grid, dim3(kThreads), sh, s, f, p, out, nlines, g,
                            pb.ax.d_tw32, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done));

@@ -72,13 +72,9 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
     a.n = n;
     a.h = h;
     a.s = xform_scale(kind, n);
-    const int M = n / 2;
-    set_tile(a.gx64, n, tile_x(n, 8));
-    set_tile(a.gx32, n, tile_x(n, 4));
-    set_tile(a.gy64, n, tile_y(n, 8));
-    set_tile(a.gy32, n, tile_y(n, 4));
-    for (XGeom *g : {&a.gx64, &a.gx32, &a.gy64, &a.gy32})
-        if (!factor(M, *g)) return CANS_ERR_UNSUPPORTED;
+    if (!make_geom(a.gx64, AX_X, n, 8) || !make_geom(a.gx32, AX_X, n, 4) || !make_geom(a.gy64, AX_Y, n, 8) ||
+        !make_geom(a.gy32, AX_Y, n, 4))
+        return CANS_ERR_UNSUPPORTED;
     std::vector<cx<double>> t64 = twiddles(n);
     std::vector<cx<float>> t32(t64.size());
     for (size_t i = 0; i < t64.size(); ++i) t32[i] = mk((float)t64[i].re, (float)t64[i].im);

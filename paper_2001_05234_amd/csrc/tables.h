@@ -39,7 +39,13 @@ inline bool factor(int M, XGeom &g)
     if (r != 1) return false;
     g.nst = nst;
     int s = 1;
-    for (int i = 0; i < nst; ++i) { g.rad[i] = rads[i]; g.str[i] = s; s *= rads[i]; }
+    for (int i = 0; i < nst; ++i) {
+        g.rad[i] = rads[i];
+        g.str[i] = s;
+        g.mag_s[i] = mag_of((unsigned)s);
+        g.mag_nb[i] = mag_of((unsigned)(M / rads[i]));
+        s *= rads[i];
+    }
     return true;
 }
 
@@ -50,16 +56,43 @@ inline int pow2floor(long v)
     return p;
 }
 
-inline void set_tile(XGeom &g, int n, int L)
+inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Tile of L lines for an n-point transform with elements of `elem` bytes:
+// lines per tile such that a tile holds at most 4096 complex values (2048 in
+// FP64), 3840 when M has a factor 3 or 5 (the in-place stages hold at most
+// 16 complex values per thread of a 256-thread block); y tiles at most 32
+// (FP32) / 16 (FP64) columns.
+inline int tile_lines(int axis, int n, int elem)
 {
-    g.n = n;
-    g.M = n / 2;
-    g.L = L;
-    g.lgL = 0;
-    while ((1 << g.lgL) < L) ++g.lgL;
+    const int M = n / 2 > 0 ? n / 2 : 1;
+    long cap = elem == 8 ? 2048 : 4096;
+    if (!is_pow2(M)) cap = std::min<long>(cap, 3840);
+    const int lmax = axis == AX_X ? 64 : (elem == 8 ? 16 : 32);
+    return std::max(1, std::min(lmax, pow2floor(std::max<long>(1, cap / M))));
 }
 
-// modified wavenumber mu(q) of row q (unit spacing)
+inline bool make_geom(XGeom &g, int axis, int n, int elem)
+{
+    g = XGeom{};
+    g.n = n;
+    g.M = n / 2;
+    g.L = tile_lines(axis, n, elem);
+    g.lgL = 0;
+    while ((1 << g.lgL) < g.L) ++g.lgL;
+    g.psh = elem == 8 ? 4 : 5;  // 256-byte LDS rows of 16-byte / 8-byte slots
+    g.RS = g.M + ((g.M - 1) >> g.psh) + 1;
+    g.magM = mag_of((unsigned)g.M);
+    if (!factor(g.M, g)) return false;
+    // every in-place stage must fit the per-thread capacity of a 256-thread block
+    for (int st = 0; st < g.nst; ++st)
+        if ((long)(g.M / g.rad[st]) * g.L > (long)(kMaxC / g.rad[st]) * 256) return false;
+    return true;
+}
+
+// bytes of LDS a tile takes
+inline size_t tile_bytes(int axis, const XGeom &g, int elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
+
 inline long double mu_row(int kind, int n, int q)
 {
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -78,14 +111,6 @@ inline long double mu_row(int kind, int n, int q)
     return -4.0L * s * s;
 }
 
-
-// Tile shapes: x lines hold ~2048 (FP64) / 4096 (FP32) reals per tile; y
-// tiles keep their two LDS buffers within 64 KiB.
-inline int tile_x(int n, int elem) { return std::min(64, pow2floor(std::max(1, (elem == 8 ? 2048 : 4096) / n))); }
-inline int tile_y(int n, int elem)
-{
-    return std::min(elem == 8 ? 16 : 32, pow2floor(std::max<long>(1, 65536 / (2L * n * elem))));
-}
 
 // Twiddles of an n-point transform (layout in xform_core.h).
 inline std::vector<cx<double>> twiddles(int n)

@@ -2,16 +2,18 @@
 // solver") built on one complex FFT of half length, evaluated on a tile of L
 // lines held in LDS.
 //
-// Every transform is a phase sequence over two LDS buffers (b0, b1) of n*L
-// reals each, element (index e, line l) at [e*L + l]:
-//   load   global -> b1 (real line data)                 (kernel specific)
-//   pre    b1 -> b0: pack the n reals of a line into M = n/2 complex values,
-//          with the reorder / sign / twiddle the boundary pair needs
-//   stage  Stockham radix-r pass (decimation in frequency), ping-pong b0/b1
-//   post   final -> other buffer: unpack M complex values into n reals
-//   store  other buffer -> global                         (kernel specific)
-// Phases only read what earlier phases wrote, so a barrier between phases is
-// the only synchronisation; the same functions run on the host in the tests.
+// A transform of a tile is:
+//   stage 0  each butterfly reads its inputs straight from global memory
+//            through the boundary pair's packing map (n reals of a line ->
+//            M = n/2 complex values, with reorder / sign / pre-twiddle) and
+//            writes its outputs to the LDS tile;
+//   stage t  Stockham radix-r pass (decimation in frequency) in place in LDS:
+//            inputs to registers, barrier, outputs to LDS, barrier;
+//   post     each output pair reads Z_k and Z_{M-k} from LDS, applies the
+//            unpacking map and writes the reals straight to global memory.
+// Loads and stores go through functors, so the same functions run the
+// kernels (block threads, barriers) and the serial host build of the tests
+// (one thread, out of place).
 //
 // Transforms (n even, M = n/2, unnormalised, rows indexed by q):
 //   P  forward: real DFT, layout [X_0, X_M, Re X_1, Im X_1, ..., Re X_{M-1},
@@ -28,7 +30,7 @@
 
 #include <hip/hip_runtime.h>
 
-#define CANS_HD __host__ __device__ inline
+#define CANS_HD __host__ __device__ inline __attribute__((always_inline))
 
 namespace cans {
 
@@ -142,16 +144,64 @@ CANS_HD void dft_r(const int r, cx<T> *a)
 }
 
 // ---------------------------------------------------------------------------
+// Exact division of n < 2^16 by a runtime d < 2^16: q = hi32(n * mag).
+CANS_HD unsigned mag_of(unsigned d) { return d <= 1 ? 0u : (unsigned)((1ull << 32) / d + 1); }
+CANS_HD unsigned udiv(unsigned n, unsigned d, unsigned mag)
+{
+    if (d <= 1) return n;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umulhi(n, mag);
+#else
+    return (unsigned)(((unsigned long long)n * mag) >> 32);
+#endif
+}
+
 // Geometry of one transform tile.
 struct XGeom {
     int n;      // real length (even)
     int M;      // n / 2
     int L;      // lines per tile (power of two)
     int lgL;
+    int RS;     // row stride of an x tile in complex slots (with padding)
+    int psh;    // x tiles: one pad slot every 2^psh slots (256-byte LDS rows)
     int nst;    // FFT stages
+    unsigned magM;
     int rad[kMaxStages];
-    int str[kMaxStages];  // s of each stage (product of earlier radices)
+    int str[kMaxStages];       // s of each stage (product of earlier radices)
+    unsigned mag_s[kMaxStages];   // magic for / s
+    unsigned mag_nb[kMaxStages];  // magic for / (M / rad)
 };
+
+enum { AX_X = 0, AX_Y = 1 };
+
+// LDS tile of L lines of M complex values.
+//   x tiles: line-major, slot (m, l) at l*RS + m + (m >> psh);
+//   y tiles: element-major, slot (m, l) at m*(L+1) + l.
+template <int AXIS, typename T>
+struct Tile {
+    cx<T> *c;
+    int L, RS, psh;
+    CANS_HD cx<T> &at(int m, int l) const
+    {
+        return AXIS == AX_X ? c[l * RS + m + (m >> psh)] : c[m * (L + 1) + l];
+    }
+};
+
+// complex slots a tile needs
+CANS_HD int tile_slots(int axis, const XGeom &g) { return axis == AX_X ? g.L * g.RS : g.M * (g.L + 1); }
+
+// work item w of `per` items per line -> (line, item)
+template <int AXIS>
+CANS_HD void split_item(int w, int per, unsigned mag, int lgL, int L, int &l, int &it)
+{
+    if (AXIS == AX_X) {
+        l = (int)udiv((unsigned)w, (unsigned)per, mag);
+        it = w - l * per;
+    } else {
+        l = w & (L - 1);
+        it = w >> lgL;
+    }
+}
 
 // Twiddle table of one axis (complex, in the compute type), offsets in units
 // of cx<T>:
@@ -167,194 +217,243 @@ CANS_HD int tw_pre4(int M) { return 3 * M + 1; }
 CANS_HD int tw_post4(int M) { return 4 * M + 1; }
 CANS_HD int tw_size(int M) { return 5 * M + 1; }
 
-// real element e of line l in a tile buffer
-template <typename T> CANS_HD T &R(T *b, const XGeom &g, int e, int l) { return b[e * g.L + l]; }
-template <typename T> CANS_HD cx<T> &C(T *b, const XGeom &g, int m, int l)
-{
-    return reinterpret_cast<cx<T> *>(b)[m * g.L + l];
-}
-
-// Makhoul's even/odd reorder: v_j = x_{2j} (j < M), x_{2(n-1-j)+1} (j >= M);
-// returns the source index and whether it is odd.
+// Makhoul's even/odd reorder: v_j = x_{2j} (j < M), x_{2(n-1-j)+1} (j >= M).
 CANS_HD int mk_src(int j, int n, int M) { return j < M ? 2 * j : 2 * (n - 1 - j) + 1; }
 
-// ---- pre: b1 (real) -> b0 (complex) --------------------------------------
-template <int KIND, bool FWD, typename T>
-CANS_HD void phase_pre(int tid, int nt, const XGeom &g, T *b0, const T *b1c, const cx<T> *tw)
+// ---- packing map: z_m of line l from the line's reals src(e) ---------------
+template <int KIND, bool FWD, typename T, typename Src>
+CANS_HD cx<T> pack(int m, const XGeom &g, const Src &src, const cx<T> *tw)
 {
-    T *b1 = const_cast<T *>(b1c);
     const int n = g.n, M = g.M;
-    for (int w = tid; w < M * g.L; w += nt) {
-        const int m = w >> g.lgL, l = w & (g.L - 1);
-        cx<T> z;
-        if (KIND == K_ND || KIND == K_DN) {
-            T a = R(b1, g, 2 * m, l), b = R(b1, g, n - 1 - 2 * m, l);
-            z = (KIND == K_ND) ? mk(a, b) : mk(b, a);
-            z = z * tw[tw_pre4(M) + m];
-        } else if (FWD) {
-            if (KIND == K_P) {
-                z = mk(R(b1, g, 2 * m, l), R(b1, g, 2 * m + 1, l));
-            } else {
-                int s0 = mk_src(2 * m, n, M), s1 = mk_src(2 * m + 1, n, M);
-                T v0 = R(b1, g, s0, l), v1 = R(b1, g, s1, l);
-                if (KIND == K_DD) {  // (-1)^i on the input
-                    if (s0 & 1) v0 = -v0;
-                    if (s1 & 1) v1 = -v1;
-                }
-                z = mk(v0, v1);
-            }
-        } else {
-            // inverse: build the half spectrum X_k, X_{M-k} of a real line,
-            // then Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) W_n^{-k}
-            cx<T> Xk, Xc;
-            const int kc = M - m;  // in 1..M
-            if (KIND == K_P) {
-                Xk = (m == 0) ? mk(R(b1, g, 0, l), T(0)) : mk(R(b1, g, 2 * m, l), R(b1, g, 2 * m + 1, l));
-                Xc = (kc == M) ? mk(R(b1, g, 1, l), T(0)) : mk(R(b1, g, 2 * kc, l), R(b1, g, 2 * kc + 1, l));
-            } else {
-                // V_q = e^{i pi q/2n} (Y_q - i Y_{n-q}); V_0 = Y_0; V_M = sqrt2 Y_M.
-                // DD reads its input reversed: Y'_q = Y_{n-1-q}.
-                auto Y = [&](int q) -> T { return R(b1, g, KIND == K_DD ? n - 1 - q : q, l); };
-                auto V = [&](int q) -> cx<T> {
-                    if (q == 0) return mk(Y(0), T(0));
-                    if (q == M) return mk(T(1.41421356237309504880168872420969808) * Y(M), T(0));
-                    cx<T> cs = tw[tw_qw(M) + q];
-                    return cs * mk(Y(q), -Y(n - q));
-                };
-                Xk = V(m);
-                Xc = V(kc);
-            }
-            Xc = conj(Xc);
-            cx<T> E = Xk + Xc;
-            cx<T> O = (Xk - Xc) * conj(tw[tw_split(M) + m]);
-            z = E + mul_pi(O);
-        }
-        C(b0, g, m, l) = z;
+    if (KIND == K_ND || KIND == K_DN) {
+        const T a = src(2 * m), b = src(n - 1 - 2 * m);
+        return ((KIND == K_ND) ? mk(a, b) : mk(b, a)) * tw[tw_pre4(M) + m];
     }
+    if (FWD) {
+        if (KIND == K_P) return mk(src(2 * m), src(2 * m + 1));
+        const int s0 = mk_src(2 * m, n, M), s1 = mk_src(2 * m + 1, n, M);
+        T v0 = src(s0), v1 = src(s1);
+        if (KIND == K_DD) {  // (-1)^i on the input
+            if (s0 & 1) v0 = -v0;
+            if (s1 & 1) v1 = -v1;
+        }
+        return mk(v0, v1);
+    }
+    // inverse: half spectrum X_k, X_{M-k} of a real line, then
+    // Z_k = (X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) W_n^{-k}
+    cx<T> Xk, Xc;
+    const int kc = M - m;  // in 1..M
+    if (KIND == K_P) {
+        Xk = (m == 0) ? mk(src(0), T(0)) : mk(src(2 * m), src(2 * m + 1));
+        Xc = (kc == M) ? mk(src(1), T(0)) : mk(src(2 * kc), src(2 * kc + 1));
+    } else {
+        // V_q = e^{i pi q/2n} (Y_q - i Y_{n-q}); V_0 = Y_0; V_M = sqrt2 Y_M;
+        // DST-III reads its input reversed: Y'_q = Y_{n-1-q}
+        auto Y = [&](int q) -> T { return src(KIND == K_DD ? n - 1 - q : q); };
+        auto V = [&](int q) -> cx<T> {
+            if (q == 0) return mk(Y(0), T(0));
+            if (q == M) return mk(T(1.41421356237309504880168872420969808) * Y(M), T(0));
+            return tw[tw_qw(M) + q] * mk(Y(q), -Y(n - q));
+        };
+        Xk = V(m);
+        Xc = V(kc);
+    }
+    Xc = conj(Xc);
+    const cx<T> E = Xk + Xc;
+    const cx<T> O = (Xk - Xc) * conj(tw[tw_split(M) + m]);
+    return E + mul_pi(O);
 }
 
-// ---- one Stockham stage: src -> dst ---------------------------------------
+// ---- unpacking map: the reals of output pair k from Z (the FFT result) -----
+// put(q, v) receives output real q of the line.
+template <int KIND, bool FWD, typename T, typename ZAt, typename Put>
+CANS_HD void unpack(int k, const XGeom &g, const ZAt &Z, const Put &put, const cx<T> *tw)
+{
+    const int n = g.n, M = g.M;
+    const cx<T> z = Z(k);
+    if (KIND == K_ND || KIND == K_DN) {
+        const cx<T> u = z * tw[tw_post4(M) + k];
+        put(2 * k, u.re);
+        put(n - 1 - 2 * k, (KIND == K_ND) ? -u.im : u.im);
+        return;
+    }
+    if (FWD) {
+        // split the M-point FFT of the packed line into the real DFT V_k
+        cx<T> V;
+        if (k == 0) {
+            V = mk(z.re + z.im, T(0));
+        } else {
+            const cx<T> zc = conj(Z(M - k));
+            const cx<T> E = scal(z + zc, T(0.5));
+            const cx<T> O = scal(mul_ni(z - zc), T(0.5));
+            V = E + tw[tw_split(M) + k] * O;
+        }
+        if (KIND == K_P) {
+            if (k == 0) {
+                put(0, V.re);
+                put(1, z.re - z.im);
+            } else {
+                put(2 * k, V.re);
+                put(2 * k + 1, V.im);
+            }
+            return;
+        }
+        // DCT-II: X_q = c Re V_q + s Im V_q, X_{n-q} = s Re V_q - c Im V_q;
+        // DST-II stores X_q at n-1-q
+        auto out = [&](int q, T v) { put(KIND == K_DD ? n - 1 - q : q, v); };
+        if (k == 0) {
+            out(0, V.re);
+            out(M, (z.re - z.im) * tw[tw_qw(M) + M].re);
+        } else {
+            const cx<T> cs = tw[tw_qw(M) + k];
+            out(k, cs.re * V.re + cs.im * V.im);
+            out(n - k, cs.im * V.re - cs.re * V.im);
+        }
+        return;
+    }
+    if (KIND == K_P) {
+        put(2 * k, z.re);
+        put(2 * k + 1, z.im);
+        return;
+    }
+    // undo Makhoul's reorder; DST-III multiplies by (-1)^i
+    const int d0 = mk_src(2 * k, n, M), d1 = mk_src(2 * k + 1, n, M);
+    T v0 = z.re, v1 = z.im;
+    if (KIND == K_DD) {
+        if (d0 & 1) v0 = -v0;
+        if (d1 & 1) v1 = -v1;
+    }
+    put(d0, v0);
+    put(d1, v1);
+}
+
+// ---- one Stockham stage ----------------------------------------------------
 // Butterfly (q, p) of a stage with radix RAD and stride s reads
 // x[q + s (p + j m)], j < RAD, m = M/(s RAD), and writes
-// y[q + s (RAD p + u)] = DFT_RAD(x)_u * W_M^{p u s}.
+// y[q + s (RAD p + u)] = DFT_RAD(x)_u * W_M^{p u s}.  The twiddle W^{p s}
+// is read once; its powers are formed by at most three products.
 template <int RAD, bool FWD, typename T>
-CANS_HD void stage_rad(int tid, int nt, const XGeom &g, int s, T *src, T *dst, const cx<T> *tw)
+CANS_HD void twiddle_powers(cx<T> w1, cx<T> *w)
+{
+    w[1] = w1;
+    if (RAD > 2) w[2] = w1 * w1;
+    if (RAD > 3) w[3] = w[2] * w1;
+    if (RAD > 4) w[4] = w[2] * w[2];
+    if (RAD > 5) { w[5] = w[4] * w1; w[6] = w[4] * w[2]; w[7] = w[4] * w[3]; }
+}
+
+// capacity of the in-place stage: complex values a thread holds
+constexpr int kMaxC = 16;
+
+// IN(m, l) gives the stage input (LDS, or the packing map for stage 0).
+// INPLACE: the inputs of all of this thread's butterflies are read before
+// `sync` and the outputs written after it, so src and dst may be one tile.
+template <int RAD, bool FWD, int AXIS, bool INPLACE, typename T, typename In, typename Sync>
+CANS_HD void stage_rad(int tid, int nt, const XGeom &g, int st, const In &in, const Tile<AXIS, T> &dst,
+                       const cx<T> *tw, const Sync &sync)
 {
     const int M = g.M;
-    const int m = M / (s * RAD);
-    const int nb = (M / RAD) << g.lgL;
-    for (int w = tid; w < nb; w += nt) {
-        const int l = w & (g.L - 1), b = w >> g.lgL;
-        const int q = b % s, p = b / s;
-        cx<T> a[RAD];
-#pragma unroll
-        for (int j = 0; j < RAD; ++j) a[j] = C(src, g, q + s * (p + j * m), l);
-        dft_r<FWD>(RAD, a);
-        C(dst, g, q + s * (RAD * p), l) = a[0];
-#pragma unroll
-        for (int u = 1; u < RAD; ++u)
-            C(dst, g, q + s * (RAD * p + u), l) = twid<FWD>(a[u], tw[tw_fft(M) + p * u * s]);
-    }
-}
-
-template <bool FWD, typename T>
-CANS_HD void phase_stage(int tid, int nt, const XGeom &g, int st, const T *srcc, T *dst, const cx<T> *tw)
-{
-    T *src = const_cast<T *>(srcc);
     const int s = g.str[st];
-    switch (g.rad[st]) {
-    case 2: stage_rad<2, FWD>(tid, nt, g, s, src, dst, tw); break;
-    case 3: stage_rad<3, FWD>(tid, nt, g, s, src, dst, tw); break;
-    case 4: stage_rad<4, FWD>(tid, nt, g, s, src, dst, tw); break;
-    case 5: stage_rad<5, FWD>(tid, nt, g, s, src, dst, tw); break;
-    default: stage_rad<8, FWD>(tid, nt, g, s, src, dst, tw); break;
-    }
-}
-
-// ---- post: final complex buffer -> real buffer ----------------------------
-template <int KIND, bool FWD, typename T>
-CANS_HD void phase_post(int tid, int nt, const XGeom &g, const T *srcc, T *out, const cx<T> *tw)
-{
-    T *src = const_cast<T *>(srcc);
-    const int n = g.n, M = g.M;
-    for (int w = tid; w < M * g.L; w += nt) {
-        const int k = w >> g.lgL, l = w & (g.L - 1);
-        cx<T> Z = C(src, g, k, l);
-        if (KIND == K_ND || KIND == K_DN) {
-            cx<T> u = Z * tw[tw_post4(M) + k];
-            R(out, g, 2 * k, l) = u.re;
-            R(out, g, n - 1 - 2 * k, l) = (KIND == K_ND) ? -u.im : u.im;
-        } else if (FWD) {
-            // split the M-point FFT of the packed line into the real DFT V_k
-            cx<T> V;
-            if (k == 0) {
-                V = mk(Z.re + Z.im, T(0));
-            } else {
-                cx<T> Zc = conj(C(src, g, M - k, l));
-                cx<T> E = scal(Z + Zc, T(0.5));
-                cx<T> O = scal(mul_ni(Z - Zc), T(0.5));
-                V = E + tw[tw_split(M) + k] * O;
-            }
-            if (KIND == K_P) {
-                if (k == 0) {
-                    R(out, g, 0, l) = V.re;
-                    R(out, g, 1, l) = Z.re - Z.im;
-                } else {
-                    R(out, g, 2 * k, l) = V.re;
-                    R(out, g, 2 * k + 1, l) = V.im;
-                }
-            } else {
-                // DCT-II: X_q = c Re V_q + s Im V_q, X_{n-q} = s Re V_q - c Im V_q;
-                // DST-II stores X_q at n-1-q
-                auto put = [&](int q, T v) { R(out, g, KIND == K_DD ? n - 1 - q : q, l) = v; };
-                if (k == 0) {
-                    put(0, V.re);
-                    put(M, (Z.re - Z.im) * tw[tw_qw(M) + M].re);
-                } else {
-                    cx<T> cs = tw[tw_qw(M) + k];
-                    put(k, cs.re * V.re + cs.im * V.im);
-                    put(n - k, cs.im * V.re - cs.re * V.im);
-                }
-            }
-        } else {
-            if (KIND == K_P) {
-                R(out, g, 2 * k, l) = Z.re;
-                R(out, g, 2 * k + 1, l) = Z.im;
-            } else {
-                // undo Makhoul's reorder; DST-III multiplies by (-1)^i
-                int d0 = mk_src(2 * k, n, M), d1 = mk_src(2 * k + 1, n, M);
-                T v0 = Z.re, v1 = Z.im;
-                if (KIND == K_DD) {
-                    if (d0 & 1) v0 = -v0;
-                    if (d1 & 1) v1 = -v1;
-                }
-                R(out, g, d0, l) = v0;
-                R(out, g, d1, l) = v1;
+    const int m = M / (s * RAD);
+    const int per = M / RAD;
+    const int nb = per * g.L;
+    auto butterfly_io = [&](int w, int &l, int &q, int &p) {
+        int b;
+        split_item<AXIS>(w, per, g.mag_nb[st], g.lgL, g.L, l, b);
+        p = (int)udiv((unsigned)b, (unsigned)s, g.mag_s[st]);
+        q = b - p * s;
+    };
+    auto finish = [&](int l, int q, int p, cx<T> *a) {
+        dft_r<FWD>(RAD, a);
+        cx<T> wp[8];
+        twiddle_powers<RAD, FWD>(tw[tw_fft(M) + p * s], wp);
+        dst.at(q + s * (RAD * p), l) = a[0];
+#pragma unroll
+        for (int u = 1; u < RAD; ++u) dst.at(q + s * (RAD * p + u), l) = twid<FWD>(a[u], wp[u]);
+    };
+    if (INPLACE) {
+        constexpr int NB = kMaxC / RAD;
+        cx<T> a[NB][RAD];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            const int w = tid + jb * nt;
+            if (w < nb) {
+                int l, q, p;
+                butterfly_io(w, l, q, p);
+#pragma unroll
+                for (int j = 0; j < RAD; ++j) a[jb][j] = in(q + s * (p + j * m), l);
             }
         }
+        sync();
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            const int w = tid + jb * nt;
+            if (w < nb) {
+                int l, q, p;
+                butterfly_io(w, l, q, p);
+                finish(l, q, p, a[jb]);
+            }
+        }
+    } else {
+        for (int w = tid; w < nb; w += nt) {
+            int l, q, p;
+            butterfly_io(w, l, q, p);
+            cx<T> a[RAD];
+#pragma unroll
+            for (int j = 0; j < RAD; ++j) a[j] = in(q + s * (p + j * m), l);
+            finish(l, q, p, a);
+        }
+    }
+    sync();
+}
+
+template <bool FWD, int AXIS, bool INPLACE, typename T, typename In, typename Sync>
+CANS_HD void stage_any(int tid, int nt, const XGeom &g, int st, const In &in, const Tile<AXIS, T> &dst,
+                       const cx<T> *tw, const Sync &sync)
+{
+    switch (g.rad[st]) {
+    case 2: stage_rad<2, FWD, AXIS, INPLACE>(tid, nt, g, st, in, dst, tw, sync); break;
+    case 3: stage_rad<3, FWD, AXIS, INPLACE>(tid, nt, g, st, in, dst, tw, sync); break;
+    case 4: stage_rad<4, FWD, AXIS, INPLACE>(tid, nt, g, st, in, dst, tw, sync); break;
+    case 5: stage_rad<5, FWD, AXIS, INPLACE>(tid, nt, g, st, in, dst, tw, sync); break;
+    default: stage_rad<8, FWD, AXIS, INPLACE>(tid, nt, g, st, in, dst, tw, sync); break;
     }
 }
 
-// Run pre, stages and post on a tile whose real data sits in b1; the result
-// (real) ends in the returned buffer.  `sync` is the barrier between phases.
-// Run with tid = 0, nt = 1 and an empty `sync`, it is the serial reference
-// execution of the same arithmetic (used by the host-side tests).
-template <int KIND, bool FWD, typename T, typename Sync>
-CANS_HD T *tile_transform(int tid, int nt, const XGeom &g, T *b0, T *b1, const cx<T> *tw, Sync sync)
+// The whole transform of a tile.
+//   src(e, l):   real e of input line l (global memory, or a computed value)
+//   put(q, l, v): real q of output line l
+//   ta, tb:      tiles; the kernels pass one tile twice (INPLACE), the host
+//                build passes two (ping-pong).
+// The caller synchronises before reusing the tile.
+template <int KIND, bool FWD, int AXIS, bool INPLACE, typename T, typename Src, typename Put, typename Sync>
+CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, const Put &put, Tile<AXIS, T> ta,
+                            Tile<AXIS, T> tb, const cx<T> *tw, const Sync &sync)
 {
     // DCT-IV and DST-IV are their own inverses: the FFT runs forward both ways
     constexpr bool FFTF = FWD || KIND == K_ND || KIND == K_DN;
-    phase_pre<KIND, FWD>(tid, nt, g, b0, b1, tw);
-    sync();
-    T *src = b0, *dst = b1;
-    for (int st = 0; st < g.nst; ++st) {
-        phase_stage<FFTF>(tid, nt, g, st, src, dst, tw);
+    auto packed = [&](int m, int l) -> cx<T> {
+        return pack<KIND, FWD, T>(m, g, [&](int e) -> T { return src(e, l); }, tw);
+    };
+    Tile<AXIS, T> cur = ta, nxt = tb;
+    if (g.nst == 0) {  // M = 1: the packed value is the spectrum
+        for (int w = tid; w < g.L; w += nt) cur.at(0, w) = packed(0, w);
         sync();
-        T *t = src; src = dst; dst = t;
+    } else {
+        stage_any<FFTF, AXIS, false>(tid, nt, g, 0, packed, cur, tw, sync);
+        for (int st = 1; st < g.nst; ++st) {
+            auto lds = [&](int m, int l) -> cx<T> { return cur.at(m, l); };
+            stage_any<FFTF, AXIS, INPLACE>(tid, nt, g, st, lds, nxt, tw, sync);
+            Tile<AXIS, T> t = cur; cur = nxt; nxt = t;
+        }
     }
-    phase_post<KIND, FWD>(tid, nt, g, src, dst, tw);
-    sync();
-    return dst;
+    const int total = g.M * g.L;
+    for (int w = tid; w < total; w += nt) {
+        int l, k;
+        split_item<AXIS>(w, g.M, g.magM, g.lgL, g.L, l, k);
+        unpack<KIND, FWD, T>(
+            k, g, [&](int kk) -> cx<T> { return cur.at(kk, l); }, [&](int q, T v) { put(q, l, v); }, tw);
+    }
 }
 
 }  // namespace cans

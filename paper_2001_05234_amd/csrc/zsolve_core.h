@@ -273,12 +273,12 @@ CANS_HD void zp_shift(ZLane<MMAX> &L, ZSeg sg, double m)
 template <int MMAX>
 CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
 {
-    // the pinned row of the singular lane carries rhs 0
-    if (L.sing && sg.k0 + sg.m == a.nz) L.f[sg.m - 1] = 0.0;
     double cp = 0, d = 0, g = 0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
         if (t < sg.m) {
+            // the pinned row of the singular lane carries rhs 0
+            if (L.sing && sg.k0 + t == a.nz - 1) L.f[t] = 0.0;
             double ak, bk, ck;
             zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
             const double rr = rcp64(t == 0 ? bk : bk - ak * cp);

@@ -19,22 +19,36 @@ struct NoSync {
     void operator()() const {}
 };
 
-template <int KIND, bool FWD, typename T>
-T *run_tile(const XGeom &g, T *b0, T *b1, const cx<T> *tw)
+// transform along x (axis 0) or y (axis 1) of a (nz, ny, nx) field, in place,
+// tile by tile with the kernels' tile shapes (two tiles: out of place)
+template <int KIND, bool FWD, int AXIS, typename T>
+void xform_k(const XGeom &g, int nx, int ny, int nz, std::vector<T> &a, const cx<T> *tw)
 {
-    return tile_transform<KIND, FWD>(0, 1, g, b0, b1, tw, NoSync());
-}
-
-template <typename T>
-T *dispatch(int kind, bool fwd, const XGeom &g, T *b0, T *b1, const cx<T> *tw)
-{
-#define CASE(K)                                                             \
-    case K: return fwd ? run_tile<K, true>(g, b0, b1, tw) : run_tile<K, false>(g, b0, b1, tw);
-    switch (kind) {
-        CASE(K_P) CASE(K_NN) CASE(K_DD) CASE(K_ND) CASE(K_DN)
+    std::vector<cx<T>> b0(tile_slots(AXIS, g)), b1(tile_slots(AXIS, g));
+    Tile<AXIS, T> ta{b0.data(), g.L, g.RS, g.psh}, tb{b1.data(), g.L, g.RS, g.psh};
+    std::vector<T> out(a.size());
+    const int n = g.n;
+    if constexpr (AXIS == AX_X) {
+        const long nlines = (long)ny * nz;
+        for (long line0 = 0; line0 < nlines; line0 += g.L) {
+            auto src = [&](int e, int l) -> T { return line0 + l < nlines ? a[(size_t)(line0 + l) * n + e] : T(0); };
+            auto put = [&](int q, int l, T v) {
+                if (line0 + l < nlines) out[(size_t)(line0 + l) * n + q] = v;
+            };
+            tile_transform<KIND, FWD, AX_X, false>(0, 1, g, src, put, ta, tb, tw, NoSync());
+        }
+    } else {
+        for (int k = 0; k < nz; ++k)
+            for (int i0 = 0; i0 < nx; i0 += g.L) {
+                const size_t base = (size_t)k * nx * ny;
+                auto src = [&](int e, int l) -> T { return i0 + l < nx ? a[base + (size_t)e * nx + i0 + l] : T(0); };
+                auto put = [&](int q, int l, T v) {
+                    if (i0 + l < nx) out[base + (size_t)q * nx + i0 + l] = v;
+                };
+                tile_transform<KIND, FWD, AX_Y, false>(0, 1, g, src, put, ta, tb, tw, NoSync());
+            }
     }
-#undef CASE
-    return nullptr;
+    a.swap(out);
 }
 
 template <typename T>
@@ -46,39 +60,27 @@ std::vector<cx<T>> tw_as(int n)
     return o;
 }
 
-// transform along x (axis 0) or y (axis 1) of a (nz, ny, nx) field, in place
 template <typename T>
 int xform(int kind, bool fwd, int axis, int nx, int ny, int nz, std::vector<T> &a)
 {
     const int n = axis == 0 ? nx : ny;
-    XGeom g{};
-    set_tile(g, n, axis == 0 ? tile_x(n, sizeof(T)) : tile_y(n, sizeof(T)));
-    if (!factor(n / 2, g)) return -2;
+    XGeom g;
+    if (!make_geom(g, axis == 0 ? AX_X : AX_Y, n, sizeof(T))) return -2;
     std::vector<cx<T>> tw = tw_as<T>(n);
-    std::vector<T> buf(2 * (size_t)n * g.L);
-    T *b0 = buf.data(), *b1 = b0 + (size_t)n * g.L;
-    if (axis == 0) {
-        const long nlines = (long)ny * nz;
-        for (long line0 = 0; line0 < nlines; line0 += g.L) {
-            for (int l = 0; l < g.L; ++l)
-                for (int i = 0; i < n; ++i)
-                    R(b1, g, i, l) = line0 + l < nlines ? a[(size_t)(line0 + l) * n + i] : T(0);
-            T *res = dispatch<T>(kind, fwd, g, b0, b1, tw.data());
-            for (int l = 0; l < g.L && line0 + l < nlines; ++l)
-                for (int i = 0; i < n; ++i) a[(size_t)(line0 + l) * n + i] = R(res, g, i, l);
-        }
-    } else {
-        for (int k = 0; k < nz; ++k)
-            for (int i0 = 0; i0 < nx; i0 += g.L) {
-                const size_t base = (size_t)k * nx * ny;
-                for (int j = 0; j < n; ++j)
-                    for (int l = 0; l < g.L; ++l)
-                        R(b1, g, j, l) = i0 + l < nx ? a[base + (size_t)j * nx + i0 + l] : T(0);
-                T *res = dispatch<T>(kind, fwd, g, b0, b1, tw.data());
-                for (int j = 0; j < n; ++j)
-                    for (int l = 0; l < g.L && i0 + l < nx; ++l) a[base + (size_t)j * nx + i0 + l] = R(res, g, j, l);
-            }
+#define CASE(K)                                                                            \
+    case K:                                                                                \
+        if (axis == 0) {                                                                   \
+            if (fwd) xform_k<K, true, AX_X>(g, nx, ny, nz, a, tw.data());                  \
+            else xform_k<K, false, AX_X>(g, nx, ny, nz, a, tw.data());                     \
+        } else {                                                                           \
+            if (fwd) xform_k<K, true, AX_Y>(g, nx, ny, nz, a, tw.data());                  \
+            else xform_k<K, false, AX_Y>(g, nx, ny, nz, a, tw.data());                     \
+        }                                                                                  \
+        break;
+    switch (kind) {
+        CASE(K_P) CASE(K_NN) CASE(K_DD) CASE(K_ND) CASE(K_DN)
     }
+#undef CASE
     return 0;
 }
 
