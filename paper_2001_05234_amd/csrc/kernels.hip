@@ -82,14 +82,6 @@ __global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, 
     const int n = g.n;
     const long line0 = (long)blockIdx.x * g.L;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
-    double acc = 0;
-    auto src = [&](int e, int l) -> T {
-        const long line = line0 + l;
-        if (line >= nlines) return T(0);
-        const Tin x = in[line * n + e];
-        if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
-        return (T)x;
-    };
     const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
     auto put = [&](int q, int l, T v) {
         const long line = line0 + l;
@@ -99,14 +91,37 @@ __global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, 
             else out[idx] = (Tout)v;
         }
     };
-    tile_transform<KIND, FWD, AX_X, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
-    if (wsum_part) {
-        double z1 = 0, z2 = 0;
-        block_sum3(acc, z1, z2);
-        if (threadIdx.x == 0) {
-            wsum_part[3 * blockIdx.x] = acc;
-            wsum_part[3 * blockIdx.x + 1] = 0;
-            wsum_part[3 * blockIdx.x + 2] = 0;
+    // inverse real-DFT / DCT / DST synthesis reads every input twice: stage
+    // the lines in LDS with coalesced loads first
+    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
+    if constexpr (STAGED) {
+        for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
+            const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
+            const long line = line0 + l;
+            tile_real(tile, e, l) = line < nlines ? (T)in[line * n + e] : T(0);
+        }
+        __syncthreads();
+        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
+        tile_transform<KIND, FWD, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    } else {
+        double acc = 0;
+        auto src = [&](int e, int l) -> T {
+            const long line = line0 + l;
+            if (line >= nlines) return T(0);
+            const Tin x = in[line * n + e];
+            if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
+            return (T)x;
+        };
+        tile_transform<KIND, FWD, AX_X, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
+                                                     BlockSync());
+        if (wsum_part) {
+            double z1 = 0, z2 = 0;
+            block_sum3(acc, z1, z2);
+            if (threadIdx.x == 0) {
+                wsum_part[3 * blockIdx.x] = acc;
+                wsum_part[3 * blockIdx.x + 1] = 0;
+                wsum_part[3 * blockIdx.x + 2] = 0;
+            }
         }
     }
 }
@@ -124,15 +139,27 @@ __global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, i
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = (int)(t % ntx) * g.L;
     const size_t base = (size_t)(t / ntx) * nx * ny;
-    auto src = [&](int e, int l) -> T {
-        const int i = i0 + l;
-        return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
-    };
     auto put = [&](int q, int l, T v) {
         const int i = i0 + l;
         if (i < nx) out[base + (size_t)q * nx + i] = (Tio)v;
     };
-    tile_transform<KIND, FWD, AX_Y, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
+    if constexpr (STAGED) {
+        for (int idx = threadIdx.x; idx < ny * g.L; idx += kThreads) {
+            const int l = idx & (g.L - 1), e = idx >> g.lgL, i = i0 + l;
+            tile_real(tile, e, l) = i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+        }
+        __syncthreads();
+        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
+        tile_transform<KIND, FWD, AX_Y, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    } else {
+        auto src = [&](int e, int l) -> T {
+            const int i = i0 + l;
+            return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+        };
+        tile_transform<KIND, FWD, AX_Y, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
+                                                     BlockSync());
+    }
 }
 
 // Residual of the current p fused with the forward x transform of it:
@@ -156,24 +183,31 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mf = info[I_REMOVED];
     double srr = 0, sff = 0, spw = 0;
-    auto src = [&](int e, int l) -> float {
+    // residual of the tile's lines into LDS (coalesced, each point once)
+    for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
+        const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
         const long line = line0 + l;
-        if (line >= nlines) return 0.f;
-        const int k = line_level(line, line0, k0, j0, ny);
-        const int j = (int)(line - (long)k * ny);
-        const size_t idx = (size_t)line * n + e;
-        const double fv = f[idx] - mf;
-        const double r = fv - lap_point(p, e, j, k, la);
-        srr += r * r;
-        sff += fv * fv;
-        spw += dzf[k] * p[idx];
-        return (float)r;
-    };
+        float v = 0.f;
+        if (line < nlines) {
+            const int k = line_level(line, line0, k0, j0, ny);
+            const int j = (int)(line - (long)k * ny);
+            const size_t gi = (size_t)line * n + e;
+            const double fv = f[gi] - mf;
+            const double r = fv - lap_point(p, e, j, k, la);
+            srr += r * r;
+            sff += fv * fv;
+            spw += dzf[k] * p[gi];
+            v = (float)r;
+        }
+        tile_real(tile, e, l) = v;
+    }
+    __syncthreads();
+    auto src = [&](int e, int l) -> float { return tile_real(tile, e, l); };
     auto put = [&](int q, int l, float v) {
         const long line = line0 + l;
         if (line < nlines) out[(size_t)line * n + q] = v;
     };
-    tile_transform<KIND, true, AX_X, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    tile_transform<KIND, true, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
     block_sum3(srr, sff, spw);
     if (threadIdx.x == 0) {
         partials[3 * blockIdx.x + 0] = srr;
@@ -281,8 +315,8 @@ static ZArgs zargs(const Problem &pb, double *removed);
 
 // Partitioned column solve: 64 columns per block (lane = column), one z
 // segment per wave, everything in registers and LDS (see zsolve_core.h).
-template <typename T, int MMAX>
-__global__ __launch_bounds__(1024) void k_zsolve_part(T *data, ZArgs a, const int *__restrict__ done)
+template <typename T, int MMAX, int NTMAX>
+__global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs a, const int *__restrict__ done)
 {
     if (done && *done) return;
     __shared__ double coef[6][16][64];
@@ -343,9 +377,9 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
     const int S = (pb.nz + mm - 1) / mm;
     const dim3 grid((unsigned)((plane + 63) / 64)), block(64 * S);
     switch (mm) {
-    case 8: hipLaunchKernelGGL((k_zsolve_part<T, 8>), grid, block, 0, s, data, za, done); break;
-    case 16: hipLaunchKernelGGL((k_zsolve_part<T, 16>), grid, block, 0, s, data, za, done); break;
-    default: hipLaunchKernelGGL((k_zsolve_part<T, 24>), grid, block, 0, s, data, za, done); break;
+    case 8: hipLaunchKernelGGL((k_zsolve_part<T, 8, 1024>), grid, block, 0, s, data, za, done); break;
+    case 16: hipLaunchKernelGGL((k_zsolve_part<T, 16, 1024>), grid, block, 0, s, data, za, done); break;
+    default: hipLaunchKernelGGL((k_zsolve_part<T, 48, 512>), grid, block, 0, s, data, za, done); break;
     }
     return check_launch();
 }

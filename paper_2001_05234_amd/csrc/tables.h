@@ -83,6 +83,7 @@ inline bool make_geom(XGeom &g, int axis, int n, int elem)
     g.psh = elem == 8 ? 4 : 5;  // 256-byte LDS rows of 16-byte / 8-byte slots
     g.RS = g.M + ((g.M - 1) >> g.psh) + 1;
     g.magM = mag_of((unsigned)g.M);
+    g.magN = mag_of((unsigned)g.n);
     if (!factor(g.M, g)) return false;
     // every in-place stage must fit the per-thread capacity of a 256-thread block
     for (int st = 0; st < g.nst; ++st)

@@ -166,6 +166,7 @@ struct XGeom {
     int psh;    // x tiles: one pad slot every 2^psh slots (256-byte LDS rows)
     int nst;    // FFT stages
     unsigned magM;
+    unsigned magN;     // magic for / n
     int rad[kMaxStages];
     int str[kMaxStages];       // s of each stage (product of earlier radices)
     unsigned mag_s[kMaxStages];   // magic for / s
@@ -421,12 +422,14 @@ CANS_HD void stage_any(int tid, int nt, const XGeom &g, int st, const In &in, co
 }
 
 // The whole transform of a tile.
-//   src(e, l):   real e of input line l (global memory, or a computed value)
+//   src(e, l):   real e of input line l (global memory, a computed value, or
+//                with SRCTILE the tile itself, filled by the caller)
 //   put(q, l, v): real q of output line l
 //   ta, tb:      tiles; the kernels pass one tile twice (INPLACE), the host
 //                build passes two (ping-pong).
 // The caller synchronises before reusing the tile.
-template <int KIND, bool FWD, int AXIS, bool INPLACE, typename T, typename Src, typename Put, typename Sync>
+template <int KIND, bool FWD, int AXIS, bool INPLACE, bool SRCTILE, typename T, typename Src, typename Put,
+          typename Sync>
 CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, const Put &put, Tile<AXIS, T> ta,
                             Tile<AXIS, T> tb, const cx<T> *tw, const Sync &sync)
 {
@@ -436,16 +439,25 @@ CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, con
         return pack<KIND, FWD, T>(m, g, [&](int e) -> T { return src(e, l); }, tw);
     };
     Tile<AXIS, T> cur = ta, nxt = tb;
-    if (g.nst == 0) {  // M = 1: the packed value is the spectrum
-        for (int w = tid; w < g.L; w += nt) cur.at(0, w) = packed(0, w);
+    if (g.nst == 0) {
+        // M = 1: the packed value is the spectrum; each line's slot is read
+        // and written by the same thread
+        for (int w = tid; w < g.L; w += nt) {
+            const cx<T> z = packed(0, w);
+            nxt.at(0, w) = z;
+        }
         sync();
+        cur = nxt;
+    } else if (SRCTILE) {
+        stage_any<FFTF, AXIS, INPLACE>(tid, nt, g, 0, packed, nxt, tw, sync);
+        Tile<AXIS, T> t = cur; cur = nxt; nxt = t;
     } else {
         stage_any<FFTF, AXIS, false>(tid, nt, g, 0, packed, cur, tw, sync);
-        for (int st = 1; st < g.nst; ++st) {
-            auto lds = [&](int m, int l) -> cx<T> { return cur.at(m, l); };
-            stage_any<FFTF, AXIS, INPLACE>(tid, nt, g, st, lds, nxt, tw, sync);
-            Tile<AXIS, T> t = cur; cur = nxt; nxt = t;
-        }
+    }
+    for (int st = 1; st < g.nst; ++st) {
+        auto lds = [&](int m, int l) -> cx<T> { return cur.at(m, l); };
+        stage_any<FFTF, AXIS, INPLACE>(tid, nt, g, st, lds, nxt, tw, sync);
+        Tile<AXIS, T> t = cur; cur = nxt; nxt = t;
     }
     const int total = g.M * g.L;
     for (int w = tid; w < total; w += nt) {
@@ -454,6 +466,13 @@ CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, con
         unpack<KIND, FWD, T>(
             k, g, [&](int kk) -> cx<T> { return cur.at(kk, l); }, [&](int q, T v) { put(q, l, v); }, tw);
     }
+}
+
+// real e of line l of a tile (the real view used by SRCTILE loads)
+template <int AXIS, typename T>
+CANS_HD T &tile_real(const Tile<AXIS, T> &t, int e, int l)
+{
+    return reinterpret_cast<T *>(&t.at(e >> 1, l))[e & 1];
 }
 
 }  // namespace cans

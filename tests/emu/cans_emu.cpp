@@ -24,10 +24,23 @@ struct NoSync {
 template <int KIND, bool FWD, int AXIS, typename T>
 void xform_k(const XGeom &g, int nx, int ny, int nz, std::vector<T> &a, const cx<T> *tw)
 {
+    // as the kernels: inverse real-DFT / DCT / DST synthesis stages its lines
+    // in the tile first
+    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
     std::vector<cx<T>> b0(tile_slots(AXIS, g)), b1(tile_slots(AXIS, g));
     Tile<AXIS, T> ta{b0.data(), g.L, g.RS, g.psh}, tb{b1.data(), g.L, g.RS, g.psh};
     std::vector<T> out(a.size());
     const int n = g.n;
+    auto run = [&](auto gsrc, auto put) {
+        if constexpr (STAGED) {
+            for (int l = 0; l < g.L; ++l)
+                for (int e = 0; e < n; ++e) tile_real(ta, e, l) = gsrc(e, l);
+            auto src = [&](int e, int l) -> T { return tile_real(ta, e, l); };
+            tile_transform<KIND, FWD, AXIS, false, true>(0, 1, g, src, put, ta, tb, tw, NoSync());
+        } else {
+            tile_transform<KIND, FWD, AXIS, false, false>(0, 1, g, gsrc, put, ta, tb, tw, NoSync());
+        }
+    };
     if constexpr (AXIS == AX_X) {
         const long nlines = (long)ny * nz;
         for (long line0 = 0; line0 < nlines; line0 += g.L) {
@@ -35,7 +48,7 @@ void xform_k(const XGeom &g, int nx, int ny, int nz, std::vector<T> &a, const cx
             auto put = [&](int q, int l, T v) {
                 if (line0 + l < nlines) out[(size_t)(line0 + l) * n + q] = v;
             };
-            tile_transform<KIND, FWD, AX_X, false>(0, 1, g, src, put, ta, tb, tw, NoSync());
+            run(src, put);
         }
     } else {
         for (int k = 0; k < nz; ++k)
@@ -45,7 +58,7 @@ void xform_k(const XGeom &g, int nx, int ny, int nz, std::vector<T> &a, const cx
                 auto put = [&](int q, int l, T v) {
                     if (i0 + l < nx) out[base + (size_t)q * nx + i0 + l] = v;
                 };
-                tile_transform<KIND, FWD, AX_Y, false>(0, 1, g, src, put, ta, tb, tw, NoSync());
+                run(src, put);
             }
     }
     a.swap(out);
@@ -136,7 +149,7 @@ void zsolve_any(Setup &s, T *data, double *removed)
     s.z.removed = removed;
     if (mm == 8) zsolve_part_mm<8>(s, data, removed);
     else if (mm == 16) zsolve_part_mm<16>(s, data, removed);
-    else if (mm == 24) zsolve_part_mm<24>(s, data, removed);
+    else if (mm == 48) zsolve_part_mm<48>(s, data, removed);
     else for (size_t col = 0; col < (size_t)s.nx * s.ny; ++col) zsolve_column(col, data, s.z);
 }
 
@@ -210,7 +223,7 @@ int emu_zsolve_part(int nx, int ny, int nz, const int *bc, double dx, double dy,
     switch (mm) {
     case 8: zsolve_part_mm<8>(s, data, removed); return 0;
     case 16: zsolve_part_mm<16>(s, data, removed); return 0;
-    case 24: zsolve_part_mm<24>(s, data, removed); return 0;
+    case 48: zsolve_part_mm<48>(s, data, removed); return 0;
     default: return -2;
     }
 }
