@@ -143,7 +143,8 @@ __global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, i
         const int i = i0 + l;
         if (i < nx) out[base + (size_t)q * nx + i] = (Tio)v;
     };
-    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
+    // y tiles read their rows directly (staging through LDS measured slower)
+    constexpr bool STAGED = false;
     if constexpr (STAGED) {
         for (int idx = threadIdx.x; idx < ny * g.L; idx += kThreads) {
             const int l = idx & (g.L - 1), e = idx >> g.lgL, i = i0 + l;
@@ -379,7 +380,7 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
     switch (mm) {
     case 8: hipLaunchKernelGGL((k_zsolve_part<T, 8, 1024>), grid, block, 0, s, data, za, done); break;
     case 16: hipLaunchKernelGGL((k_zsolve_part<T, 16, 1024>), grid, block, 0, s, data, za, done); break;
-    default: hipLaunchKernelGGL((k_zsolve_part<T, 48, 512>), grid, block, 0, s, data, za, done); break;
+    default: hipLaunchKernelGGL((k_zsolve_part<T, 24, 1024>), grid, block, 0, s, data, za, done); break;
     }
     return check_launch();
 }

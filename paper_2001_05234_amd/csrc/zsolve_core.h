@@ -372,15 +372,14 @@ CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col,
         if (t < sg.m) data[col + plane * (sg.k0 + t)] = (T)L.f[t];
 }
 
-// register depth per lane for nz: up to 16 segments of <= 16 levels (1024
-// threads, <= 128 registers each), else up to 8 segments of <= 48 levels
-// (512 threads); 0 when nz > 384 (the plain elimination with a workspace is
-// used then, and for periodic z)
+// register depth per lane for nz: up to 16 segments (one wave each, 1024
+// threads) of at most 8, 16 or 24 levels; 0 when nz > 384 (the plain
+// elimination with a workspace is used then, and for periodic z)
 inline int zpart_mmax(int nz)
 {
     if (nz <= 128) return 8;
     if (nz <= 256) return 16;
-    if (nz <= 384) return 48;
+    if (nz <= 384) return 24;
     return 0;
 }
 

@@ -149,7 +149,7 @@ void zsolve_any(Setup &s, T *data, double *removed)
     s.z.removed = removed;
     if (mm == 8) zsolve_part_mm<8>(s, data, removed);
     else if (mm == 16) zsolve_part_mm<16>(s, data, removed);
-    else if (mm == 48) zsolve_part_mm<48>(s, data, removed);
+    else if (mm == 24) zsolve_part_mm<24>(s, data, removed);
     else for (size_t col = 0; col < (size_t)s.nx * s.ny; ++col) zsolve_column(col, data, s.z);
 }
 
@@ -223,7 +223,7 @@ int emu_zsolve_part(int nx, int ny, int nz, const int *bc, double dx, double dy,
     switch (mm) {
     case 8: zsolve_part_mm<8>(s, data, removed); return 0;
     case 16: zsolve_part_mm<16>(s, data, removed); return 0;
-    case 48: zsolve_part_mm<48>(s, data, removed); return 0;
+    case 24: zsolve_part_mm<24>(s, data, removed); return 0;
     default: return -2;
     }
 }
