@@ -98,6 +98,34 @@ def copy_gbs(torch, nbytes):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def bench_batched(torch, capi, inputs, args):
+    """64 uneven problems (sizes, boundary sets and stretching drawn from a
+    seed) solved as one graph launch, FP32 transforms + FP64 refinement."""
+    probs = inputs.batch_c5()
+    fs = [torch.from_numpy(pr.rhs()).cuda() for pr in probs]
+    ps = [torch.zeros_like(f) for f in fs]
+    plan = capi.BatchedPlan(probs, precision="fp32_refine", tol=1e-10, max_iter=4)
+    for _ in range(3):
+        plan.solve(fs, ps)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(5, args.steps)
+    s.record()
+    for _ in range(reps):
+        plan.solve(fs, ps)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    npts = sum(pr.npts for pr in probs)
+    conv = all(plan.info(i)["converged"] for i in range(len(probs)))
+    worst = max(plan.info(i)["residual"] for i in range(len(probs)))
+    plan.close()
+    say(f"[bench] batched: {len(probs)} problems, {npts} points, {ms:.3f} ms, converged {conv}, worst residual {worst:.2e}")
+    return {"workload": "c5: 64 uneven problems, seed 5, FP32 transforms + FP64 refinement to 1e-10, one graph launch",
+            "value": npts / (ms * 1e-3), "unit": "grid pts/s", "ms_per_step": ms, "grid_points": npts,
+            "converged": conv, "worst_residual": worst}
+
+
 def cpu_baseline(pr, f, nz_sample):
     """The oracle, as it stands, on the first nz_sample z-levels of the grid
     (full x-y planes: the same per-point work, O(nx + ny) transform
@@ -126,6 +154,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--cpu-sample-levels", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--solve-only", action="store_true", help="time the refine solve only (profiling runs)")
     ap.add_argument("--fp64-only", action="store_true", help="time the FP64 solve only (profiling runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -217,6 +246,8 @@ def main():
     plan64.close()
     del b
     out["copy_GBps"] = copy_gbs(torch, 1 << 30)
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, capi, inputs, args)
 
     if not args.no_cpu_baseline:
         say("[bench] cpu baseline (oracle)")

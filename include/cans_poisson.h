@@ -176,7 +176,11 @@ int cans_poisson_plan_batched(cans_plan_t *out, int count, const cans_desc *desc
                               const cans_opts *opts);
 
 /* Solve every problem of a batched plan: rhs[i], p[i] are device arrays of
- * problem i.  Enqueued on `stream` without host synchronisation. */
+ * problem i.  The whole batch is one graph launch on `stream` (no host
+ * synchronisation): the first call, and any call with different array
+ * addresses, captures the kernels of all problems into a HIP graph whose
+ * independent branches run problems concurrently; later calls replay it.
+ * Same ownership and aliasing rules as cans_poisson_solve. */
 int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, double *const *p,
                                hipStream_t stream);
 

@@ -4,6 +4,7 @@
 // workspace, and the order of kernel launches of one solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -14,12 +15,29 @@
 
 using namespace cans;
 
+// Batched solves run as one captured graph: the instances are spread over
+// kBranches capture streams (largest first, each to the least loaded branch)
+// so independent problems execute concurrently, and the whole batch is a
+// single hipGraphLaunch on the caller's stream.
+constexpr int kBranches = 4;
+
+struct BatchGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> key;   // rhs and p pointers the graph was captured with
+    hipStream_t cap = nullptr;
+    hipStream_t side[kBranches] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBranches] = {};
+    std::vector<int> branch;         // branch of each instance
+};
+
 struct cans_plan_s {
     int device = 0;
     cans_opts opts{};
     std::vector<Problem> probs;
     std::vector<void *> allocs;
     size_t bytes = 0;
+    BatchGraph g;
 };
 
 namespace {
@@ -138,10 +156,45 @@ int check_opts(const cans_opts &o)
     return CANS_OK;
 }
 
+void free_graph(BatchGraph &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    for (int b = 0; b < kBranches; ++b) {
+        if (g.side[b]) (void)hipStreamDestroy(g.side[b]);
+        if (g.join[b]) (void)hipEventDestroy(g.join[b]);
+        g.side[b] = nullptr;
+        g.join[b] = nullptr;
+    }
+    if (g.cap) (void)hipStreamDestroy(g.cap);
+    if (g.fork) (void)hipEventDestroy(g.fork);
+    g.cap = nullptr;
+    g.fork = nullptr;
+}
+
 void free_plan(cans_plan_s *pl)
 {
+    free_graph(pl->g);
     for (void *p : pl->allocs) (void)hipFree(p);
     delete pl;
+}
+
+// longest-processing-time assignment of instances to graph branches
+std::vector<int> assign_branches(const std::vector<Problem> &probs)
+{
+    std::vector<int> order(probs.size()), br(probs.size(), 0);
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return probs[a].npts() > probs[b].npts(); });
+    double load[kBranches] = {0, 0, 0, 0};
+    for (int i : order) {
+        int best = 0;
+        for (int b = 1; b < kBranches; ++b)
+            if (load[b] < load[best]) best = b;
+        br[i] = best;
+        load[best] += (double)probs[i].npts();
+    }
+    return br;
 }
 
 int solve_fp64(const Problem &pb, const double *rhs, double *p, hipStream_t s)
@@ -285,18 +338,61 @@ int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream
 int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, double *const *p, hipStream_t stream)
 {
     if (!plan || !rhs || !p) return CANS_ERR_INVALID_ARG;
-    for (size_t i = 0; i < plan->probs.size(); ++i) {
+    const size_t n = plan->probs.size();
+    std::vector<const void *> key(2 * n);
+    for (size_t i = 0; i < n; ++i) {
         if (!rhs[i] || !p[i]) return CANS_ERR_INVALID_ARG;
         if (plan->opts.precision != CANS_PREC_FP64 && (const void *)rhs[i] == (const void *)p[i])
             return CANS_ERR_ALIAS;
+        key[2 * i] = rhs[i];
+        key[2 * i + 1] = p[i];
     }
-    for (size_t i = 0; i < plan->probs.size(); ++i) {
-        const Problem &pb = plan->probs[i];
-        int rc = plan->opts.precision == CANS_PREC_FP64 ? solve_fp64(pb, rhs[i], p[i], stream)
-                                                        : solve_refine(pb, plan->opts, rhs[i], p[i], stream);
-        if (rc != CANS_OK) return rc;
+    BatchGraph &g = plan->g;
+    if (!g.exec || g.key != key) {
+        // (re)capture the whole batch; kernels only, so replays are exact
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        if (!g.cap) {
+            if (hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&g.fork, hipEventDisableTiming) != hipSuccess)
+                return CANS_ERR_HIP;
+            for (int b = 0; b < kBranches; ++b)
+                if (hipStreamCreateWithFlags(&g.side[b], hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&g.join[b], hipEventDisableTiming) != hipSuccess)
+                    return CANS_ERR_HIP;
+            g.branch = assign_branches(plan->probs);
+        }
+        if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return CANS_ERR_HIP;
+        int rc = CANS_OK;
+        if (hipEventRecord(g.fork, g.cap) != hipSuccess) rc = CANS_ERR_HIP;
+        for (int b = 0; b < kBranches && rc == CANS_OK; ++b)
+            if (hipStreamWaitEvent(g.side[b], g.fork, 0) != hipSuccess) rc = CANS_ERR_HIP;
+        for (size_t i = 0; i < n && rc == CANS_OK; ++i) {
+            const Problem &pb = plan->probs[i];
+            hipStream_t s = g.side[g.branch[i]];
+            rc = plan->opts.precision == CANS_PREC_FP64 ? solve_fp64(pb, rhs[i], p[i], s)
+                                                        : solve_refine(pb, plan->opts, rhs[i], p[i], s);
+        }
+        for (int b = 0; b < kBranches && rc == CANS_OK; ++b)
+            if (hipEventRecord(g.join[b], g.side[b]) != hipSuccess || hipStreamWaitEvent(g.cap, g.join[b], 0) != hipSuccess)
+                rc = CANS_ERR_HIP;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(g.cap, &graph);
+        if (rc != CANS_OK || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc != CANS_OK ? rc : CANS_ERR_HIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            g.exec = nullptr;
+            return CANS_ERR_HIP;
+        }
+        g.key = key;
     }
-    return CANS_OK;
+    return hipGraphLaunch(g.exec, stream) == hipSuccess ? CANS_OK : CANS_ERR_HIP;
 }
 
 int cans_poisson_get_info(cans_plan_t plan, cans_info *out)
