@@ -62,8 +62,10 @@ enum cans_precision {
 enum cans_xform_mode {
     CANS_XFORM_AUTO = 0,
     CANS_XFORM_FFT = 1,         /* LDS radix FFT with fused pre/post twiddles */
-    CANS_XFORM_DENSE = 2        /* dense matrix product on the matrix cores
-                                   (FP32_REFINE only; x axis only) */
+    CANS_XFORM_DENSE = 2        /* dense matrix product on the matrix cores,
+                                   split-bf16 operands, FP32 accumulation
+                                   (FP32_REFINE only; x axis only; nx = 128,
+                                   256, 384 or 512) */
 };
 
 typedef struct cans_opts {

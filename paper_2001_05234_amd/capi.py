@@ -132,7 +132,7 @@ class Plan:
     ``cans_poisson_solve`` on a stream without host synchronisation."""
 
     def __init__(self, nx: int, ny: int, nz: int, bc, dx: float, dy: float, dzf,
-                 precision: str = "fp64", tol: float = 1e-10, max_iter: int = 4):
+                 precision: str = "fp64", tol: float = 1e-10, max_iter: int = 4, xform_x: str = "auto"):
         lib = load()
         self._lib = lib
         self.shape = (nz, ny, nx)
@@ -141,6 +141,7 @@ class Plan:
         o.precision = PREC_FP64 if precision == "fp64" else PREC_FP32_REFINE
         o.tol = tol
         o.max_iter = max_iter
+        o.xform_x = {"auto": XFORM_AUTO, "fft": XFORM_FFT, "dense": XFORM_DENSE}[xform_x]
         dz = np.ascontiguousarray(np.asarray(dzf, dtype=np.float64))
         if dz.shape != (nz,):
             raise ValueError("dzf must hold nz cell widths")

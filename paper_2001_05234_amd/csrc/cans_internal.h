@@ -32,6 +32,9 @@ struct Axis {
     double *d_lam = nullptr;   // mu(q)/h^2 in the transform's row order
     cx<double> *d_tw64 = nullptr;
     cx<float> *d_tw32 = nullptr;
+    // dense (matrix-core) form: bf16 hi/lo of the forward and inverse matrices
+    bool dense = false;
+    unsigned short *d_wf_hi = nullptr, *d_wf_lo = nullptr, *d_wi_hi = nullptr, *d_wi_lo = nullptr;
 };
 
 struct Problem {

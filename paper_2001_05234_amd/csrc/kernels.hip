@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cans_internal.h"
+#include "dense_core.h"
 
 namespace cans {
 
@@ -385,6 +386,98 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
     return check_launch();
 }
 
+
+// ---------------------------------------------------------------------------
+// Dense (matrix-core) x transforms of the refinement path: the same prologues
+// and epilogues as the FFT kernels around dense_transform (32 lines a block).
+template <bool FWD, typename Tin, typename Tout, int EPI>
+__global__ __launch_bounds__(256) void k_dense_x(const Tin *in, Tout *out, long nlines, int n, unsigned magn,
+                                                 const unsigned short *__restrict__ Wh,
+                                                 const unsigned short *__restrict__ Wl,
+                                                 const double *__restrict__ info, const int *__restrict__ done,
+                                                 const double *__restrict__ dzf, int ny,
+                                                 double *__restrict__ wsum_part)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long line0 = (long)blockIdx.x * kDenseLines;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
+    double acc = 0;
+    auto src = [&](int e, int l) -> float {
+        const long line = line0 + l;
+        if (line >= nlines) return 0.f;
+        const Tin x = in[line * n + e];
+        if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
+        return (float)x;
+    };
+    const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
+    auto put = [&](int q, int l, float v) {
+        const long line = line0 + l;
+        if (line < nlines) {
+            const size_t idx = (size_t)line * n + q;
+            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
+            else out[idx] = (Tout)v;
+        }
+    };
+    dense_transform(n, magn, src, put, Wh, Wl, reinterpret_cast<unsigned short *>(smem));
+    if (wsum_part) {
+        double z1 = 0, z2 = 0;
+        block_sum3(acc, z1, z2);
+        if (threadIdx.x == 0) {
+            wsum_part[3 * blockIdx.x] = acc;
+            wsum_part[3 * blockIdx.x + 1] = 0;
+            wsum_part[3 * blockIdx.x + 2] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ f, const double *__restrict__ p,
+                                                     float *out, long nlines, int n, unsigned magn,
+                                                     const unsigned short *__restrict__ Wh,
+                                                     const unsigned short *__restrict__ Wl, LapArgs la,
+                                                     const double *__restrict__ dzf,
+                                                     const double *__restrict__ info,
+                                                     double *__restrict__ partials, const int *__restrict__ done)
+{
+    if (*done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ny = la.ny;
+    const long line0 = (long)blockIdx.x * kDenseLines;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
+    const double mf = info[I_REMOVED];
+    double srr = 0, sff = 0, spw = 0;
+    auto src = [&](int e, int l) -> float {
+        const long line = line0 + l;
+        if (line >= nlines) return 0.f;
+        const int k = line_level(line, line0, k0, j0, ny);
+        const int j = (int)(line - (long)k * ny);
+        const size_t gi = (size_t)line * n + e;
+        const double fv = f[gi] - mf;
+        const double r = fv - lap_point(p, e, j, k, la);
+        srr += r * r;
+        sff += fv * fv;
+        spw += dzf[k] * p[gi];
+        return (float)r;
+    };
+    auto put = [&](int q, int l, float v) {
+        const long line = line0 + l;
+        if (line < nlines) out[(size_t)line * n + q] = v;
+    };
+    dense_transform(n, magn, src, put, Wh, Wl, reinterpret_cast<unsigned short *>(smem));
+    block_sum3(srr, sff, spw);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x + 0] = srr;
+        partials[3 * blockIdx.x + 1] = sff;
+        partials[3 * blockIdx.x + 2] = spw;
+    }
+}
+
+static dim3 dense_grid(const Problem &pb)
+{
+    const long nlines = (long)pb.ny * pb.nz;
+    return dim3((unsigned)((nlines + kDenseLines - 1) / kDenseLines));
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 static size_t tile_lds(int axis, const XGeom &g, size_t elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
@@ -419,6 +512,12 @@ int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hip
 
 int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *done, hipStream_t s)
 {
+    if (pb.ax.dense) {
+        hipLaunchKernelGGL((k_dense_x<true, double, float, 0>), dense_grid(pb), dim3(256), dense_lds(pb.nx), s, in, out,
+                           (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wf_hi, pb.ax.d_wf_lo, nullptr, done,
+                           pb.d_dzf, pb.ny, pb.partials);
+        return check_launch();
+    }
     const XGeom &g = pb.ax.gx32;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
@@ -446,6 +545,17 @@ int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipSt
 int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, const int *done,
                     hipStream_t s)
 {
+    if (pb.ax.dense) {
+        if (update)
+            hipLaunchKernelGGL((k_dense_x<false, float, double, 1>), dense_grid(pb), dim3(256), dense_lds(pb.nx), s,
+                               in, p, (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wi_hi, pb.ax.d_wi_lo,
+                               pb.d_info, done, nullptr, pb.ny, nullptr);
+        else
+            hipLaunchKernelGGL((k_dense_x<false, float, double, 0>), dense_grid(pb), dim3(256), dense_lds(pb.nx), s,
+                               in, p, (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wi_hi, pb.ax.d_wi_lo,
+                               pb.d_info, done, nullptr, pb.ny, nullptr);
+        return check_launch();
+    }
     const XGeom &g = pb.ax.gx32;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
@@ -495,12 +605,19 @@ static LapArgs lapargs(const Problem &pb)
 int resid_blocks(const Problem &pb)
 {
     const long nlines = (long)pb.ny * pb.nz;
-    return (int)((nlines + pb.ax.gx32.L - 1) / pb.ax.gx32.L);
+    const int L = pb.ax.dense ? kDenseLines : pb.ax.gx32.L;
+    return (int)((nlines + L - 1) / L);
 }
 
 int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float *out, const int *done,
                       hipStream_t s)
 {
+    if (pb.ax.dense) {
+        hipLaunchKernelGGL(k_dense_resid, dense_grid(pb), dim3(256), dense_lds(pb.nx), s, f, p, out,
+                           (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wf_hi, pb.ax.d_wf_lo, lapargs(pb),
+                           pb.d_dzf, pb.d_info, pb.partials, done);
+        return check_launch();
+    }
     const XGeom &g = pb.ax.gx32;
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)resid_blocks(pb));
@@ -515,7 +632,7 @@ int launch_resid_norm(const Problem &pb, const double *f, const double *p, const
 {
     const long nlines = (long)pb.ny * pb.nz;
     hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)resid_blocks(pb)), dim3(kThreads), 0, s, f, p, nlines,
-                       pb.ax.gx32.L, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done);
+                       pb.ax.dense ? kDenseLines : pb.ax.gx32.L, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done);
     return check_launch();
 }
 

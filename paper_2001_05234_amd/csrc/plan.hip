@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "cans_internal.h"
+#include "dense_core.h"
 #include "tables.h"
 
 using namespace cans;
@@ -103,6 +104,32 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
     return CANS_OK;
 }
 
+// bf16 hi/lo split of a long double matrix (via its FP32 value)
+void split_bf16(const std::vector<long double> &W, std::vector<unsigned short> &hi, std::vector<unsigned short> &lo)
+{
+    hi.resize(W.size());
+    lo.resize(W.size());
+    for (size_t i = 0; i < W.size(); ++i) {
+        const float x = (float)W[i];
+        hi[i] = to_bf16(x);
+        lo[i] = to_bf16(x - from_bf16(hi[i]));
+    }
+}
+
+int build_dense(cans_plan_s *pl, Axis &a)
+{
+    if (!dense_ok(a.n)) return CANS_ERR_UNSUPPORTED;
+    std::vector<unsigned short> hi, lo;
+    split_bf16(dense_forward(a.kind, a.n), hi, lo);
+    CANS_TRY(upload(pl, &a.d_wf_hi, hi.data(), hi.size()));
+    CANS_TRY(upload(pl, &a.d_wf_lo, lo.data(), lo.size()));
+    split_bf16(dense_inverse(a.kind, a.n), hi, lo);
+    CANS_TRY(upload(pl, &a.d_wi_hi, hi.data(), hi.size()));
+    CANS_TRY(upload(pl, &a.d_wi_lo, lo.data(), lo.size()));
+    a.dense = true;
+    return CANS_OK;
+}
+
 int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const int *bc, double dx, double dy,
                   const double *dz)
 {
@@ -112,6 +139,7 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     const int kx = axis_kind(bc[0], bc[1]), ky = axis_kind(bc[2], bc[3]), kz = axis_kind(bc[4], bc[5]);
     CANS_TRY(build_axis(pl, pb.ax, kx, nx, dx));
     CANS_TRY(build_axis(pl, pb.ay, ky, ny, dy));
+    if (pl->opts.xform_x == CANS_XFORM_DENSE) CANS_TRY(build_dense(pl, pb.ax));
     pb.cyclic = kz == K_P;
     pb.singular = (kx == K_P || kx == K_NN) && (ky == K_P || ky == K_NN) && (kz == K_P || kz == K_NN);
     pb.scale = 1.0 / ((double)pb.ax.s * (double)pb.ay.s);
@@ -152,7 +180,10 @@ int check_opts(const cans_opts &o)
     if (o.max_iter < 0 || o.max_iter > CANS_HISTORY - 1) return CANS_ERR_INVALID_ARG;
     if (!(o.tol >= 0) || !std::isfinite(o.tol)) return CANS_ERR_INVALID_ARG;
     for (int m : {o.xform_x, o.xform_y})
-        if (m != CANS_XFORM_AUTO && m != CANS_XFORM_FFT) return CANS_ERR_UNSUPPORTED;
+        if (m != CANS_XFORM_AUTO && m != CANS_XFORM_FFT && m != CANS_XFORM_DENSE) return CANS_ERR_INVALID_ARG;
+    // the matrix-core form exists for the x axis of the refinement path
+    if (o.xform_y == CANS_XFORM_DENSE) return CANS_ERR_UNSUPPORTED;
+    if (o.xform_x == CANS_XFORM_DENSE && o.precision != CANS_PREC_FP32_REFINE) return CANS_ERR_UNSUPPORTED;
     return CANS_OK;
 }
 

@@ -169,4 +169,47 @@ inline void zcoef(int nz, int lo, int hi, const std::vector<double> &dzf, std::v
 // normalisation s of B T = s I
 inline int xform_scale(int kind, int n) { return (kind == K_ND || kind == K_DN) ? n / 2 : n; }
 
+// Row q of the forward transform of an axis as a dense vector (the same rows,
+// order and signs the FFT path produces): T[q][e], long double.
+inline std::vector<long double> dense_forward(int kind, int n)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> T((size_t)n * n);
+    for (int q = 0; q < n; ++q)
+        for (int e = 0; e < n; ++e) {
+            long double v;
+            const long double x = e + 0.5L;
+            switch (kind) {
+            case K_P:
+                if (q == 0) v = 1;
+                else if (q == 1) v = (e & 1) ? -1 : 1;
+                else if (q % 2 == 0) v = cosl(2 * pi * (q / 2) * e / n);
+                else v = -sinl(2 * pi * (q / 2) * e / n);
+                break;
+            case K_NN: v = cosl(pi * q * x / n); break;
+            case K_DD: v = sinl(pi * (q + 1) * x / n); break;
+            case K_ND: v = cosl(pi * (2 * q + 1) * (2 * e + 1) / (4.0L * n)); break;
+            default: v = sinl(pi * (2 * q + 1) * (2 * e + 1) / (4.0L * n)); break;
+            }
+            T[(size_t)q * n + e] = v;
+        }
+    return T;
+}
+
+// The inverse B = s T^{-1} = s T^T diag(1/|row_q|^2), as rows B[e][q].
+inline std::vector<long double> dense_inverse(int kind, int n)
+{
+    std::vector<long double> T = dense_forward(kind, n), B((size_t)n * n);
+    const long double s = xform_scale(kind, n);
+    for (int q = 0; q < n; ++q) {
+        long double nn = 0;
+        for (int e = 0; e < n; ++e) nn += T[(size_t)q * n + e] * T[(size_t)q * n + e];
+        for (int e = 0; e < n; ++e) B[(size_t)e * n + q] = s * T[(size_t)q * n + e] / nn;
+    }
+    return B;
+}
+
+// dense transforms apply to n = 128 .. 512 in steps of 128
+inline bool dense_ok(int n) { return n >= 128 && n <= 512 && n % 128 == 0; }
+
 }  // namespace cans
