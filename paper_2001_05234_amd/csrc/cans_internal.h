@@ -51,6 +51,7 @@ struct Problem {
     double *wc = nullptr, *wd = nullptr, *wz = nullptr;
     float *a32 = nullptr;          // FP32 spectral field (refine mode)
     double *partials = nullptr;    // residual block sums
+    double *sums = nullptr;        // first-level sums of the partials (256 triples)
     int nres_blocks = 0;
     double *d_info = nullptr;
     int *d_flag = nullptr;         // [0] refinement finished

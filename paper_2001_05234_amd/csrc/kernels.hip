@@ -253,7 +253,31 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
     }
 }
 
-// Sum the block partials in a fixed order, record the relative residual of
+// First level of the block-partial reductions: block b sums its contiguous
+// chunk of triples (fixed order) into sums[3b..3b+2].
+constexpr int kReduceBlocks = 256;
+
+__global__ __launch_bounds__(kThreads) void k_reduce1(const double *__restrict__ partials, int nblk,
+                                                      double *__restrict__ sums, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    const int chunk = (nblk + kReduceBlocks - 1) / kReduceBlocks;
+    const int lo = blockIdx.x * chunk, hi = min(nblk, lo + chunk);
+    double a = 0, b = 0, c = 0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kThreads) {
+        a += partials[3 * i];
+        b += partials[3 * i + 1];
+        c += partials[3 * i + 2];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        sums[3 * blockIdx.x] = a;
+        sums[3 * blockIdx.x + 1] = b;
+        sums[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// Sum the first-level sums in a fixed order, record the relative residual of
 // check number `check` and decide: converged (<= tol) or out of steps.
 __global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nblk,
                                                        int check, int max_iter, double tol,
@@ -639,16 +663,20 @@ int launch_resid_norm(const Problem &pb, const double *f, const double *p, const
 int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb), check, max_iter,
-                       tol, inv_wvol, pb.singular, pb.d_info, pb.d_flag);
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb),
+                       pb.sums, pb.d_flag);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, check, max_iter, tol,
+                       inv_wvol, pb.singular, pb.d_info, pb.d_flag);
     return check_launch();
 }
 
 int launch_mean_rhs(const Problem &pb, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
-    hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb), inv_wvol,
-                       pb.singular, pb.d_info);
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb),
+                       pb.sums, nullptr);
+    hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, inv_wvol, pb.singular,
+                       pb.d_info);
     return check_launch();
 }
 

@@ -166,6 +166,7 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
         CANS_TRY(alloc(pl, &pb.a32, N));
         pb.nres_blocks = resid_blocks(pb);
         CANS_TRY(alloc(pl, &pb.partials, 3 * (size_t)pb.nres_blocks));
+        CANS_TRY(alloc(pl, &pb.sums, 3 * 256));
     }
     std::vector<double> info(I_SIZE, 0.0);
     CANS_TRY(upload(pl, &pb.d_info, info.data(), I_SIZE));

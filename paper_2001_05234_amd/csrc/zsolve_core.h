@@ -269,16 +269,23 @@ CANS_HD void zp_shift(ZLane<MMAX> &L, ZSeg sg, double m)
         if (t < sg.m) L.f[t] -= m;
 }
 
-// step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F
+// step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F.
+// The top-down sweep (level i) and the bottom-up sweep (level MMAX-1-i, live
+// once it is below m) run in one unrolled loop: two independent dependency
+// chains for the scheduler to interleave.
 template <int MMAX>
 CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
 {
-    double cp = 0, d = 0, g = 0;
+    // the pinned row of the singular lane carries rhs 0
 #pragma unroll
-    for (int t = 0; t < MMAX; ++t) {
+    for (int t = 0; t < MMAX; ++t)
+        if (t < sg.m && L.sing && sg.k0 + t == a.nz - 1) L.f[t] = 0.0;
+    double cp = 0, d = 0, g = 0;    // top-down: c', d', fill-in of xL
+    double ep = 0, dd = 0, h = 0;   // bottom-up: a'', d'', fill-in of xR
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) {
+        const int t = i;
         if (t < sg.m) {
-            // the pinned row of the singular lane carries rhs 0
-            if (L.sing && sg.k0 + t == a.nz - 1) L.f[t] = 0.0;
             double ak, bk, ck;
             zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
             const double rr = rcp64(t == 0 ? bk : bk - ak * cp);
@@ -287,26 +294,23 @@ CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
             g = (t == 0 ? ak : -ak * g) * rr;
             cp = ck * rr;
         }
-    }
-    out[2] = g;   // C
-    out[4] = cp;  // E
-    out[5] = d;   // F
-    double ep = 0, dd = 0, h = 0;
-#pragma unroll
-    for (int t = MMAX - 1; t >= 0; --t) {
-        if (t < sg.m) {
+        const int u = MMAX - 1 - i;
+        if (u < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
-            const bool last = (t == sg.m - 1);
+            zrow(a, sg.k0 + u, L.lam, L.sing, ak, bk, ck);
+            const bool last = (u == sg.m - 1);
             const double rr = rcp64(last ? bk : bk - ck * ep);
-            dd = (last ? L.f[t] : L.f[t] - ck * dd) * rr;
+            dd = (last ? L.f[u] : L.f[u] - ck * dd) * rr;
             h = (last ? ck : -ck * h) * rr;
             ep = ak * rr;
         }
     }
     out[0] = ep;  // A
     out[1] = h;   // B
+    out[2] = g;   // C
     out[3] = dd;  // D
+    out[4] = cp;  // E
+    out[5] = d;   // F
 }
 
 // step 2: the reduced system of one column over its S segments.
