@@ -339,49 +339,53 @@ __global__ __launch_bounds__(256) void k_zsolve(T *data, ZArgs a, const int *__r
 
 static ZArgs zargs(const Problem &pb, double *removed);
 
-// Partitioned column solve: 64 columns per block (lane = column), one z
-// segment per wave, everything in registers and LDS (see zsolve_core.h).
-template <typename T, int MMAX, int NTMAX>
+// Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
+// into S segments of at most MMAX levels held in registers; a wave holds
+// 64/CPB segments of the same columns (see zsolve_core.h).
+template <typename T, int MMAX, int CPB, int NTMAX>
 __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs a, const int *__restrict__ done)
 {
     if (done && *done) return;
-    __shared__ double coef[6][16][64];
-    __shared__ double red[16];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, S = blockDim.x >> 6;
-    const size_t col = (size_t)blockIdx.x * 64 + lane;
-    const ZSeg sg = zseg(a.nz, S, w);
+    __shared__ double coef[6 * 1024];
+    __shared__ double red[32];
+    constexpr int SPW = 64 / CPB;  // segments per wave
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = lane % CPB, seg = w * SPW + lane / CPB;
+    const int S = (int)(blockDim.x >> 6) * SPW;
+    auto C = [&](int q, int s) -> double & { return coef[q * 1024 + s * CPB + c]; };
+    const size_t col = (size_t)blockIdx.x * CPB + c;
+    const ZSeg sg = zseg(a.nz, S, seg);
     ZLane<MMAX> L;
     zp_load(L, data, a, col, sg);
     const bool sblock = a.singular && blockIdx.x == 0;
     if (sblock) {  // project the singular column on the range of its operator
         const double s = L.sing ? zp_wsum(L, a, sg) : 0.0;
-        if (lane == 0) red[w] = s;
+        if (c == 0) red[seg] = s;
         __syncthreads();
         double tot = 0;
         for (int q = 0; q < S; ++q) tot += red[q];
         const double m = tot / a.wsum;
         if (L.sing) zp_shift(L, sg, m);
-        if (L.sing && w == 0 && a.removed) *a.removed = m;
+        if (L.sing && seg == 0 && a.removed) *a.removed = m;
         __syncthreads();
     }
     double out[6];
     zp_reduce(L, a, sg, out);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) coef[q][w][lane] = out[q];
+    for (int q = 0; q < 6; ++q) C(q, seg) = out[q];
     __syncthreads();
-    if (w == 0) {
+    if (w == 0 && lane < CPB) {
         zp_interface(
-            S, [&](int s, int q) -> double & { return coef[q][s][lane]; },
-            [&](int s) -> double & { return coef[4][s][lane]; },
-            [&](int s) -> double & { return coef[5][s][lane]; });
+            S, [&](int s, int q) -> double & { return C(q, s); }, [&](int s) -> double & { return C(4, s); },
+            [&](int s) -> double & { return C(5, s); });
     }
     __syncthreads();
-    const double xL = w > 0 ? coef[5][w - 1][lane] : 0.0;
-    const double xR = w < S - 1 ? coef[4][w + 1][lane] : 0.0;
+    const double xL = seg > 0 ? C(5, seg - 1) : 0.0;
+    const double xR = seg < S - 1 ? C(4, seg + 1) : 0.0;
     zp_finish(L, a, sg, xL, xR);
     if (sblock) {  // zero weighted mean of the singular column
         const double s = L.sing ? zp_wsum(L, a, sg) : 0.0;
-        if (lane == 0) red[w] = s;
+        if (c == 0) red[seg] = s;
         __syncthreads();
         double tot = 0;
         for (int q = 0; q < S; ++q) tot += red[q];
@@ -394,22 +398,21 @@ template <typename T>
 static int launch_zsolve(const Problem &pb, T *data, double *removed, const int *done, hipStream_t s)
 {
     const size_t plane = (size_t)pb.nx * pb.ny;
-    const int mm = pb.cyclic ? 0 : zpart_mmax(pb.nz);
+    const ZPart zp = pb.cyclic ? ZPart{0, 0, 0} : zpart_shape(pb.nz);
     ZArgs za = zargs(pb, removed);
-    if (mm == 0) {
+    if (zp.mmax == 0) {
         hipLaunchKernelGGL(k_zsolve<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data, za, done);
         return check_launch();
     }
-    const int S = (pb.nz + mm - 1) / mm;
-    const dim3 grid((unsigned)((plane + 63) / 64)), block(64 * S);
-    switch (mm) {
-    case 8: hipLaunchKernelGGL((k_zsolve_part<T, 8, 1024>), grid, block, 0, s, data, za, done); break;
-    case 16: hipLaunchKernelGGL((k_zsolve_part<T, 16, 1024>), grid, block, 0, s, data, za, done); break;
-    default: hipLaunchKernelGGL((k_zsolve_part<T, 24, 1024>), grid, block, 0, s, data, za, done); break;
-    }
+    const dim3 grid((unsigned)((plane + zp.cpb - 1) / zp.cpb)), block(zp.threads);
+    if (zp.mmax == 8)
+        hipLaunchKernelGGL((k_zsolve_part<T, 8, 64, 1024>), grid, block, 0, s, data, za, done);
+    else if (zp.cpb == 64)
+        hipLaunchKernelGGL((k_zsolve_part<T, 16, 64, 1024>), grid, block, 0, s, data, za, done);
+    else
+        hipLaunchKernelGGL((k_zsolve_part<T, 16, 32, 1024>), grid, block, 0, s, data, za, done);
     return check_launch();
 }
-
 
 // ---------------------------------------------------------------------------
 // Dense (matrix-core) x transforms of the refinement path: the same prologues

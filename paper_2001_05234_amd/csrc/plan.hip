@@ -157,7 +157,7 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     // workspace of the plain elimination (periodic z, or nz beyond the
     // register-resident partitioned solve): multipliers and modified rhs
     const size_t N = pb.npts();
-    if (pb.cyclic || zpart_mmax(nz) == 0) {
+    if (pb.cyclic || zpart_shape(nz).mmax == 0) {
         CANS_TRY(alloc(pl, &pb.wc, N));
         CANS_TRY(alloc(pl, &pb.wd, N));
         if (pb.cyclic) CANS_TRY(alloc(pl, &pb.wz, N));

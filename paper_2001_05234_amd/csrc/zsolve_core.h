@@ -376,15 +376,28 @@ CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col,
         if (t < sg.m) data[col + plane * (sg.k0 + t)] = (T)L.f[t];
 }
 
-// register depth per lane for nz: up to 16 segments (one wave each, 1024
-// threads) of at most 8, 16 or 24 levels; 0 when nz > 384 (the plain
-// elimination with a workspace is used then, and for periodic z)
-inline int zpart_mmax(int nz)
+// Shape of the partitioned solve for nz: register depth per lane, columns
+// per block and threads per block (segments = threads/64 * 64/cpb).
+//   nz <= 128: 64 columns, segments of <= 8 levels;
+//   nz <= 256: 64 columns, segments of <= 16 levels;
+//   nz <= 512: 32 columns (two segments per wave), segments of <= 16 levels.
+// mmax = 0 when nz > 512 (the plain elimination with a workspace is used
+// then, and for periodic z).
+struct ZPart {
+    int mmax, cpb, threads;
+};
+
+inline ZPart zpart_shape(int nz)
 {
-    if (nz <= 128) return 8;
-    if (nz <= 256) return 16;
-    if (nz <= 384) return 24;
-    return 0;
+    if (nz <= 128) return ZPart{8, 64, 64 * ((nz + 7) / 8)};
+    if (nz <= 256) return ZPart{16, 64, 64 * ((nz + 15) / 16)};
+    if (nz <= 512) {
+        const int segs = (nz + 15) / 16;          // <= 32, two per wave
+        return ZPart{16, 32, 64 * ((segs + 1) / 2)};
+    }
+    return ZPart{0, 0, 0};
 }
+
+inline int zpart_mmax(int nz) { return zpart_shape(nz).mmax; }
 
 }  // namespace cans

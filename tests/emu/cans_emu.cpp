@@ -138,19 +138,16 @@ int setup(Setup &s, int nx, int ny, int nz, const int *bc, double dx, double dy,
     return 0;
 }
 
-template <int MMAX, typename T>
-void zsolve_part_mm(Setup &s, T *data, double *removed);
+template <typename T>
+bool zsolve_part_any(Setup &s, T *data, double *removed);
 
 // the z solve the GPU runs for this problem
 template <typename T>
 void zsolve_any(Setup &s, T *data, double *removed)
 {
-    const int mm = s.z.cyclic ? 0 : zpart_mmax(s.nz);
     s.z.removed = removed;
-    if (mm == 8) zsolve_part_mm<8>(s, data, removed);
-    else if (mm == 16) zsolve_part_mm<16>(s, data, removed);
-    else if (mm == 24) zsolve_part_mm<24>(s, data, removed);
-    else for (size_t col = 0; col < (size_t)s.nx * s.ny; ++col) zsolve_column(col, data, s.z);
+    if (!zsolve_part_any(s, data, removed))
+        for (size_t col = 0; col < (size_t)s.nx * s.ny; ++col) zsolve_column(col, data, s.z);
 }
 
 template <typename T>
@@ -163,49 +160,62 @@ void solve_pass(Setup &s, std::vector<T> &a, double *removed)
     xform<T>(s.kx, false, 0, s.nx, s.ny, s.nz, a);
 }
 
-// the partitioned z kernel, phase by phase over all waves and lanes of a block
+// the partitioned z kernel, phase by phase over all segments and columns of a
+// block (CPB columns, S segments)
 template <int MMAX, typename T>
-void zsolve_part_mm(Setup &s, T *data, double *removed)
+void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
 {
     const ZArgs &a = s.z;
     const size_t plane = (size_t)s.nx * s.ny;
-    const int S = (s.nz + MMAX - 1) / MMAX;
-    std::vector<ZLane<MMAX>> L(S * 64);
-    std::vector<double> coef(6 * 16 * 64);
-    auto C = [&](int q, int seg, int lane) -> double & { return coef[(q * 16 + seg) * 64 + lane]; };
-    for (size_t blk = 0; blk * 64 < plane; ++blk) {
+    std::vector<ZLane<MMAX>> L((size_t)S * cpb);
+    std::vector<double> coef(6 * 1024);
+    auto C = [&](int q, int seg, int c) -> double & { return coef[q * 1024 + seg * cpb + c]; };
+    auto lane = [&](int seg, int c) -> ZLane<MMAX> & { return L[(size_t)seg * cpb + c]; };
+    for (size_t blk = 0; blk * cpb < plane; ++blk) {
         const bool sblock = a.singular && blk == 0;
         for (int w = 0; w < S; ++w)
-            for (int ln = 0; ln < 64; ++ln) zp_load(L[w * 64 + ln], data, a, blk * 64 + ln, zseg(s.nz, S, w));
+            for (int c = 0; c < cpb; ++c) zp_load(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
         if (sblock) {
             double tot = 0;
-            for (int w = 0; w < S; ++w) tot += zp_wsum(L[w * 64], a, zseg(s.nz, S, w));
-            for (int w = 0; w < S; ++w) zp_shift(L[w * 64], zseg(s.nz, S, w), tot / a.wsum);
+            for (int w = 0; w < S; ++w) tot += zp_wsum(lane(w, 0), a, zseg(s.nz, S, w));
+            for (int w = 0; w < S; ++w) zp_shift(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
             if (removed) *removed = tot / a.wsum;
         }
         for (int w = 0; w < S; ++w)
-            for (int ln = 0; ln < 64; ++ln) {
+            for (int c = 0; c < cpb; ++c) {
                 double out[6];
-                zp_reduce(L[w * 64 + ln], a, zseg(s.nz, S, w), out);
-                for (int q = 0; q < 6; ++q) C(q, w, ln) = out[q];
+                zp_reduce(lane(w, c), a, zseg(s.nz, S, w), out);
+                for (int q = 0; q < 6; ++q) C(q, w, c) = out[q];
             }
-        for (int ln = 0; ln < 64; ++ln)
+        for (int c = 0; c < cpb; ++c)
             zp_interface(
-                S, [&](int sg, int q) -> double & { return C(q, sg, ln); },
-                [&](int sg) -> double & { return C(4, sg, ln); }, [&](int sg) -> double & { return C(5, sg, ln); });
+                S, [&](int sg, int q) -> double & { return C(q, sg, c); },
+                [&](int sg) -> double & { return C(4, sg, c); }, [&](int sg) -> double & { return C(5, sg, c); });
         for (int w = 0; w < S; ++w)
-            for (int ln = 0; ln < 64; ++ln) {
-                const double xL = w > 0 ? C(5, w - 1, ln) : 0.0, xR = w < S - 1 ? C(4, w + 1, ln) : 0.0;
-                zp_finish(L[w * 64 + ln], a, zseg(s.nz, S, w), xL, xR);
+            for (int c = 0; c < cpb; ++c) {
+                const double xL = w > 0 ? C(5, w - 1, c) : 0.0, xR = w < S - 1 ? C(4, w + 1, c) : 0.0;
+                zp_finish(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
             }
         if (sblock) {
             double tot = 0;
-            for (int w = 0; w < S; ++w) tot += zp_wsum(L[w * 64], a, zseg(s.nz, S, w));
-            for (int w = 0; w < S; ++w) zp_shift(L[w * 64], zseg(s.nz, S, w), tot / a.wsum);
+            for (int w = 0; w < S; ++w) tot += zp_wsum(lane(w, 0), a, zseg(s.nz, S, w));
+            for (int w = 0; w < S; ++w) zp_shift(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
         }
         for (int w = 0; w < S; ++w)
-            for (int ln = 0; ln < 64; ++ln) zp_store(L[w * 64 + ln], data, a, blk * 64 + ln, zseg(s.nz, S, w));
+            for (int c = 0; c < cpb; ++c) zp_store(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
     }
+}
+
+// the kernel shape the GPU launches for this nz; false when it does not apply
+template <typename T>
+bool zsolve_part_any(Setup &s, T *data, double *removed)
+{
+    const ZPart zp = s.z.cyclic ? ZPart{0, 0, 0} : zpart_shape(s.nz);
+    if (zp.mmax == 0) return false;
+    const int S = (zp.threads / 64) * (64 / zp.cpb);
+    if (zp.mmax == 8) zsolve_part_mm<8>(s, data, removed, zp.cpb, S);
+    else zsolve_part_mm<16>(s, data, removed, zp.cpb, S);
+    return true;
 }
 
 }  // namespace
@@ -219,15 +229,8 @@ int emu_zsolve_part(int nx, int ny, int nz, const int *bc, double dx, double dy,
 {
     Setup s;
     if (setup(s, nx, ny, nz, bc, dx, dy, dz)) return -1;
-    const int mm = s.z.cyclic ? 0 : zpart_mmax(nz);
-    switch (mm) {
-    case 8: zsolve_part_mm<8>(s, data, removed); return 0;
-    case 16: zsolve_part_mm<16>(s, data, removed); return 0;
-    case 24: zsolve_part_mm<24>(s, data, removed); return 0;
-    default: return -2;
-    }
+    return zsolve_part_any(s, data, removed) ? 0 : -2;
 }
-
 
 // One transform along axis 0 (x) or 1 (y), FP64 (prec 64) or FP32 (prec 32).
 int emu_xform(int kind, int fwd, int axis, int prec, int nx, int ny, int nz, const double *in, double *out)

@@ -74,7 +74,7 @@ def test_zsolve_stage():
         assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
 
 
-@pytest.mark.parametrize("nz", [1, 2, 5, 8, 9, 17, 31, 64, 96, 100, 256, 384])
+@pytest.mark.parametrize("nz", [1, 2, 5, 8, 9, 17, 31, 64, 96, 100, 129, 256, 257, 300, 384, 512])
 def test_zsolve_partitioned(nz):
     """Register-resident partitioned z solve (segments per wave, reduced
     interface system) against the oracle's column solves, including the
@@ -95,7 +95,7 @@ def test_zsolve_partitioned(nz):
             phl, _ = O.spectral_solve(fh, bc, 0.3, 0.5, dzf, ld=True)
             assert rel(pe * s, phl) < 2 * rel(ph, phl), (nz, bc, e)
         assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
-    # periodic z and nz > 384 use the plain elimination
+    # periodic z (and nz > 512) use the plain elimination
     assert emu.zsolve_part(fh, (P, P, N, N, P, P), 0.3, 0.5, np.full(nz, 0.1)) is None
 
 
