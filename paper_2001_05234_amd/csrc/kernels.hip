@@ -186,22 +186,37 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
     const double mf = info[I_REMOVED];
     double srr = 0, sff = 0, spw = 0;
     // residual of the tile's lines into LDS (coalesced, each point once)
-    for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
-        const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
-        const long line = line0 + l;
-        float v = 0.f;
-        if (line < nlines) {
-            const int k = line_level(line, line0, k0, j0, ny);
-            const int j = (int)(line - (long)k * ny);
-            const size_t gi = (size_t)line * n + e;
-            const double fv = f[gi] - mf;
-            const double r = fv - lap_point(p, e, j, k, la);
-            srr += r * r;
-            sff += fv * fv;
-            spw += dzf[k] * p[gi];
-            v = (float)r;
+    auto one = [&](int e, int l, long line, int j, int k) {
+        const size_t gi = (size_t)line * n + e;
+        const double fv = f[gi] - mf;
+        const double r = fv - lap_point(p, e, j, k, la);
+        srr += r * r;
+        sff += fv * fv;
+        spw += dzf[k] * p[gi];
+        tile_real(tile, e, l) = (float)r;
+    };
+    if (n % kThreads == 0) {
+        // whole lines per thread group: line, j and k are uniform per pass
+        for (int l = 0; l < g.L; ++l) {
+            const long line = line0 + l;
+            if (line < nlines) {
+                const int k = line_level(line, line0, k0, j0, ny), j = (int)(line - (long)k * ny);
+                for (int e = threadIdx.x; e < n; e += kThreads) one(e, l, line, j, k);
+            } else {
+                for (int e = threadIdx.x; e < n; e += kThreads) tile_real(tile, e, l) = 0.f;
+            }
         }
-        tile_real(tile, e, l) = v;
+    } else {
+        for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
+            const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
+            const long line = line0 + l;
+            if (line < nlines) {
+                const int k = line_level(line, line0, k0, j0, ny), j = (int)(line - (long)k * ny);
+                one(e, l, line, j, k);
+            } else {
+                tile_real(tile, e, l) = 0.f;
+            }
+        }
     }
     __syncthreads();
     auto src = [&](int e, int l) -> float { return tile_real(tile, e, l); };

@@ -162,6 +162,13 @@ CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
 {
     const size_t sx = 1, sy = (size_t)a.nx, sz = (size_t)a.nx * a.ny;
     const size_t e = i + sy * j + sz * k;
+    if (i > 0 && i < a.nx - 1 && j > 0 && j < a.ny - 1 && k > 0 && k < a.nz - 1) {
+        // interior: no ghost cells
+        const double *q = p + e;
+        const double c = q[0];
+        return (q[-1] - 2.0 * c + q[1]) * a.idx2 + (q[-(long)sy] - 2.0 * c + q[sy]) * a.idy2
+             + a.zcf[k] * (q[sz] - c) - a.zaf[k] * (c - q[-(long)sz]);
+    }
     const double c = p[e];
     const double xm = i > 0 ? p[e - sx] : ghost(a.bc[0], c, p[e + (a.nx - 1) * sx]);
     const double xp = i < a.nx - 1 ? p[e + sx] : ghost(a.bc[1], c, p[e - (a.nx - 1) * sx]);
@@ -226,7 +233,9 @@ CANS_HD void zrow(const ZArgs &a, int k, double lam, bool sing, double &ak, doub
     ak = a.za[k];
     bk = a.zb[k] + lam;
     ck = a.zc[k];
-    if (sing && k == a.nz - 1) { ak = 0.0; bk = 1.0; ck = 0.0; }
+    if (k == a.nz - 1) {  // uniform across a segment: only the last level pays
+        if (sing) { ak = 0.0; bk = 1.0; ck = 0.0; }
+    }
 }
 
 template <int MMAX>
@@ -245,9 +254,12 @@ CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, 
     L.valid = col < plane;
     L.sing = a.singular && col == 0;
     L.lam = L.valid ? a.lamx[col % a.nx] + a.lamy[col / a.nx] : -1.0;
+    const T *ptr = data + (L.valid ? col : 0) + plane * sg.k0;
 #pragma unroll
-    for (int t = 0; t < MMAX; ++t)
-        if (t < sg.m) L.f[t] = L.valid ? a.scale * (double)data[col + plane * (sg.k0 + t)] : 0.0;
+    for (int t = 0; t < MMAX; ++t) {
+        if (t < sg.m) L.f[t] = L.valid ? a.scale * (double)ptr[0] : 0.0;
+        ptr += plane;
+    }
 }
 
 // weighted partial sum of this segment (singular lane only)
@@ -371,9 +383,12 @@ CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col,
 {
     if (!L.valid) return;
     const size_t plane = (size_t)a.nx * a.ny;
+    T *ptr = data + col + plane * sg.k0;
 #pragma unroll
-    for (int t = 0; t < MMAX; ++t)
-        if (t < sg.m) data[col + plane * (sg.k0 + t)] = (T)L.f[t];
+    for (int t = 0; t < MMAX; ++t) {
+        if (t < sg.m) ptr[0] = (T)L.f[t];
+        ptr += plane;
+    }
 }
 
 // Shape of the partitioned solve for nz: register depth per lane, columns
