@@ -104,7 +104,7 @@ def bench_batched(torch, capi, inputs, args):
     probs = inputs.batch_c5()
     fs = [torch.from_numpy(pr.rhs()).cuda() for pr in probs]
     ps = [torch.zeros_like(f) for f in fs]
-    plan = capi.BatchedPlan(probs, precision="fp32_refine", tol=1e-10, max_iter=4)
+    plan = capi.BatchedPlan(probs, precision="fp32_refine", tol=1e-10, max_iter=4, autotune=not args.no_autotune)
     for _ in range(3):
         plan.solve(fs, ps)
     torch.cuda.synchronize()
@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--cpu-sample-levels", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="built-in tile choice instead of plan-time tuning")
     ap.add_argument("--solve-only", action="store_true", help="time the refine solve only (profiling runs)")
     ap.add_argument("--fp64-only", action="store_true", help="time the FP64 solve only (profiling runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -183,13 +184,14 @@ def main():
     npts = pr.npts
 
     if args.fp64_only:
-        plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64")
+        plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
+                           autotune=not args.no_autotune)
         ms64, _ = time_solves(plan64, fd, pd, args.steps, args.warmup, torch)
         print(json.dumps({"fp64_ms_per_step": ms64, "value": npts / (ms64 * 1e-3)}), flush=True)
         return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
-                     tol=1e-10, max_iter=4)
+                     tol=1e-10, max_iter=4, autotune=not args.no_autotune)
     ms, wall = time_solves(plan, fd, pd, args.steps, args.warmup, torch)
     info = plan.info()
     say(f"[bench] refine: {ms:.3f} ms/solve, info {info}")
@@ -235,7 +237,8 @@ def main():
 
     # plain FP64 solve of the same rhs
     say("[bench] fp64 plan")
-    plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64")
+    plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
+                       autotune=not args.no_autotune)
     ms64, _ = time_solves(plan64, fd, pd, max(1, args.steps // 2), 2, torch)
     k64 = {}
     b = torch.zeros_like(fd)

@@ -76,6 +76,12 @@ typedef struct cans_opts {
                            ||Pi f - L p||_2 / ||Pi f||_2 <= tol; default 1e-10 */
     int max_iter;       /* FP32_REFINE: most refinement steps enqueued per
                            solve (0..16); default 4 */
+    int autotune;       /* 1: at plan time, time candidate transform tiles
+                           (lines per tile, radix-8 or radix-4 first) for
+                           every transform kernel the plan uses on the
+                           current device and keep the fastest (allocates a
+                           temporary field and synchronises); 0: built-in
+                           choice.  Default 0. */
 } cans_opts;
 
 #define CANS_HISTORY 17

@@ -34,7 +34,7 @@ EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "ca
 
 class CansOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("xform_x", ctypes.c_int), ("xform_y", ctypes.c_int),
-                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class CansInfo(ctypes.Structure):
@@ -132,7 +132,8 @@ class Plan:
     ``cans_poisson_solve`` on a stream without host synchronisation."""
 
     def __init__(self, nx: int, ny: int, nz: int, bc, dx: float, dy: float, dzf,
-                 precision: str = "fp64", tol: float = 1e-10, max_iter: int = 4, xform_x: str = "auto"):
+                 precision: str = "fp64", tol: float = 1e-10, max_iter: int = 4, xform_x: str = "auto",
+                 autotune: bool = False):
         lib = load()
         self._lib = lib
         self.shape = (nz, ny, nx)
@@ -142,6 +143,7 @@ class Plan:
         o.tol = tol
         o.max_iter = max_iter
         o.xform_x = {"auto": XFORM_AUTO, "fft": XFORM_FFT, "dense": XFORM_DENSE}[xform_x]
+        o.autotune = int(bool(autotune))
         dz = np.ascontiguousarray(np.asarray(dzf, dtype=np.float64))
         if dz.shape != (nz,):
             raise ValueError("dzf must hold nz cell widths")
@@ -183,13 +185,15 @@ class Plan:
 class BatchedPlan:
     """Many independent problems in one plan (``cans_poisson_plan_batched``)."""
 
-    def __init__(self, problems, precision: str = "fp32_refine", tol: float = 1e-10, max_iter: int = 4):
+    def __init__(self, problems, precision: str = "fp32_refine", tol: float = 1e-10, max_iter: int = 4,
+                 autotune: bool = False):
         lib = load()
         self._lib = lib
         o = default_opts()
         o.precision = PREC_FP64 if precision == "fp64" else PREC_FP32_REFINE
         o.tol = tol
         o.max_iter = max_iter
+        o.autotune = int(bool(autotune))
         self._dz = []
         descs = (CansDesc * len(problems))()
         for d, pr in zip(descs, problems):

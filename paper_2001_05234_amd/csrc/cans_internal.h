@@ -27,8 +27,9 @@ struct Axis {
     int n = 0;
     double h = 1;
     int s = 1;                 // B T = s I
-    XGeom gx64{}, gx32{};      // tile geometry as an x transform (FP64 / FP32)
-    XGeom gy64{}, gy32{};      // tile geometry as a y transform
+    // tile geometry as an x or a y transform, FP64 / FP32, [0] inverse [1] forward
+    XGeom gx64[2]{}, gx32[2]{};
+    XGeom gy64[2]{}, gy32[2]{};
     double *d_lam = nullptr;   // mu(q)/h^2 in the transform's row order
     cx<double> *d_tw64 = nullptr;
     cx<float> *d_tw32 = nullptr;

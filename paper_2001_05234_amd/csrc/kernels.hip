@@ -526,7 +526,7 @@ static size_t tile_lds(int axis, const XGeom &g, size_t elem) { return (size_t)t
 
 int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s)
 {
-    const XGeom &g = pb.ax.gx64;
+    const XGeom &g = pb.ax.gx64[fwd ? 1 : 0];
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
     const size_t sh = tile_lds(AX_X, g, sizeof(double));
@@ -540,7 +540,7 @@ int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hip
 
 int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s)
 {
-    const XGeom &g = pb.ay.gy64;
+    const XGeom &g = pb.ay.gy64[fwd ? 1 : 0];
     const int ntx = (pb.nx + g.L - 1) / g.L;
     const dim3 grid((unsigned)(ntx * pb.nz));
     const size_t sh = tile_lds(AX_Y, g, sizeof(double));
@@ -560,7 +560,7 @@ int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *
                            pb.d_dzf, pb.ny, pb.partials);
         return check_launch();
     }
-    const XGeom &g = pb.ax.gx32;
+    const XGeom &g = pb.ax.gx32[1];
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
@@ -572,7 +572,7 @@ int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *
 
 int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipStream_t s)
 {
-    const XGeom &g = pb.ay.gy32;
+    const XGeom &g = pb.ay.gy32[fwd ? 1 : 0];
     const int ntx = (pb.nx + g.L - 1) / g.L;
     const dim3 grid((unsigned)(ntx * pb.nz));
     const size_t sh = tile_lds(AX_Y, g, sizeof(float));
@@ -598,7 +598,7 @@ int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, 
                                pb.d_info, done, nullptr, pb.ny, nullptr);
         return check_launch();
     }
-    const XGeom &g = pb.ax.gx32;
+    const XGeom &g = pb.ax.gx32[0];
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
@@ -647,7 +647,7 @@ static LapArgs lapargs(const Problem &pb)
 int resid_blocks(const Problem &pb)
 {
     const long nlines = (long)pb.ny * pb.nz;
-    const int L = pb.ax.dense ? kDenseLines : pb.ax.gx32.L;
+    const int L = pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L;
     return (int)((nlines + L - 1) / L);
 }
 
@@ -660,7 +660,7 @@ int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float
                            pb.d_dzf, pb.d_info, pb.partials, done);
         return check_launch();
     }
-    const XGeom &g = pb.ax.gx32;
+    const XGeom &g = pb.ax.gx32[1];
     const long nlines = (long)pb.ny * pb.nz;
     const dim3 grid((unsigned)resid_blocks(pb));
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
@@ -674,7 +674,7 @@ int launch_resid_norm(const Problem &pb, const double *f, const double *p, const
 {
     const long nlines = (long)pb.ny * pb.nz;
     hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)resid_blocks(pb)), dim3(kThreads), 0, s, f, p, nlines,
-                       pb.ax.dense ? kDenseLines : pb.ax.gx32.L, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done);
+                       pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done);
     return check_launch();
 }
 

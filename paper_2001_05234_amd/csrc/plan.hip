@@ -91,9 +91,10 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
     a.n = n;
     a.h = h;
     a.s = xform_scale(kind, n);
-    if (!make_geom(a.gx64, AX_X, n, 8) || !make_geom(a.gx32, AX_X, n, 4) || !make_geom(a.gy64, AX_Y, n, 8) ||
-        !make_geom(a.gy32, AX_Y, n, 4))
-        return CANS_ERR_UNSUPPORTED;
+    for (int d = 0; d < 2; ++d)
+        if (!make_geom(a.gx64[d], AX_X, n, 8) || !make_geom(a.gx32[d], AX_X, n, 4) ||
+            !make_geom(a.gy64[d], AX_Y, n, 8) || !make_geom(a.gy32[d], AX_Y, n, 4))
+            return CANS_ERR_UNSUPPORTED;
     std::vector<cx<double>> t64 = twiddles(n);
     std::vector<cx<float>> t32(t64.size());
     for (size_t i = 0; i < t64.size(); ++i) t32[i] = mk((float)t64[i].re, (float)t64[i].im);
@@ -130,6 +131,75 @@ int build_dense(cans_plan_s *pl, Axis &a)
     return CANS_OK;
 }
 
+// Plan-time tuning of the transform tiles: for every transform kernel the
+// plan uses (x/y, forward/inverse, its precision), time the default tile and
+// the candidates with a quarter .. four times the lines per tile, each with
+// radix-8-first and radix-4-first plans, on a scratch field; keep the fastest.
+int autotune(cans_plan_s *pl, Problem &pb)
+{
+    (void)pl;
+    const size_t N = pb.npts();
+    double *s64 = nullptr;
+    if (hipMalloc(&s64, N * sizeof(double)) != hipSuccess) return CANS_ERR_ALLOC;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = CANS_OK;
+    if (hipMemset(s64, 0, N * sizeof(double)) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = CANS_ERR_HIP;
+    if (rc == CANS_OK && pb.a32 && hipMemset(pb.a32, 0, N * sizeof(float)) != hipSuccess) rc = CANS_ERR_HIP;
+    auto timeit = [&](auto launch) -> float {
+        if (launch() != CANS_OK || launch() != CANS_OK) return 1e30f;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < 3; ++r)
+            if (launch() != CANS_OK) return 1e30f;
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) return 1e30f;
+        float ms = 1e30f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    auto tune = [&](XGeom &slot, int axis, int n, int elem, auto launch) {
+        XGeom best = slot;
+        float tbest = timeit(launch);
+        const int L0 = slot.L;
+        for (int L : {L0 / 4, L0 / 2, L0, L0 * 2, L0 * 4})
+            for (int rmax : {8, 4}) {
+                XGeom g;
+                if (L < 1 || (L == L0 && rmax == 8) || !make_geom(g, axis, n, elem, L, rmax)) continue;
+                slot = g;
+                const float t = timeit(launch);
+                if (t < tbest) {
+                    tbest = t;
+                    best = g;
+                }
+            }
+        slot = best;
+    };
+    if (rc == CANS_OK) {
+        if (pl->opts.precision == CANS_PREC_FP64) {
+            tune(pb.ax.gx64[1], AX_X, pb.nx, 8, [&] { return launch_x_f64(pb, true, s64, s64, st); });
+            tune(pb.ax.gx64[0], AX_X, pb.nx, 8, [&] { return launch_x_f64(pb, false, s64, s64, st); });
+            tune(pb.ay.gy64[1], AX_Y, pb.ny, 8, [&] { return launch_y_f64(pb, true, s64, s64, st); });
+            tune(pb.ay.gy64[0], AX_Y, pb.ny, 8, [&] { return launch_y_f64(pb, false, s64, s64, st); });
+        } else {
+            if (!pb.ax.dense) {
+                tune(pb.ax.gx32[1], AX_X, pb.nx, 4, [&] { return launch_x_fwd_32(pb, s64, pb.a32, nullptr, st); });
+                tune(pb.ax.gx32[0], AX_X, pb.nx, 4,
+                     [&] { return launch_x_inv_32(pb, pb.a32, s64, false, nullptr, st); });
+            }
+            tune(pb.ay.gy32[1], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, true, pb.a32, nullptr, st); });
+            tune(pb.ay.gy32[0], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, false, pb.a32, nullptr, st); });
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) rc = CANS_ERR_HIP;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(s64);
+    return rc;
+}
+
 int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const int *bc, double dx, double dy,
                   const double *dz)
 {
@@ -164,10 +234,11 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     }
     if (pl->opts.precision == CANS_PREC_FP32_REFINE) {
         CANS_TRY(alloc(pl, &pb.a32, N));
-        pb.nres_blocks = resid_blocks(pb);
-        CANS_TRY(alloc(pl, &pb.partials, 3 * (size_t)pb.nres_blocks));
+        // block partial sums: enough for any tile shape (one line per block)
+        CANS_TRY(alloc(pl, &pb.partials, 3 * (size_t)pb.ny * pb.nz));
         CANS_TRY(alloc(pl, &pb.sums, 3 * 256));
     }
+    if (pl->opts.autotune) CANS_TRY(autotune(pl, pb));
     std::vector<double> info(I_SIZE, 0.0);
     CANS_TRY(upload(pl, &pb.d_info, info.data(), I_SIZE));
     int zero = 0;
@@ -180,6 +251,7 @@ int check_opts(const cans_opts &o)
     if (o.precision != CANS_PREC_FP64 && o.precision != CANS_PREC_FP32_REFINE) return CANS_ERR_INVALID_ARG;
     if (o.max_iter < 0 || o.max_iter > CANS_HISTORY - 1) return CANS_ERR_INVALID_ARG;
     if (!(o.tol >= 0) || !std::isfinite(o.tol)) return CANS_ERR_INVALID_ARG;
+    if (o.autotune != 0 && o.autotune != 1) return CANS_ERR_INVALID_ARG;
     for (int m : {o.xform_x, o.xform_y})
         if (m != CANS_XFORM_AUTO && m != CANS_XFORM_FFT && m != CANS_XFORM_DENSE) return CANS_ERR_INVALID_ARG;
     // the matrix-core form exists for the x axis of the refinement path
@@ -299,6 +371,7 @@ void cans_default_opts(cans_opts *o)
     o->xform_y = CANS_XFORM_AUTO;
     o->tol = 1e-10;
     o->max_iter = 4;
+    o->autotune = 0;
 }
 
 const char *cans_status_string(int code)

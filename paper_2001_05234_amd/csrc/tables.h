@@ -25,14 +25,16 @@ inline int axis_kind(int lo, int hi)
     return -1;
 }
 
-// Radix plan of an M-point FFT: 8s first, then the remaining power of two,
-// then 3s and 5s.  Returns false if M has another prime factor.
-inline bool factor(int M, XGeom &g)
+// Radix plan of an M-point FFT: radix `rmax` (8 or 4) first, then the
+// remaining power of two, then 3s and 5s.  Returns false if M has another
+// prime factor.
+inline bool factor(int M, XGeom &g, int rmax = 8)
 {
     int r = M, nst = 0;
     int rads[kMaxStages];
-    while (r % 8 == 0 && nst < kMaxStages) { rads[nst++] = 8; r /= 8; }
-    if (r % 4 == 0 && nst < kMaxStages) { rads[nst++] = 4; r /= 4; }
+    if (rmax >= 8)
+        while (r % 8 == 0 && nst < kMaxStages) { rads[nst++] = 8; r /= 8; }
+    while (r % 4 == 0 && nst < kMaxStages) { rads[nst++] = 4; r /= 4; }
     if (r % 2 == 0 && nst < kMaxStages) { rads[nst++] = 2; r /= 2; }
     while (r % 3 == 0 && nst < kMaxStages) { rads[nst++] = 3; r /= 3; }
     while (r % 5 == 0 && nst < kMaxStages) { rads[nst++] = 5; r /= 5; }
@@ -72,27 +74,32 @@ inline int tile_lines(int axis, int n, int elem)
     return std::max(1, std::min(lmax, pow2floor(std::max<long>(1, cap / M))));
 }
 
-inline bool make_geom(XGeom &g, int axis, int n, int elem)
+// bytes of LDS a tile takes
+inline size_t tile_bytes(int axis, const XGeom &g, int elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
+
+// Geometry of an n-point transform tile; L = 0 takes the default lines per
+// tile, rmax the radix preference.  False if the tile does not fit.
+inline bool make_geom(XGeom &g, int axis, int n, int elem, int L = 0, int rmax = 8)
 {
     g = XGeom{};
     g.n = n;
     g.M = n / 2;
-    g.L = tile_lines(axis, n, elem);
+    g.L = L > 0 ? L : tile_lines(axis, n, elem);
+    if (!is_pow2(g.L) || g.L > (axis == AX_X ? 64 : 32)) return false;
     g.lgL = 0;
     while ((1 << g.lgL) < g.L) ++g.lgL;
     g.psh = elem == 8 ? 4 : 5;  // 256-byte LDS rows of 16-byte / 8-byte slots
     g.RS = g.M + ((g.M - 1) >> g.psh) + 1;
     g.magM = mag_of((unsigned)g.M);
     g.magN = mag_of((unsigned)g.n);
-    if (!factor(g.M, g)) return false;
+    if (!factor(g.M, g, rmax)) return false;
+    if (tile_bytes(axis, g, elem) > 65536) return false;
     // every in-place stage must fit the per-thread capacity of a 256-thread block
     for (int st = 0; st < g.nst; ++st)
         if ((long)(g.M / g.rad[st]) * g.L > (long)(kMaxC / g.rad[st]) * 256) return false;
     return true;
 }
 
-// bytes of LDS a tile takes
-inline size_t tile_bytes(int axis, const XGeom &g, int elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
 
 inline long double mu_row(int kind, int n, int q)
 {

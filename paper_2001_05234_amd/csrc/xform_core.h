@@ -452,9 +452,7 @@ CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, con
         stage_any<FFTF, AXIS, INPLACE>(tid, nt, g, 0, packed, nxt, tw, sync);
         Tile<AXIS, T> t = cur; cur = nxt; nxt = t;
     } else {
-        // stage 0 reads global memory: with INPLACE each thread issues the
-        // loads of all its butterflies before computing (more loads in flight)
-        stage_any<FFTF, AXIS, INPLACE>(tid, nt, g, 0, packed, cur, tw, sync);
+        stage_any<FFTF, AXIS, false>(tid, nt, g, 0, packed, cur, tw, sync);
     }
     for (int st = 1; st < g.nst; ++st) {
         auto lds = [&](int m, int l) -> cx<T> { return cur.at(m, l); };

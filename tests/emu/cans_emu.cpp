@@ -74,11 +74,11 @@ std::vector<cx<T>> tw_as(int n)
 }
 
 template <typename T>
-int xform(int kind, bool fwd, int axis, int nx, int ny, int nz, std::vector<T> &a)
+int xform(int kind, bool fwd, int axis, int nx, int ny, int nz, std::vector<T> &a, int L = 0, int rmax = 8)
 {
     const int n = axis == 0 ? nx : ny;
     XGeom g;
-    if (!make_geom(g, axis == 0 ? AX_X : AX_Y, n, sizeof(T))) return -2;
+    if (!make_geom(g, axis == 0 ? AX_X : AX_Y, n, sizeof(T), L, rmax)) return -2;
     std::vector<cx<T>> tw = tw_as<T>(n);
 #define CASE(K)                                                                            \
     case K:                                                                                \
@@ -232,22 +232,30 @@ int emu_zsolve_part(int nx, int ny, int nz, const int *bc, double dx, double dy,
     return zsolve_part_any(s, data, removed) ? 0 : -2;
 }
 
-// One transform along axis 0 (x) or 1 (y), FP64 (prec 64) or FP32 (prec 32).
-int emu_xform(int kind, int fwd, int axis, int prec, int nx, int ny, int nz, const double *in, double *out)
+// One transform along axis 0 (x) or 1 (y), FP64 (prec 64) or FP32 (prec 32),
+// with the tile geometry (L lines, radix preference) the tuner may pick;
+// L = 0 is the built-in choice.  Returns -2 when that geometry is invalid.
+int emu_xform_geom(int kind, int fwd, int axis, int prec, int nx, int ny, int nz, int L, int rmax, const double *in,
+                   double *out)
 {
     const size_t N = (size_t)nx * ny * nz;
     int rc;
     if (prec == 64) {
         std::vector<double> a(in, in + N);
-        rc = xform<double>(kind, fwd != 0, axis, nx, ny, nz, a);
+        rc = xform<double>(kind, fwd != 0, axis, nx, ny, nz, a, L, rmax);
         std::memcpy(out, a.data(), N * sizeof(double));
     } else {
         std::vector<float> a(N);
         for (size_t e = 0; e < N; ++e) a[e] = (float)in[e];
-        rc = xform<float>(kind, fwd != 0, axis, nx, ny, nz, a);
+        rc = xform<float>(kind, fwd != 0, axis, nx, ny, nz, a, L, rmax);
         for (size_t e = 0; e < N; ++e) out[e] = a[e];
     }
     return rc;
+}
+
+int emu_xform(int kind, int fwd, int axis, int prec, int nx, int ny, int nz, const double *in, double *out)
+{
+    return emu_xform_geom(kind, fwd, axis, prec, nx, ny, nz, 0, 8, in, out);
 }
 
 // The column solves on spectral data (in place), as the z kernel does.

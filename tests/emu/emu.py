@@ -37,6 +37,7 @@ def lib():
         i, d = ctypes.c_int, ctypes.c_double
         ip = ctypes.POINTER(ctypes.c_int)
         L.emu_xform.argtypes = [i, i, i, i, i, i, i, dp, dp]
+        L.emu_xform_geom.argtypes = [i, i, i, i, i, i, i, i, i, dp, dp]
         L.emu_zsolve.argtypes = [i, i, i, ip, d, d, dp, dp, dp]
         L.emu_zsolve_part.argtypes = [i, i, i, ip, d, d, dp, dp, dp]
         L.emu_solve.argtypes = [i, i, i, ip, d, d, dp, i, d, dp, dp, dp]
@@ -53,6 +54,18 @@ def xform(field, kind, fwd, axis, prec=64):
     nz, ny, nx = f.shape
     out = np.zeros_like(f)
     rc = lib().emu_xform(kind, int(fwd), axis, prec, nx, ny, nz, _p(f), _p(out))
+    assert rc == 0
+    return out
+
+
+def xform_geom(field, kind, fwd, axis, prec, L, rmax):
+    """As xform with an explicit tile geometry; None if the geometry is invalid."""
+    f = np.ascontiguousarray(field, dtype=np.float64)
+    nz, ny, nx = f.shape
+    out = np.zeros_like(f)
+    rc = lib().emu_xform_geom(kind, int(fwd), axis, prec, nx, ny, nz, L, rmax, _p(f), _p(out))
+    if rc == -2:
+        return None
     assert rc == 0
     return out
 

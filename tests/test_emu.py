@@ -39,6 +39,33 @@ def test_transforms_fp64(shape, kind):
         assert rel(emu.xform(f, kind, True, axis, prec=32), T) < 2e-6
 
 
+@pytest.mark.parametrize("n", [2, 6, 16, 20, 48, 72, 128, 144, 512, 1024])
+def test_transforms_every_tuned_geometry(n):
+    """Every tile geometry the plan-time tuner may choose (lines per tile from
+    a quarter to four times the default, radix-8 or radix-4 first) gives the
+    same transform, along x and y, FP64 and FP32."""
+    rng = np.random.default_rng(n)
+    f = rng.standard_normal((2, 3, n)) if n > 128 else rng.standard_normal((2, 40, n))
+    g = np.ascontiguousarray(np.swapaxes(f, 1, 2))
+    tried = 0
+    for kind in range(5):
+        for fwd in (True, False):
+            ref_x = O.transform(f, 0, kind) if fwd else scale(kind, n) * O.transform(f, 0, kind, inverse=True)
+            ref_y = O.transform(g, 1, kind) if fwd else scale(kind, n) * O.transform(g, 1, kind, inverse=True)
+            for L in (1, 2, 4, 8, 16, 32, 64):
+                for rmax in (8, 4):
+                    for prec, tol in ((64, 1e-13), (32, 3e-6)):
+                        out = emu.xform_geom(f, kind, fwd, 0, prec, L, rmax)
+                        if out is not None:
+                            tried += 1
+                            assert rel(out, ref_x) < tol, (n, kind, fwd, L, rmax, prec)
+                        out = emu.xform_geom(g, kind, fwd, 1, prec, L, rmax)
+                        if out is not None:
+                            tried += 1
+                            assert rel(out, ref_y) < tol, (n, kind, fwd, L, rmax, prec, "y")
+    assert tried > 0
+
+
 @pytest.mark.parametrize("zp", PAIRS)
 @pytest.mark.parametrize("yp", PAIRS)
 @pytest.mark.parametrize("xp", PAIRS)

@@ -38,7 +38,7 @@ def test_c5_batched_refine(c5):
     FP32 transforms + FP64 refinement, one graph launch."""
     probs, rhs = c5
     say("c5 plan", sum(p.npts for p in probs), "points")
-    plan = capi.BatchedPlan(probs, precision="fp32_refine", tol=1e-10, max_iter=4)
+    plan = capi.BatchedPlan(probs, precision="fp32_refine", tol=1e-10, max_iter=4, autotune=True)
     fs = [torch.from_numpy(f).cuda() for f in rhs]
     ps = [torch.zeros_like(f) for f in fs]
     say("c5 solve")

@@ -54,9 +54,10 @@ def demean(p, bc, dzf):
     return p - O.weighted_mean(p, dzf) if O.is_singular(bc) else p
 
 
-def gpu_solve(f, bc, dx, dy, dzf, precision="fp64", tol=1e-10, max_iter=4, inplace=False):
+def gpu_solve(f, bc, dx, dy, dzf, precision="fp64", tol=1e-10, max_iter=4, inplace=False, autotune=False):
     nz, ny, nx = f.shape
-    plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf, precision=precision, tol=tol, max_iter=max_iter)
+    plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf, precision=precision, tol=tol, max_iter=max_iter,
+                     autotune=autotune)
     fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
     if inplace:
         plan.solve(fd, fd)
@@ -277,3 +278,18 @@ def test_c3_full_size():
     assert abs(O.weighted_mean(p64, pr.dzf)) < 1e-13 * scale
     assert abs(O.weighted_mean(p32, pr.dzf)) < 1e-13 * scale
     assert abs(info["removed_mean"]) < 1e-12 and abs(info64["removed_mean"]) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["c2", "c4"])
+def test_autotuned_plans(name):
+    """Plans whose transform tiles were picked by the plan-time tuner give the
+    same results (FP64 and refined)."""
+    pr = inputs.config(name)
+    f = pr.rhs()
+    say("autotune", name)
+    po, _ = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+    pg, _ = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, autotune=True)
+    check_fp64(pg, f, pr.bc, pr.dx, pr.dy, pr.dzf, po)
+    pg, info = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine", autotune=True)
+    assert info["converged"] and info["residual"] <= 1e-10
+    assert rel(demean(pg, pr.bc, pr.dzf), po) < TOL_REF

@@ -73,13 +73,17 @@ def test_plan_validation_spacing():
 
 def test_options_validation():
     o = capi.default_opts()
-    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4
+    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4 and o.autotune == 0
     o.max_iter = 99
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.precision = 7
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.tol = -1.0
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.autotune = 2
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.xform_y = 2
+    assert _plan(128, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -2
 
 
 def test_null_arguments():
