@@ -164,7 +164,8 @@ size_t cans_poisson_workspace_bytes(cans_plan_t plan);
  *   0 clear the refinement state (needed before 6 after a finished solve),
  *   1 in -> field (forward x), 2 / 4 forward / inverse y, 3 z solve,
  *   5 field -> out (inverse x), 6 residual of p = out for rhs = in fused with
- *   the forward x transform, 7 out += inverse x of the field.
+ *   the forward x transform, 7 out += inverse x of the field, 8 residual
+ *   norms of p = out for rhs = in (6 and 8 need state 0 first).
  */
 int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, double *out,
                              hipStream_t stream);

@@ -233,7 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
     }
 }
 
-// Residual norms only (the check after the last correction).
+// Residual norms only (the check after a correction): block partial sums of
+// |r|^2, |f - mean|^2 and sum dzf p over lines_per_block lines.
 __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restrict__ f,
                                                          const double *__restrict__ p, long nlines,
                                                          int lines_per_block, LapArgs la,
@@ -243,21 +244,23 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
                                                          const int *__restrict__ done)
 {
     if (*done) return;
-    const int n = la.nx;
+    const int n = la.nx, ny = la.ny;
     const long line0 = (long)blockIdx.x * lines_per_block;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mf = info[I_REMOVED];
     double srr = 0, sff = 0, spw = 0;
-    for (int e = threadIdx.x; e < n * lines_per_block; e += kThreads) {
-        const int l = e / n, i = e - l * n;
+    for (int l = 0; l < lines_per_block; ++l) {
         const long line = line0 + l;
-        if (line < nlines) {
-            const int j = (int)(line % la.ny), k = (int)(line / la.ny);
-            const size_t idx = (size_t)line * n + i;
-            const double fv = f[idx] - mf;
-            const double r = fv - lap_point(p, i, j, k, la);
+        if (line >= nlines) break;
+        const int k = line_level(line, line0, k0, j0, ny), j = (int)(line - (long)k * ny);
+        const double wk = dzf[k];
+        for (int e = threadIdx.x; e < n; e += kThreads) {
+            const size_t gi = (size_t)line * n + e;
+            const double fv = f[gi] - mf;
+            const double r = fv - lap_point(p, e, j, k, la);
             srr += r * r;
             sff += fv * fv;
-            spw += dzf[k] * p[idx];
+            spw += wk * p[gi];
         }
     }
     block_sum3(srr, sff, spw);

@@ -326,16 +326,20 @@ int solve_refine(const Problem &pb, const cans_opts &o, const double *rhs, doubl
     CANS_TRY(launch_zsolve_32(pb, pb.a32, nullptr, nullptr, s));
     CANS_TRY(launch_y_32(pb, false, pb.a32, nullptr, s));
     CANS_TRY(launch_x_inv_32(pb, pb.a32, p, false, nullptr, s));
-    for (int it = 0; it < o.max_iter; ++it) {
-        CANS_TRY(launch_resid_xfwd(pb, rhs, p, pb.a32, done, s));
-        CANS_TRY(launch_finalize(pb, it, o.max_iter, o.tol, s));
+    // check 0, fused with the forward x transform the first correction needs
+    CANS_TRY(launch_resid_xfwd(pb, rhs, p, pb.a32, done, s));
+    CANS_TRY(launch_finalize(pb, 0, o.max_iter, o.tol, s));
+    for (int it = 1; it <= o.max_iter; ++it) {
         CANS_TRY(launch_y_32(pb, true, pb.a32, done, s));
         CANS_TRY(launch_zsolve_32(pb, pb.a32, nullptr, done, s));
         CANS_TRY(launch_y_32(pb, false, pb.a32, done, s));
         CANS_TRY(launch_x_inv_32(pb, pb.a32, p, true, done, s));
+        // check `it` without a transform; only if it fails is the residual
+        // formed again with its forward x transform for the next correction
+        CANS_TRY(launch_resid_norm(pb, rhs, p, done, s));
+        CANS_TRY(launch_finalize(pb, it, o.max_iter, o.tol, s));
+        if (it < o.max_iter) CANS_TRY(launch_resid_xfwd(pb, rhs, p, pb.a32, done, s));
     }
-    CANS_TRY(launch_resid_norm(pb, rhs, p, done, s));
-    CANS_TRY(launch_finalize(pb, o.max_iter, o.max_iter, o.tol, s));
     return CANS_OK;
 }
 
@@ -531,6 +535,9 @@ int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, doub
             if (!in || !out) return CANS_ERR_INVALID_ARG;
             return launch_resid_xfwd(pb, in, out, pb.a32, pb.d_flag, stream);
         case 7: return out ? launch_x_inv_32(pb, pb.a32, out, true, nullptr, stream) : CANS_ERR_INVALID_ARG;
+        case 8:
+            if (!in || !out) return CANS_ERR_INVALID_ARG;
+            return launch_resid_norm(pb, in, out, pb.d_flag, stream);
         default: return CANS_ERR_INVALID_ARG;
         }
     }
