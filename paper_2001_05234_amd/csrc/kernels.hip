@@ -360,35 +360,48 @@ static ZArgs zargs(const Problem &pb, double *removed);
 // Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
 // into S segments of at most MMAX levels held in registers; a wave holds
 // 64/CPB segments of the same columns (see zsolve_core.h).
-template <typename T, int MMAX, int CPB, int NTMAX>
-__global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs a, const int *__restrict__ done)
+template <typename T, int MMAX, int CPB, int NTMAX, bool FULL>
+__global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const int *__restrict__ done)
 {
     if (done && *done) return;
     __shared__ double coef[6 * 1024];
     __shared__ double red[32];
+    __shared__ double zabc[3 * 512];  // the z coefficients, staged once per block
     constexpr int SPW = 64 / CPB;  // segments per wave
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < ag.nz; i += blockDim.x) {
+        zabc[i] = ag.za[i];
+        zabc[512 + i] = ag.zb[i];
+        zabc[1024 + i] = ag.zc[i];
+    }
+    ZArgs a = ag;
+    a.za = zabc;
+    a.zb = zabc + 512;
+    a.zc = zabc + 1024;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int c = lane % CPB, seg = w * SPW + lane / CPB;
     const int S = (int)(blockDim.x >> 6) * SPW;
     auto C = [&](int q, int s) -> double & { return coef[q * 1024 + s * CPB + c]; };
     const size_t col = (size_t)blockIdx.x * CPB + c;
     const ZSeg sg = zseg(a.nz, S, seg);
     ZLane<MMAX> L;
-    zp_load(L, data, a, col, sg);
+    zp_load<MMAX, FULL>(L, data, a, col, sg);
     const bool sblock = a.singular && blockIdx.x == 0;
     if (sblock) {  // project the singular column on the range of its operator
-        const double s = L.sing ? zp_wsum(L, a, sg) : 0.0;
+        const double s = L.sing ? zp_wsum<MMAX, FULL>(L, a, sg) : 0.0;
         if (c == 0) red[seg] = s;
         __syncthreads();
         double tot = 0;
         for (int q = 0; q < S; ++q) tot += red[q];
         const double m = tot / a.wsum;
-        if (L.sing) zp_shift(L, sg, m);
+        if (L.sing) zp_shift<MMAX, FULL>(L, sg, m);
         if (L.sing && seg == 0 && a.removed) *a.removed = m;
         __syncthreads();
     }
     double out[6];
-    zp_reduce(L, a, sg, out);
+    if (sblock) zp_reduce<MMAX, FULL, true>(L, a, sg, out);
+    else zp_reduce<MMAX, FULL, false>(L, a, sg, out);
 #pragma unroll
     for (int q = 0; q < 6; ++q) C(q, seg) = out[q];
     __syncthreads();
@@ -400,16 +413,17 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs a, const i
     __syncthreads();
     const double xL = seg > 0 ? C(5, seg - 1) : 0.0;
     const double xR = seg < S - 1 ? C(4, seg + 1) : 0.0;
-    zp_finish(L, a, sg, xL, xR);
+    if (sblock) zp_finish<MMAX, FULL, true>(L, a, sg, xL, xR);
+    else zp_finish<MMAX, FULL, false>(L, a, sg, xL, xR);
     if (sblock) {  // zero weighted mean of the singular column
-        const double s = L.sing ? zp_wsum(L, a, sg) : 0.0;
+        const double s = L.sing ? zp_wsum<MMAX, FULL>(L, a, sg) : 0.0;
         if (c == 0) red[seg] = s;
         __syncthreads();
         double tot = 0;
         for (int q = 0; q < S; ++q) tot += red[q];
-        if (L.sing) zp_shift(L, sg, tot / a.wsum);
+        if (L.sing) zp_shift<MMAX, FULL>(L, sg, tot / a.wsum);
     }
-    zp_store(L, data, a, col, sg);
+    zp_store<MMAX, FULL>(L, data, a, col, sg);
 }
 
 template <typename T>
@@ -423,12 +437,26 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
         return check_launch();
     }
     const dim3 grid((unsigned)((plane + zp.cpb - 1) / zp.cpb)), block(zp.threads);
-    if (zp.mmax == 8)
-        hipLaunchKernelGGL((k_zsolve_part<T, 8, 64, 1024>), grid, block, 0, s, data, za, done);
-    else if (zp.cpb == 64)
-        hipLaunchKernelGGL((k_zsolve_part<T, 16, 64, 1024>), grid, block, 0, s, data, za, done);
-    else
-        hipLaunchKernelGGL((k_zsolve_part<T, 16, 32, 1024>), grid, block, 0, s, data, za, done);
+    const int S = (zp.threads / 64) * (64 / zp.cpb);
+    const bool full = pb.nz == S * zp.mmax;  // every segment holds mmax levels
+    // a FULL 16-level kernel keeps both segment sweeps unrolled in registers;
+    // at 768 threads per block it gets 168 VGPRs instead of 128 and does not
+    // spill
+    const bool small = zp.threads <= 768;
+#define CANS_ZP(MM, CPB, NT, FULLV) \
+    hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, FULLV>), grid, block, 0, s, data, za, done)
+    if (zp.mmax == 8) {
+        if (full) CANS_ZP(8, 64, 1024, true); else CANS_ZP(8, 64, 1024, false);
+    } else if (zp.cpb == 64) {
+        if (full && small) CANS_ZP(16, 64, 768, true);
+        else if (full) CANS_ZP(16, 64, 1024, true);
+        else CANS_ZP(16, 64, 1024, false);
+    } else {
+        if (full && small) CANS_ZP(16, 32, 768, true);
+        else if (full) CANS_ZP(16, 32, 1024, true);
+        else CANS_ZP(16, 32, 1024, false);
+    }
+#undef CANS_ZP
     return check_launch();
 }
 

@@ -227,17 +227,17 @@ CANS_HD ZSeg zseg(int nz, int S, int w)
 }
 
 // row coefficients of level k for a lane; the singular lane pins its last
-// row to x = 0
+// row to x = 0 (SING: compiled only where the singular column can occur)
+template <bool SING>
 CANS_HD void zrow(const ZArgs &a, int k, double lam, bool sing, double &ak, double &bk, double &ck)
 {
     ak = a.za[k];
     bk = a.zb[k] + lam;
     ck = a.zc[k];
-    if (k == a.nz - 1) {  // uniform across a segment: only the last level pays
-        if (sing) { ak = 0.0; bk = 1.0; ck = 0.0; }
-    }
+    if (SING && sing && k == a.nz - 1) { ak = 0.0; bk = 1.0; ck = 0.0; }
 }
 
+// FULL: every segment has exactly MMAX levels, so the level guards fold away.
 template <int MMAX>
 struct ZLane {
     double f[MMAX];   // rhs, later the forward-swept rhs, later x
@@ -247,7 +247,7 @@ struct ZLane {
 };
 
 // load the segment's rhs (scaled) and the column's lambda
-template <int MMAX, typename T>
+template <int MMAX, bool FULL, typename T>
 CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
     const size_t plane = (size_t)a.nx * a.ny;
@@ -257,49 +257,49 @@ CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, 
     const T *ptr = data + (L.valid ? col : 0) + plane * sg.k0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
-        if (t < sg.m) L.f[t] = L.valid ? a.scale * (double)ptr[0] : 0.0;
+        if (FULL || t < sg.m) L.f[t] = L.valid ? a.scale * (double)ptr[0] : 0.0;
         ptr += plane;
     }
 }
 
 // weighted partial sum of this segment (singular lane only)
-template <int MMAX>
+template <int MMAX, bool FULL>
 CANS_HD double zp_wsum(const ZLane<MMAX> &L, const ZArgs &a, ZSeg sg)
 {
     double s = 0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t)
-        if (t < sg.m) s += a.dzf[sg.k0 + t] * L.f[t];
+        if (FULL || t < sg.m) s += a.dzf[sg.k0 + t] * L.f[t];
     return s;
 }
 
-template <int MMAX>
+template <int MMAX, bool FULL>
 CANS_HD void zp_shift(ZLane<MMAX> &L, ZSeg sg, double m)
 {
 #pragma unroll
     for (int t = 0; t < MMAX; ++t)
-        if (t < sg.m) L.f[t] -= m;
+        if (FULL || t < sg.m) L.f[t] -= m;
 }
 
 // step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F.
 // The top-down sweep (level i) and the bottom-up sweep (level MMAX-1-i, live
 // once it is below m) run in one unrolled loop: two independent dependency
 // chains for the scheduler to interleave.
-template <int MMAX>
+template <int MMAX, bool FULL, bool SING>
 CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
 {
     // the pinned row of the singular lane carries rhs 0
 #pragma unroll
     for (int t = 0; t < MMAX; ++t)
-        if (t < sg.m && L.sing && sg.k0 + t == a.nz - 1) L.f[t] = 0.0;
+        if (SING && (FULL || t < sg.m) && L.sing && sg.k0 + t == a.nz - 1) L.f[t] = 0.0;
     double cp = 0, d = 0, g = 0;    // top-down: c', d', fill-in of xL
     double ep = 0, dd = 0, h = 0;   // bottom-up: a'', d'', fill-in of xR
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) {
         const int t = i;
-        if (t < sg.m) {
+        if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            zrow<SING>(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
             const double rr = rcp64(t == 0 ? bk : bk - ak * cp);
             L.r[t] = rr;
             d = (t == 0 ? L.f[t] : L.f[t] - ak * d) * rr;
@@ -307,10 +307,10 @@ CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
             cp = ck * rr;
         }
         const int u = MMAX - 1 - i;
-        if (u < sg.m) {
+        if (FULL || u < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + u, L.lam, L.sing, ak, bk, ck);
-            const bool last = (u == sg.m - 1);
+            zrow<SING>(a, sg.k0 + u, L.lam, L.sing, ak, bk, ck);
+            const bool last = FULL ? (u == MMAX - 1) : (u == sg.m - 1);
             const double rr = rcp64(last ? bk : bk - ck * ep);
             dd = (last ? L.f[u] : L.f[u] - ck * dd) * rr;
             h = (last ? ck : -ck * h) * rr;
@@ -353,15 +353,15 @@ CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo)
 }
 
 // step 3: x of the segment from its outside neighbours xL, xR
-template <int MMAX>
+template <int MMAX, bool FULL, bool SING>
 CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, double xR)
 {
     double d = xL;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
-        if (t < sg.m) {
+        if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            zrow<SING>(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
             d = (L.f[t] - ak * d) * L.r[t];
             L.f[t] = d;
         }
@@ -369,16 +369,16 @@ CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, doubl
     double x = xR;
 #pragma unroll
     for (int t = MMAX - 1; t >= 0; --t) {
-        if (t < sg.m) {
+        if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            zrow<SING>(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
             x = L.f[t] - ck * L.r[t] * x;
             L.f[t] = x;
         }
     }
 }
 
-template <int MMAX, typename T>
+template <int MMAX, bool FULL, typename T>
 CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
     if (!L.valid) return;
@@ -386,7 +386,7 @@ CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col,
     T *ptr = data + col + plane * sg.k0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
-        if (t < sg.m) ptr[0] = (T)L.f[t];
+        if (FULL || t < sg.m) ptr[0] = (T)L.f[t];
         ptr += plane;
     }
 }

@@ -162,7 +162,7 @@ void solve_pass(Setup &s, std::vector<T> &a, double *removed)
 
 // the partitioned z kernel, phase by phase over all segments and columns of a
 // block (CPB columns, S segments)
-template <int MMAX, typename T>
+template <int MMAX, bool FULL, typename T>
 void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
 {
     const ZArgs &a = s.z;
@@ -174,17 +174,18 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
     for (size_t blk = 0; blk * cpb < plane; ++blk) {
         const bool sblock = a.singular && blk == 0;
         for (int w = 0; w < S; ++w)
-            for (int c = 0; c < cpb; ++c) zp_load(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
+            for (int c = 0; c < cpb; ++c) zp_load<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
         if (sblock) {
             double tot = 0;
-            for (int w = 0; w < S; ++w) tot += zp_wsum(lane(w, 0), a, zseg(s.nz, S, w));
-            for (int w = 0; w < S; ++w) zp_shift(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
+            for (int w = 0; w < S; ++w) tot += zp_wsum<MMAX, FULL>(lane(w, 0), a, zseg(s.nz, S, w));
+            for (int w = 0; w < S; ++w) zp_shift<MMAX, FULL>(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
             if (removed) *removed = tot / a.wsum;
         }
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
                 double out[6];
-                zp_reduce(lane(w, c), a, zseg(s.nz, S, w), out);
+                if (sblock) zp_reduce<MMAX, FULL, true>(lane(w, c), a, zseg(s.nz, S, w), out);
+                else zp_reduce<MMAX, FULL, false>(lane(w, c), a, zseg(s.nz, S, w), out);
                 for (int q = 0; q < 6; ++q) C(q, w, c) = out[q];
             }
         for (int c = 0; c < cpb; ++c)
@@ -194,15 +195,16 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
                 const double xL = w > 0 ? C(5, w - 1, c) : 0.0, xR = w < S - 1 ? C(4, w + 1, c) : 0.0;
-                zp_finish(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
+                if (sblock) zp_finish<MMAX, FULL, true>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
+                else zp_finish<MMAX, FULL, false>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
             }
         if (sblock) {
             double tot = 0;
-            for (int w = 0; w < S; ++w) tot += zp_wsum(lane(w, 0), a, zseg(s.nz, S, w));
-            for (int w = 0; w < S; ++w) zp_shift(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
+            for (int w = 0; w < S; ++w) tot += zp_wsum<MMAX, FULL>(lane(w, 0), a, zseg(s.nz, S, w));
+            for (int w = 0; w < S; ++w) zp_shift<MMAX, FULL>(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
         }
         for (int w = 0; w < S; ++w)
-            for (int c = 0; c < cpb; ++c) zp_store(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
+            for (int c = 0; c < cpb; ++c) zp_store<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
     }
 }
 
@@ -213,8 +215,14 @@ bool zsolve_part_any(Setup &s, T *data, double *removed)
     const ZPart zp = s.z.cyclic ? ZPart{0, 0, 0} : zpart_shape(s.nz);
     if (zp.mmax == 0) return false;
     const int S = (zp.threads / 64) * (64 / zp.cpb);
-    if (zp.mmax == 8) zsolve_part_mm<8>(s, data, removed, zp.cpb, S);
-    else zsolve_part_mm<16>(s, data, removed, zp.cpb, S);
+    const bool full = s.nz == S * zp.mmax;
+    if (zp.mmax == 8) {
+        if (full) zsolve_part_mm<8, true>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<8, false>(s, data, removed, zp.cpb, S);
+    } else {
+        if (full) zsolve_part_mm<16, true>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<16, false>(s, data, removed, zp.cpb, S);
+    }
     return true;
 }
 

@@ -101,7 +101,7 @@ def test_zsolve_stage():
         assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
 
 
-@pytest.mark.parametrize("nz", [1, 2, 5, 8, 9, 17, 31, 64, 96, 100, 129, 256, 257, 300, 384, 512])
+@pytest.mark.parametrize("nz", [1, 2, 5, 8, 9, 16, 17, 31, 64, 96, 100, 128, 129, 256, 257, 300, 384, 512])
 def test_zsolve_partitioned(nz):
     """Register-resident partitioned z solve (segments per wave, reduced
     interface system) against the oracle's column solves, including the
