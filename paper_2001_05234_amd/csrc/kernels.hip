@@ -583,6 +583,15 @@ int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hip
     return check_launch();
 }
 
+// blocks of the first forward x transform, which also leaves the partial
+// weighted sums of the rhs (one triple per block)
+static int xfwd_blocks(const Problem &pb)
+{
+    const long nlines = (long)pb.ny * pb.nz;
+    const int L = pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L;
+    return (int)((nlines + L - 1) / L);
+}
+
 int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *done, hipStream_t s)
 {
     if (pb.ax.dense) {
@@ -593,7 +602,7 @@ int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *
     }
     const XGeom &g = pb.ax.gx32[1];
     const long nlines = (long)pb.ny * pb.nz;
-    const dim3 grid((unsigned)((nlines + g.L - 1) / g.L));
+    const dim3 grid((unsigned)xfwd_blocks(pb));
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         hipLaunchKernelGGL((k_xform_x<KD, true, float, double, float, 0>), grid, dim3(kThreads), sh, s,
@@ -722,7 +731,7 @@ int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipS
 int launch_mean_rhs(const Problem &pb, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
-    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb),
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, xfwd_blocks(pb),
                        pb.sums, nullptr);
     hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, inv_wvol, pb.singular,
                        pb.d_info);
