@@ -127,23 +127,45 @@ def bench_batched(torch, capi, inputs, args):
             "converged": conv, "worst_residual": worst}
 
 
-def cpu_baseline(pr, f, nz_sample):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pr, f, nz_sample, nz_sample_1t):
     """The oracle, as it stands, on the first nz_sample z-levels of the grid
     (full x-y planes: the same per-point work, O(nx + ny) transform
-    multiply-adds plus the z elimination)."""
+    multiply-adds plus the z elimination), with all its OpenMP threads; then
+    on one thread over the first nz_sample_1t levels."""
     import numpy as np
 
     from oracle import oracle
-    fs = np.ascontiguousarray(f[:nz_sample])
-    dzs = np.ascontiguousarray(pr.dzf[:nz_sample])
-    t0 = time.perf_counter()
-    oracle.solve(fs, pr.bc, pr.dx, pr.dy, dzs)
-    dt = time.perf_counter() - t0
-    pts = fs.size
-    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+
+    def run(nzs):
+        fs = np.ascontiguousarray(f[:nzs])
+        dzs = np.ascontiguousarray(pr.dzf[:nzs])
+        t0 = time.perf_counter()
+        oracle.solve(fs, pr.bc, pr.dx, pr.dy, dzs)
+        return fs.size, time.perf_counter() - t0
+
+    threads = oracle.threads()
+    pts, dt = run(nz_sample)
+    oracle.set_threads(1)
+    pts1, dt1 = run(nz_sample_1t)
+    oracle.set_threads(threads)
     return {"value": pts / dt, "unit": "grid pts/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle solve (O(N^2) transforms + Thomas) of the first {nz_sample} of "
-                      f"{pr.nz} z-levels of the {pr.nx}x{pr.ny}x{pr.nz} grid, {pts} points, {dt:.1f} s"}
+                      f"{pr.nz} z-levels of the {pr.nx}x{pr.ny}x{pr.nz} grid, {pts} points, {dt:.1f} s "
+                      f"on {threads} OpenMP threads",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "value_1thread": pts1 / dt1,
+            "sample_1thread": f"first {nz_sample_1t} z-levels, {pts1} points, {dt1:.1f} s on 1 thread"}
 
 
 def main():
@@ -154,6 +176,7 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--cpu-sample-levels", type=int, default=384)
+    ap.add_argument("--cpu-sample-levels-1t", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="built-in tile choice instead of plan-time tuning")
@@ -206,7 +229,7 @@ def main():
                                f"rhs = divergence of seeded N(0,1) staggered velocity; FP32 transforms, FP64 "
                                f"Thomas + residual, refined to rel. residual 1e-10",
                    "grid_points": npts, "corrections": info["iterations"],
-                   "residual": info["residual"], "wall_s": wall},
+                   "residual": info["residual"], "residual_inf": info["residual_inf"], "wall_s": wall},
     }
     if args.solve_only:
         print(json.dumps(out), flush=True)
@@ -258,7 +281,8 @@ def main():
 
     if not args.no_cpu_baseline:
         say("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(pr, f, min(args.cpu_sample_levels, pr.nz))
+        out["cpu_baseline"] = cpu_baseline(pr, f, min(args.cpu_sample_levels, pr.nz),
+                                           min(args.cpu_sample_levels_1t, pr.nz))
     print(json.dumps(out), flush=True)
 
 

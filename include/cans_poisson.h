@@ -96,6 +96,9 @@ typedef struct cans_info {
     double removed_mean;    /* singular problems (every axis periodic or
                                Neumann-Neumann): dzf-weighted mean of the rhs
                                removed to make it compatible; else 0 */
+    double residual_inf;    /* max-norm form of the last residual check,
+                               max|Pi f - L_h p| / max|Pi f| (FP32_REFINE);
+                               -1 when not measured (FP64) */
 } cans_info;
 
 typedef struct cans_plan_s *cans_plan_t;

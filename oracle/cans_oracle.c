@@ -39,6 +39,7 @@
  * bc[6] = {x-, x+, y-, y+, z-, z+}.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -57,6 +58,11 @@ typedef double REAL;
 #endif
 
 enum { BC_P = 0, BC_N = 1, BC_D = 2 };
+
+/* Threads of the OpenMP loops below (for timing the oracle on n cores), and
+ * the number a parallel loop will use. */
+void SYM(oracle_set_threads)(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int SYM(oracle_threads)(void) { return omp_get_max_threads(); }
 /* transform kinds of one axis, named by the (lower, upper) boundary pair */
 enum { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4 };
 

@@ -62,6 +62,8 @@ def _lib(ld: bool = False):
             "oracle_spectral_solve": ([i, i, i, ip, d, d, dp, dp, dp, dp], i),
             "oracle_solve": ([i, i, i, ip, d, d, dp, dp, dp, dp], i),
             "oracle_apply_L": ([i, i, i, ip, d, d, dp, dp, dp], None),
+            "oracle_set_threads": ([i], None),
+            "oracle_threads": ([], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name + sfx)
@@ -84,6 +86,16 @@ def _bc(bc):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads used by the oracle's loops (timing runs)."""
+    _lib().oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    """Threads a parallel loop of the oracle uses now."""
+    return int(_lib().oracle_threads())
 
 
 def axis_kind(lo: int, hi: int) -> int:
@@ -179,3 +191,12 @@ def residual(p, f, bc, dx, dy, dzf):
         f = f - weighted_mean(f, dzf)
     r = f - apply_L(p, bc, dx, dy, dzf)
     return float(np.linalg.norm(r) / np.linalg.norm(f))
+
+
+def residual_inf(p, f, bc, dx, dy, dzf):
+    """Max-norm form of `residual`: max|Pi f - L_h p| / max|Pi f|."""
+    f = _f64(f)
+    if is_singular(bc):
+        f = f - weighted_mean(f, dzf)
+    r = f - apply_L(p, bc, dx, dy, dzf)
+    return float(np.abs(r).max() / np.abs(f).max())

@@ -39,7 +39,8 @@ class CansOpts(ctypes.Structure):
 
 class CansInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double),
-                ("history", ctypes.c_double * HISTORY), ("removed_mean", ctypes.c_double)]
+                ("history", ctypes.c_double * HISTORY), ("removed_mean", ctypes.c_double),
+                ("residual_inf", ctypes.c_double)]
 
 
 class CansDesc(ctypes.Structure):
@@ -124,7 +125,7 @@ def default_opts() -> CansOpts:
 def _info(ci: CansInfo) -> dict:
     hist = [h for h in ci.history if h >= 0]
     return {"iterations": ci.iterations, "converged": bool(ci.converged), "residual": ci.residual,
-            "history": hist, "removed_mean": ci.removed_mean}
+            "history": hist, "removed_mean": ci.removed_mean, "residual_inf": ci.residual_inf}
 
 
 class Plan:

@@ -17,8 +17,13 @@ enum InfoSlot {
     I_CONV = 3,      // 1 when the residual test passed
     I_LAST = 4,      // last relative residual
     I_HIST = 5,      // CANS_HISTORY entries
-    I_SIZE = I_HIST + CANS_HISTORY
+    I_LINF = I_HIST + CANS_HISTORY,  // last residual in the max norm
+    I_SIZE = I_LINF + 1
 };
+
+// values per block partial of the reductions: sum r^2, sum (Pi f)^2,
+// sum dzf p, max |r|, max |Pi f| (the first pass uses entry 0 only)
+constexpr int kNP = 5;
 
 constexpr int kThreads = 256;  // threads per block of the transform kernels
 

@@ -49,6 +49,39 @@ __device__ void block_sum3(double &a, double &b, double &c)
     __syncthreads();
 }
 
+// block maxima of two non-negative values (exact in any order)
+__device__ void block_max2(double &a, double &b)
+{
+    __shared__ double red[2][kThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a = fmax(a, __shfl_down(a, off, 64));
+        b = fmax(b, __shfl_down(b, off, 64));
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kThreads / 64; ++i) { a = fmax(a, red[0][i]); b = fmax(b, red[1][i]); }
+    }
+    __syncthreads();
+}
+
+// one block partial of the residual passes (thread 0 writes)
+__device__ void put_partial(double *partials, unsigned b, double srr, double sff, double spw, double rmax,
+                            double fmax_)
+{
+    block_sum3(srr, sff, spw);
+    block_max2(rmax, fmax_);
+    if (threadIdx.x == 0) {
+        double *q = partials + (size_t)kNP * b;
+        q[0] = srr;
+        q[1] = sff;
+        q[2] = spw;
+        q[3] = rmax;
+        q[4] = fmax_;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
 // runs a contiguous range of tiles (neighbouring y tiles share cache lines).
@@ -119,9 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, 
             double z1 = 0, z2 = 0;
             block_sum3(acc, z1, z2);
             if (threadIdx.x == 0) {
-                wsum_part[3 * blockIdx.x] = acc;
-                wsum_part[3 * blockIdx.x + 1] = 0;
-                wsum_part[3 * blockIdx.x + 2] = 0;
+                wsum_part[kNP * blockIdx.x] = acc;
             }
         }
     }
@@ -166,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, i
 
 // Residual of the current p fused with the forward x transform of it:
 //   r = (f - removed mean) - L_h p   (FP64), out = T_x r (FP32);
-// block partial sums of |r|^2, |f - mean|^2 and sum dzf p.
+// block partials: sums of |r|^2, |f - mean|^2, dzf p; maxima of |r|, |f - mean|.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restrict__ f,
                                                          const double *__restrict__ p, float *out,
@@ -184,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
     const long line0 = (long)blockIdx.x * g.L;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mf = info[I_REMOVED];
-    double srr = 0, sff = 0, spw = 0;
+    double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
     // residual of the tile's lines into LDS (coalesced, each point once)
     auto one = [&](int e, int l, long line, int j, int k) {
         const size_t gi = (size_t)line * n + e;
@@ -192,6 +223,8 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
         const double r = fv - lap_point(p, e, j, k, la);
         srr += r * r;
         sff += fv * fv;
+        rmax = fmax(rmax, fabs(r));
+        fmx = fmax(fmx, fabs(fv));
         spw += dzf[k] * p[gi];
         tile_real(tile, e, l) = (float)r;
     };
@@ -225,16 +258,11 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
         if (line < nlines) out[(size_t)line * n + q] = v;
     };
     tile_transform<KIND, true, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
-    block_sum3(srr, sff, spw);
-    if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x + 0] = srr;
-        partials[3 * blockIdx.x + 1] = sff;
-        partials[3 * blockIdx.x + 2] = spw;
-    }
+    put_partial(partials, blockIdx.x, srr, sff, spw, rmax, fmx);
 }
 
-// Residual norms only (the check after a correction): block partial sums of
-// |r|^2, |f - mean|^2 and sum dzf p over lines_per_block lines.
+// Residual norms only (the check after a correction): the same block
+// partials as k_resid_xfwd over lines_per_block lines.
 __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restrict__ f,
                                                          const double *__restrict__ p, long nlines,
                                                          int lines_per_block, LapArgs la,
@@ -248,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
     const long line0 = (long)blockIdx.x * lines_per_block;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mf = info[I_REMOVED];
-    double srr = 0, sff = 0, spw = 0;
+    double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
     for (int l = 0; l < lines_per_block; ++l) {
         const long line = line0 + l;
         if (line >= nlines) break;
@@ -260,19 +288,18 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
             const double r = fv - lap_point(p, e, j, k, la);
             srr += r * r;
             sff += fv * fv;
+            rmax = fmax(rmax, fabs(r));
+            fmx = fmax(fmx, fabs(fv));
+        rmax = fmax(rmax, fabs(r));
+        fmx = fmax(fmx, fabs(fv));
             spw += wk * p[gi];
         }
     }
-    block_sum3(srr, sff, spw);
-    if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x + 0] = srr;
-        partials[3 * blockIdx.x + 1] = sff;
-        partials[3 * blockIdx.x + 2] = spw;
-    }
+    put_partial(partials, blockIdx.x, srr, sff, spw, rmax, fmx);
 }
 
-// First level of the block-partial reductions: block b sums its contiguous
-// chunk of triples (fixed order) into sums[3b..3b+2].
+// First level of the block-partial reductions: block b reduces its contiguous
+// chunk of partials (fixed order) into sums[kNP b .. kNP b + kNP - 1].
 constexpr int kReduceBlocks = 256;
 
 __global__ __launch_bounds__(kThreads) void k_reduce1(const double *__restrict__ partials, int nblk,
@@ -281,39 +308,43 @@ __global__ __launch_bounds__(kThreads) void k_reduce1(const double *__restrict__
     if (done && *done) return;
     const int chunk = (nblk + kReduceBlocks - 1) / kReduceBlocks;
     const int lo = blockIdx.x * chunk, hi = min(nblk, lo + chunk);
-    double a = 0, b = 0, c = 0;
+    double a = 0, b = 0, c = 0, d = 0, e = 0;
     for (int i = lo + (int)threadIdx.x; i < hi; i += kThreads) {
-        a += partials[3 * i];
-        b += partials[3 * i + 1];
-        c += partials[3 * i + 2];
+        const double *q = partials + (size_t)kNP * i;
+        a += q[0];
+        b += q[1];
+        c += q[2];
+        d = fmax(d, q[3]);
+        e = fmax(e, q[4]);
     }
-    block_sum3(a, b, c);
-    if (threadIdx.x == 0) {
-        sums[3 * blockIdx.x] = a;
-        sums[3 * blockIdx.x + 1] = b;
-        sums[3 * blockIdx.x + 2] = c;
-    }
+    put_partial(sums, blockIdx.x, a, b, c, d, e);
 }
 
 // Sum the first-level sums in a fixed order, record the relative residual of
-// check number `check` and decide: converged (<= tol) or out of steps.
+// check number `check` (2-norm, and the max norm beside it) and decide:
+// converged (<= tol, 2-norm) or out of steps.
 __global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nblk,
                                                        int check, int max_iter, double tol,
                                                        double inv_wvol, int singular,
                                                        double *__restrict__ info, int *__restrict__ flag)
 {
     if (flag[0]) return;
-    double a = 0, b = 0, c = 0;
+    double a = 0, b = 0, c = 0, d = 0, e = 0;
     for (int i = threadIdx.x; i < nblk; i += kThreads) {
-        a += partials[3 * i];
-        b += partials[3 * i + 1];
-        c += partials[3 * i + 2];
+        const double *q = partials + (size_t)kNP * i;
+        a += q[0];
+        b += q[1];
+        c += q[2];
+        d = fmax(d, q[3]);
+        e = fmax(e, q[4]);
     }
     block_sum3(a, b, c);
+    block_max2(d, e);
     if (threadIdx.x == 0) {
         const double rel = b > 0 ? sqrt(a / b) : sqrt(a);
         info[I_HIST + check] = rel;
         info[I_LAST] = rel;
+        info[I_LINF] = e > 0 ? d / e : d;
         info[I_MEANP] = singular ? c * inv_wvol : 0.0;
         info[I_ITERS] = check;
         if (rel <= tol) {
@@ -333,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void k_mean_rhs(const double *__restrict_
                                                        double *__restrict__ info)
 {
     double a = 0, b = 0, c = 0;
-    for (int i = threadIdx.x; i < nblk; i += kThreads) a += partials[3 * i];
+    for (int i = threadIdx.x; i < nblk; i += kThreads) a += partials[(size_t)kNP * i];
     block_sum3(a, b, c);
     if (threadIdx.x == 0) info[I_REMOVED] = singular ? a * inv_wvol : 0.0;
 }
@@ -497,9 +528,7 @@ __global__ __launch_bounds__(256) void k_dense_x(const Tin *in, Tout *out, long 
         double z1 = 0, z2 = 0;
         block_sum3(acc, z1, z2);
         if (threadIdx.x == 0) {
-            wsum_part[3 * blockIdx.x] = acc;
-            wsum_part[3 * blockIdx.x + 1] = 0;
-            wsum_part[3 * blockIdx.x + 2] = 0;
+            wsum_part[kNP * blockIdx.x] = acc;
         }
     }
 }
@@ -518,7 +547,7 @@ __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ 
     const long line0 = (long)blockIdx.x * kDenseLines;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mf = info[I_REMOVED];
-    double srr = 0, sff = 0, spw = 0;
+    double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
     auto src = [&](int e, int l) -> float {
         const long line = line0 + l;
         if (line >= nlines) return 0.f;
@@ -529,6 +558,8 @@ __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ 
         const double r = fv - lap_point(p, e, j, k, la);
         srr += r * r;
         sff += fv * fv;
+        rmax = fmax(rmax, fabs(r));
+        fmx = fmax(fmx, fabs(fv));
         spw += dzf[k] * p[gi];
         return (float)r;
     };
@@ -537,12 +568,7 @@ __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ 
         if (line < nlines) out[(size_t)line * n + q] = v;
     };
     dense_transform(n, magn, src, put, Wh, Wl, reinterpret_cast<unsigned short *>(smem));
-    block_sum3(srr, sff, spw);
-    if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x + 0] = srr;
-        partials[3 * blockIdx.x + 1] = sff;
-        partials[3 * blockIdx.x + 2] = spw;
-    }
+    put_partial(partials, blockIdx.x, srr, sff, spw, rmax, fmx);
 }
 
 static dim3 dense_grid(const Problem &pb)

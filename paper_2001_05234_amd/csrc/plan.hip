@@ -235,8 +235,8 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     if (pl->opts.precision == CANS_PREC_FP32_REFINE) {
         CANS_TRY(alloc(pl, &pb.a32, N));
         // block partial sums: enough for any tile shape (one line per block)
-        CANS_TRY(alloc(pl, &pb.partials, 3 * (size_t)pb.ny * pb.nz));
-        CANS_TRY(alloc(pl, &pb.sums, 3 * 256));
+        CANS_TRY(alloc(pl, &pb.partials, kNP * (size_t)pb.ny * pb.nz));
+        CANS_TRY(alloc(pl, &pb.sums, kNP * 256));
     }
     if (pl->opts.autotune) CANS_TRY(autotune(pl, pb));
     std::vector<double> info(I_SIZE, 0.0);
@@ -354,11 +354,13 @@ int fill_info(const Problem &pb, int precision, cans_info *out)
         out->iterations = 0;
         out->converged = 1;
         out->residual = -1;
+        out->residual_inf = -1;
         return CANS_OK;
     }
     out->iterations = (int)h[I_ITERS];
     out->converged = (int)h[I_CONV];
     out->residual = h[I_LAST];
+    out->residual_inf = h[I_LINF];
     for (int i = 0; i < CANS_HISTORY; ++i) out->history[i] = h[I_HIST + i];
     return CANS_OK;
 }

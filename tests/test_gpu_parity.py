@@ -195,8 +195,10 @@ def test_refine_bc(xp, zp):
         assert info["converged"] and info["residual"] <= 1e-10, info
         ro = O.residual(pg, f, bc, 1 / nx, 1 / ny, dzf)
         assert ro <= 1.5e-10
-        # the reported residual is the device's norm of the returned p
+        # the reported residuals are the device's norms of the returned p
         assert abs(info["residual"] - ro) <= 1e-3 * ro + 1e-16
+        ri = O.residual_inf(pg, f, bc, 1 / nx, 1 / ny, dzf)
+        assert abs(info["residual_inf"] - ri) <= 1e-3 * ri + 1e-16
         assert rel(demean(pg, bc, dzf), po) < TOL_REF
         assert abs(info["removed_mean"] - mo) < 1e-13 * max(1, abs(mo))
 
@@ -217,6 +219,8 @@ def test_refine_ragged_tiles(shape, bc):
     assert info["converged"] and info["residual"] <= 1e-10, info
     ro = O.residual(pg, f, bc, 1 / nx, 1 / ny, dzf)
     assert abs(info["residual"] - ro) <= 1e-3 * ro + 1e-16
+    ri = O.residual_inf(pg, f, bc, 1 / nx, 1 / ny, dzf)
+    assert abs(info["residual_inf"] - ri) <= 1e-3 * ri + 1e-16
     assert rel(demean(pg, bc, dzf), po) < TOL_REF
 
 

@@ -300,6 +300,26 @@ def test_apply_L_matches_dense_operator():
         np.testing.assert_allclose(O.apply_L(p, bc, 0.4, 0.6, dzf).ravel(), Ld @ p.ravel(), rtol=1e-12, atol=1e-10)
 
 
+def test_residual_norms_match_dense_operator():
+    """Both residual norms (2-norm and max-norm forms) equal those of the
+    dense operator applied to the same p, with the projection of a singular
+    rhs by its dzf-weighted mean."""
+    rng = np.random.default_rng(6)
+    for bc in [(P, P, N, N, N, N), (D, N, P, P, D, N)]:
+        nz, ny, nx = 4, 3, 6
+        dzf = inputs.tanh_dzf(nz, 1.4, 1.0)
+        p = rng.standard_normal((nz, ny, nx))
+        f = rng.standard_normal((nz, ny, nx))
+        Ld = dense_L(nx, ny, nz, bc, 0.4, 0.6, dzf)
+        pf = f.ravel().copy()
+        if O.is_singular(bc):
+            w = np.broadcast_to(dzf[:, None, None], f.shape).ravel()
+            pf -= (w @ pf) / w.sum()
+        r = pf - Ld @ p.ravel()
+        assert abs(O.residual(p, f, bc, 0.4, 0.6, dzf) - np.linalg.norm(r) / np.linalg.norm(pf)) < 1e-13
+        assert abs(O.residual_inf(p, f, bc, 0.4, 0.6, dzf) - np.abs(r).max() / np.abs(pf).max()) < 1e-13
+
+
 def test_projection_identity():
     """With f = D u (zero normal velocity at the walls), u - G p is
     discretely divergence free: D G = L_h with the staggered ghost rules
