@@ -82,6 +82,19 @@ def time_stage(plan, stage, a, b, reps, torch):
     return s.elapsed_time(e) / reps
 
 
+def run_stage(plan, stage, fd, pd, a32, reps, torch):
+    """One kernel of the refinement plan in the order of a solve (reps = 0:
+    a single untimed launch).  Stages 6 and 8 test the residual of pd, so the
+    finished flag is cleared first."""
+    if stage in (6, 8):
+        plan.debug_stage(0, fd, pd)
+    a, b = (fd, pd) if stage in (1, 6, 8) else (fd, a32)
+    if reps == 0:
+        plan.debug_stage(stage, a, b)
+        return 0.0
+    return time_stage(plan, stage, a, b, reps, torch)
+
+
 def copy_gbs(torch, nbytes):
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -184,6 +197,11 @@ def main():
     ap.add_argument("--fp64-only", action="store_true", help="time the FP64 solve only (profiling runs)")
     ap.add_argument("--copy-only", action="store_true",
                     help="1 GiB device-to-device copies only (calibrates the HBM byte counters)")
+    ap.add_argument("--kernel-only", type=int, default=0, metavar="STAGE",
+                    help="time one kernel (debug stage of the refinement plan, or of the FP64 plan with "
+                         "--fp64-only) exactly as the full run times it, nothing else (profiling runs)")
+    ap.add_argument("--xform-x", default="auto", choices=["auto", "fft", "dense"],
+                    help="x transform form of the refinement plan (dense: split-bf16 matrix-core products)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path in this build "
@@ -210,12 +228,29 @@ def main():
     if args.fp64_only:
         plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
                            autotune=not args.no_autotune)
+        if args.kernel_only:
+            name = [n for s, n, _ in KERNELS64 if s == args.kernel_only][0]
+            b = torch.zeros_like(fd)
+            src = b if args.kernel_only == 3 else fd
+            t = time_stage(plan64, args.kernel_only, src, b, max(1, args.kernel_reps // 2), torch)
+            print(json.dumps({"kernel": name, "kernel_ms": t, "plan": "fp64"}), flush=True)
+            return
         ms64, _ = time_solves(plan64, fd, pd, args.steps, args.warmup, torch)
         print(json.dumps({"fp64_ms_per_step": ms64, "value": npts / (ms64 * 1e-3)}), flush=True)
         return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
-                     tol=1e-10, max_iter=4, autotune=not args.no_autotune)
+                     tol=1e-10, max_iter=4, autotune=not args.no_autotune, xform_x=args.xform_x)
+    if args.kernel_only:
+        # the stages before it fill the plan's spectral field as in a solve
+        a32 = torch.zeros_like(fd)
+        for stage, name, _ in KERNELS32:
+            if stage == args.kernel_only:
+                t = run_stage(plan, stage, fd, pd, a32, args.kernel_reps, torch)
+                print(json.dumps({"kernel": name, "kernel_ms": t, "plan": "fp32_refine"}), flush=True)
+                return
+            run_stage(plan, stage, fd, pd, a32, 0, torch)
+        raise SystemExit(f"no stage {args.kernel_only}")
     ms, wall = time_solves(plan, fd, pd, args.steps, args.warmup, torch)
     info = plan.info()
     say(f"[bench] refine: {ms:.3f} ms/solve, info {info}")
@@ -239,12 +274,7 @@ def main():
     a32 = torch.zeros_like(fd)
     times = {}
     for stage, name, bpp in KERNELS32:
-        if stage in (6, 8):
-            plan.debug_stage(0, fd, pd)
-        if stage in (1, 6, 8):
-            t = time_stage(plan, stage, fd, pd, args.kernel_reps, torch)
-        else:
-            t = time_stage(plan, stage, fd, a32, args.kernel_reps, torch)
+        t = run_stage(plan, stage, fd, pd, a32, args.kernel_reps, torch)
         times[stage] = t
         say(f"[bench]   {name:42s} {t:8.3f} ms  {bpp * npts / (t * 1e-3) / 1e9:8.1f} GB/s")
     nr = info["iterations"]
@@ -270,7 +300,9 @@ def main():
     k64 = {}
     b = torch.zeros_like(fd)
     for stage, name, bpp in KERNELS64:
-        k64[name] = round(time_stage(plan64, stage, fd, b, max(1, args.kernel_reps // 2), torch), 4)
+        # the z stage runs in place, as in a solve (in != out would add a copy)
+        src = b if stage == 3 else fd
+        k64[name] = round(time_stage(plan64, stage, src, b, max(1, args.kernel_reps // 2), torch), 4)
     out["fp64"] = {"value": npts / (ms64 * 1e-3), "unit": "grid pts/s", "ms_per_step": ms64, "kernels_ms": k64}
     say(f"[bench] fp64: {ms64:.3f} ms/solve {k64}")
     plan64.close()

@@ -396,7 +396,6 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
 {
     if (done && *done) return;
     __shared__ double coef[6 * 1024];
-    __shared__ double red[32];
     __shared__ double zabc[3 * 512];  // the z coefficients, staged once per block
     constexpr int SPW = 64 / CPB;  // segments per wave
     for (int i = threadIdx.x; i < ag.nz; i += blockDim.x) {
@@ -418,21 +417,8 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     const ZSeg sg = zseg(a.nz, S, seg);
     ZLane<MMAX> L;
     zp_load<MMAX, FULL>(L, data, a, col, sg);
-    const bool sblock = a.singular && blockIdx.x == 0;
-    if (sblock) {  // project the singular column on the range of its operator
-        const double s = L.sing ? zp_wsum<MMAX, FULL>(L, a, sg) : 0.0;
-        if (c == 0) red[seg] = s;
-        __syncthreads();
-        double tot = 0;
-        for (int q = 0; q < S; ++q) tot += red[q];
-        const double m = tot / a.wsum;
-        if (L.sing) zp_shift<MMAX, FULL>(L, sg, m);
-        if (L.sing && seg == 0 && a.removed) *a.removed = m;
-        __syncthreads();
-    }
     double out[6];
-    if (sblock) zp_reduce<MMAX, FULL, true>(L, a, sg, out);
-    else zp_reduce<MMAX, FULL, false>(L, a, sg, out);
+    zp_reduce<MMAX, FULL>(L, a, sg, out);
 #pragma unroll
     for (int q = 0; q < 6; ++q) C(q, seg) = out[q];
     __syncthreads();
@@ -444,17 +430,14 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     __syncthreads();
     const double xL = seg > 0 ? C(5, seg - 1) : 0.0;
     const double xR = seg < S - 1 ? C(4, seg + 1) : 0.0;
-    if (sblock) zp_finish<MMAX, FULL, true>(L, a, sg, xL, xR);
-    else zp_finish<MMAX, FULL, false>(L, a, sg, xL, xR);
-    if (sblock) {  // zero weighted mean of the singular column
-        const double s = L.sing ? zp_wsum<MMAX, FULL>(L, a, sg) : 0.0;
-        if (c == 0) red[seg] = s;
-        __syncthreads();
-        double tot = 0;
-        for (int q = 0; q < S; ++q) tot += red[q];
-        if (L.sing) zp_shift<MMAX, FULL>(L, sg, tot / a.wsum);
-    }
+    zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
     zp_store<MMAX, FULL>(L, data, a, col, sg);
+    if (a.singular && blockIdx.x == 0) {
+        // the singular column, left out above: projected rhs, pinned last
+        // row, zero weighted mean, by one thread with coef as workspace
+        __syncthreads();
+        if (threadIdx.x == 0) zsolve_singular_ws<T>(0, data, a, coef, coef + 512, 1);
+    }
 }
 
 template <typename T>

@@ -36,8 +36,9 @@ template <typename T> CANS_HD void st(T *p, size_t i, double v) { p[i] = (T)v; }
 // z operator), solve with the last equation replaced by p_{nz-1} = 0 (the
 // periodic corner then multiplies the pinned unknown), and shift the result
 // to zero weighted mean.
+// wc, wd: workspace of the column, level k at wc[k * ws], wd[k * ws]
 template <typename T>
-CANS_HD void zsolve_singular(size_t col, T *data, const ZArgs &a)
+CANS_HD void zsolve_singular_ws(size_t col, T *data, const ZArgs &a, double *wc, double *wd, size_t ws)
 {
     const size_t plane = (size_t)a.nx * a.ny;
     const int nz = a.nz;
@@ -51,29 +52,36 @@ CANS_HD void zsolve_singular(size_t col, T *data, const ZArgs &a)
     }
     double piv = a.zb[0];
     double d = (a.scale * ld(data, col) - m) / piv;
-    a.wd[col] = d;
+    wd[0] = d;
     for (int k = 1; k < nz; ++k) {
         const double w = a.zc[k - 1] / piv;
-        a.wc[col + plane * k] = w;
+        wc[k * ws] = w;
         const bool last = (k == nz - 1);
         const double ak = last ? 0.0 : a.za[k];
         piv = (last ? 1.0 : a.zb[k]) - ak * w;
         const double rhs = last ? 0.0 : a.scale * ld(data, col + plane * k) - m;
         d = (rhs - ak * d) / piv;
-        a.wd[col + plane * k] = d;
+        wd[k * ws] = d;
     }
     double x = d, s2 = a.dzf[nz - 1] * x;
     for (int k = nz - 2; k >= 0; --k) {
-        x = a.wd[col + plane * k] - a.wc[col + plane * (k + 1)] * x;
-        a.wd[col + plane * k] = x;
+        x = wd[k * ws] - wc[(k + 1) * ws] * x;
+        wd[k * ws] = x;
         s2 += a.dzf[k] * x;
     }
-    a.wd[col + plane * (nz - 1)] = d;
+    wd[(nz - 1) * ws] = d;
     const double m2 = s2 / a.wsum;
-    for (int k = 0; k < nz; ++k) st(data, col + plane * k, a.wd[col + plane * k] - m2);
+    for (int k = 0; k < nz; ++k) st(data, col + plane * k, wd[k * ws] - m2);
 }
 
 // One spectral column, in place in `data` (T = double or float storage).
+template <typename T>
+CANS_HD void zsolve_singular(size_t col, T *data, const ZArgs &a)
+{
+    const size_t plane = (size_t)a.nx * a.ny;
+    zsolve_singular_ws(col, data, a, a.wc + col, a.wd + col, plane);
+}
+
 template <typename T>
 CANS_HD void zsolve_column(size_t col, T *data, const ZArgs &a)
 {
@@ -198,6 +206,8 @@ namespace cans {
 // back-substituted.  Each segment then re-runs its top-down sweep with xL
 // known (reusing the stored reciprocal pivots) and back-substitutes from xR.
 // Gauss elimination without pivoting throughout (diagonally dominant), FP64.
+// The singular column of a singular problem is not part of it: the kernel
+// solves that column apart (zsolve_singular_ws).
 
 // 1/x as v_rcp_f64 refined by two Newton steps on the device.
 CANS_HD double rcp64(double x)
@@ -210,6 +220,19 @@ CANS_HD double rcp64(double x)
     return fma(r, e, r);
 #else
     return 1.0 / x;
+#endif
+}
+
+// Materialise x here (device only).  The fill-in recurrences below are pure
+// running products; left alone, the compiler defers them to the end of the
+// unrolled sweep, which keeps every level's pivot and coefficient live at once
+// and runs the block out of registers.
+CANS_HD void zp_pin(double &x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(x));
+#else
+    (void)x;
 #endif
 }
 
@@ -226,15 +249,12 @@ CANS_HD ZSeg zseg(int nz, int S, int w)
     return s;
 }
 
-// row coefficients of level k for a lane; the singular lane pins its last
-// row to x = 0 (SING: compiled only where the singular column can occur)
-template <bool SING>
-CANS_HD void zrow(const ZArgs &a, int k, double lam, bool sing, double &ak, double &bk, double &ck)
+// row coefficients of level k for a lane
+CANS_HD void zrow(const ZArgs &a, int k, double lam, double &ak, double &bk, double &ck)
 {
     ak = a.za[k];
     bk = a.zb[k] + lam;
     ck = a.zc[k];
-    if (SING && sing && k == a.nz - 1) { ak = 0.0; bk = 1.0; ck = 0.0; }
 }
 
 // FULL: every segment has exactly MMAX levels, so the level guards fold away.
@@ -243,7 +263,7 @@ struct ZLane {
     double f[MMAX];   // rhs, later the forward-swept rhs, later x
     double r[MMAX];   // reciprocal pivots of the top-down sweep
     double lam;
-    bool sing, valid;
+    bool valid;
 };
 
 // load the segment's rhs (scaled) and the column's lambda
@@ -251,9 +271,11 @@ template <int MMAX, bool FULL, typename T>
 CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
     const size_t plane = (size_t)a.nx * a.ny;
-    L.valid = col < plane;
-    L.sing = a.singular && col == 0;
-    L.lam = L.valid ? a.lamx[col % a.nx] + a.lamy[col / a.nx] : -1.0;
+    // the singular column (singular problems, column 0) is solved apart
+    L.valid = col < plane && !(a.singular && col == 0);
+    // 32-bit index arithmetic: a plane holds at most 4096 x 4096 columns
+    const unsigned cu = L.valid ? (unsigned)col : 0u, nxu = (unsigned)a.nx;
+    L.lam = L.valid ? a.lamx[cu % nxu] + a.lamy[cu / nxu] : -1.0;
     const T *ptr = data + (L.valid ? col : 0) + plane * sg.k0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
@@ -262,36 +284,13 @@ CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, 
     }
 }
 
-// weighted partial sum of this segment (singular lane only)
-template <int MMAX, bool FULL>
-CANS_HD double zp_wsum(const ZLane<MMAX> &L, const ZArgs &a, ZSeg sg)
-{
-    double s = 0;
-#pragma unroll
-    for (int t = 0; t < MMAX; ++t)
-        if (FULL || t < sg.m) s += a.dzf[sg.k0 + t] * L.f[t];
-    return s;
-}
-
-template <int MMAX, bool FULL>
-CANS_HD void zp_shift(ZLane<MMAX> &L, ZSeg sg, double m)
-{
-#pragma unroll
-    for (int t = 0; t < MMAX; ++t)
-        if (FULL || t < sg.m) L.f[t] -= m;
-}
-
 // step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F.
 // The top-down sweep (level i) and the bottom-up sweep (level MMAX-1-i, live
 // once it is below m) run in one unrolled loop: two independent dependency
 // chains for the scheduler to interleave.
-template <int MMAX, bool FULL, bool SING>
+template <int MMAX, bool FULL>
 CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
 {
-    // the pinned row of the singular lane carries rhs 0
-#pragma unroll
-    for (int t = 0; t < MMAX; ++t)
-        if (SING && (FULL || t < sg.m) && L.sing && sg.k0 + t == a.nz - 1) L.f[t] = 0.0;
     double cp = 0, d = 0, g = 0;    // top-down: c', d', fill-in of xL
     double ep = 0, dd = 0, h = 0;   // bottom-up: a'', d'', fill-in of xR
 #pragma unroll
@@ -299,21 +298,23 @@ CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
         const int t = i;
         if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow<SING>(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            zrow(a, sg.k0 + t, L.lam, ak, bk, ck);
             const double rr = rcp64(t == 0 ? bk : bk - ak * cp);
             L.r[t] = rr;
             d = (t == 0 ? L.f[t] : L.f[t] - ak * d) * rr;
             g = (t == 0 ? ak : -ak * g) * rr;
+            zp_pin(g);
             cp = ck * rr;
         }
         const int u = MMAX - 1 - i;
         if (FULL || u < sg.m) {
             double ak, bk, ck;
-            zrow<SING>(a, sg.k0 + u, L.lam, L.sing, ak, bk, ck);
+            zrow(a, sg.k0 + u, L.lam, ak, bk, ck);
             const bool last = FULL ? (u == MMAX - 1) : (u == sg.m - 1);
             const double rr = rcp64(last ? bk : bk - ck * ep);
             dd = (last ? L.f[u] : L.f[u] - ck * dd) * rr;
             h = (last ? ck : -ck * h) * rr;
+            zp_pin(h);
             ep = ak * rr;
         }
     }
@@ -353,7 +354,7 @@ CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo)
 }
 
 // step 3: x of the segment from its outside neighbours xL, xR
-template <int MMAX, bool FULL, bool SING>
+template <int MMAX, bool FULL>
 CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, double xR)
 {
     double d = xL;
@@ -361,7 +362,7 @@ CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, doubl
     for (int t = 0; t < MMAX; ++t) {
         if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow<SING>(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            zrow(a, sg.k0 + t, L.lam, ak, bk, ck);
             d = (L.f[t] - ak * d) * L.r[t];
             L.f[t] = d;
         }
@@ -371,7 +372,7 @@ CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, doubl
     for (int t = MMAX - 1; t >= 0; --t) {
         if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow<SING>(a, sg.k0 + t, L.lam, L.sing, ak, bk, ck);
+            zrow(a, sg.k0 + t, L.lam, ak, bk, ck);
             x = L.f[t] - ck * L.r[t] * x;
             L.f[t] = x;
         }

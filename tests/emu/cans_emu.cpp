@@ -161,7 +161,7 @@ void solve_pass(Setup &s, std::vector<T> &a, double *removed)
 }
 
 // the partitioned z kernel, phase by phase over all segments and columns of a
-// block (CPB columns, S segments)
+// block (CPB columns, S segments); the singular column is solved apart
 template <int MMAX, bool FULL, typename T>
 void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
 {
@@ -172,20 +172,12 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
     auto C = [&](int q, int seg, int c) -> double & { return coef[q * 1024 + seg * cpb + c]; };
     auto lane = [&](int seg, int c) -> ZLane<MMAX> & { return L[(size_t)seg * cpb + c]; };
     for (size_t blk = 0; blk * cpb < plane; ++blk) {
-        const bool sblock = a.singular && blk == 0;
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) zp_load<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
-        if (sblock) {
-            double tot = 0;
-            for (int w = 0; w < S; ++w) tot += zp_wsum<MMAX, FULL>(lane(w, 0), a, zseg(s.nz, S, w));
-            for (int w = 0; w < S; ++w) zp_shift<MMAX, FULL>(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
-            if (removed) *removed = tot / a.wsum;
-        }
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
                 double out[6];
-                if (sblock) zp_reduce<MMAX, FULL, true>(lane(w, c), a, zseg(s.nz, S, w), out);
-                else zp_reduce<MMAX, FULL, false>(lane(w, c), a, zseg(s.nz, S, w), out);
+                zp_reduce<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), out);
                 for (int q = 0; q < 6; ++q) C(q, w, c) = out[q];
             }
         for (int c = 0; c < cpb; ++c)
@@ -195,16 +187,16 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
                 const double xL = w > 0 ? C(5, w - 1, c) : 0.0, xR = w < S - 1 ? C(4, w + 1, c) : 0.0;
-                if (sblock) zp_finish<MMAX, FULL, true>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
-                else zp_finish<MMAX, FULL, false>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
+                zp_finish<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
             }
-        if (sblock) {
-            double tot = 0;
-            for (int w = 0; w < S; ++w) tot += zp_wsum<MMAX, FULL>(lane(w, 0), a, zseg(s.nz, S, w));
-            for (int w = 0; w < S; ++w) zp_shift<MMAX, FULL>(lane(w, 0), zseg(s.nz, S, w), tot / a.wsum);
-        }
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) zp_store<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
+        if (a.singular && blk == 0) {
+            std::vector<double> wc(s.nz), wd(s.nz);
+            ZArgs as = a;
+            as.removed = removed;
+            zsolve_singular_ws<T>(0, data, as, wc.data(), wd.data(), 1);
+        }
     }
 }
 
