@@ -454,8 +454,7 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
     const int S = (zp.threads / 64) * (64 / zp.cpb);
     const bool full = pb.nz == S * zp.mmax;  // every segment holds mmax levels
     // a FULL 16-level kernel keeps both segment sweeps unrolled in registers;
-    // at 768 threads per block it gets 168 VGPRs instead of 128 and does not
-    // spill
+    // with at most 768 threads per block its register limit is 168, not 128
     const bool small = zp.threads <= 768;
 #define CANS_ZP(MM, CPB, NT, FULLV) \
     hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, FULLV>), grid, block, 0, s, data, za, done)
