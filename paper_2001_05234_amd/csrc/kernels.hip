@@ -102,8 +102,11 @@ __device__ inline int line_level(long line, long line0, int k0, int j0, int ny)
 // EPI 0: out = v;  EPI 1: out = out + v - info[I_MEANP] (refinement update).
 // `wsum_part` (optional, forward only): block partial sums of dzf_k * in in
 // FP64, so the exact weighted mean of the rhs is known in refinement mode.
+// At least 4 waves per SIMD: the staged FP64 inverses would otherwise take
+// 145 VGPRs and run 3 (the cap costs them a small spill and is faster).
 template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
-__global__ __launch_bounds__(kThreads) void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
                                                       const cx<T> *__restrict__ tw,
                                                       const double *__restrict__ info,
                                                       const int *__restrict__ done,
