@@ -106,25 +106,29 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
 }
 
 // bf16 hi/lo split of a long double matrix (via its FP32 value)
-void split_bf16(const std::vector<long double> &W, std::vector<unsigned short> &hi, std::vector<unsigned short> &lo)
+// bf16 hi/lo parts of a row-major n x n matrix, stored k-blocked (dense_wpos)
+void split_bf16(const std::vector<long double> &W, int n, std::vector<unsigned short> &hi,
+                std::vector<unsigned short> &lo)
 {
     hi.resize(W.size());
     lo.resize(W.size());
-    for (size_t i = 0; i < W.size(); ++i) {
-        const float x = (float)W[i];
-        hi[i] = to_bf16(x);
-        lo[i] = to_bf16(x - from_bf16(hi[i]));
-    }
+    for (int q = 0; q < n; ++q)
+        for (int e = 0; e < n; ++e) {
+            const float x = (float)W[(size_t)q * n + e];
+            const unsigned short h = to_bf16(x);
+            hi[dense_wpos(n, q, e)] = h;
+            lo[dense_wpos(n, q, e)] = to_bf16(x - from_bf16(h));
+        }
 }
 
 int build_dense(cans_plan_s *pl, Axis &a)
 {
     if (!dense_ok(a.n)) return CANS_ERR_UNSUPPORTED;
     std::vector<unsigned short> hi, lo;
-    split_bf16(dense_forward(a.kind, a.n), hi, lo);
+    split_bf16(dense_forward(a.kind, a.n), a.n, hi, lo);
     CANS_TRY(upload(pl, &a.d_wf_hi, hi.data(), hi.size()));
     CANS_TRY(upload(pl, &a.d_wf_lo, lo.data(), lo.size()));
-    split_bf16(dense_inverse(a.kind, a.n), hi, lo);
+    split_bf16(dense_inverse(a.kind, a.n), a.n, hi, lo);
     CANS_TRY(upload(pl, &a.d_wi_hi, hi.data(), hi.size()));
     CANS_TRY(upload(pl, &a.d_wi_lo, lo.data(), lo.size()));
     a.dense = true;
