@@ -82,6 +82,20 @@ def time_stage(plan, stage, a, b, reps, torch):
     return s.elapsed_time(e) / reps
 
 
+def workload_text(name, pr, xform_x):
+    """What is solved: sizes, boundary pairs, grid and rhs of the problem."""
+    import numpy as np
+
+    code = "PND"
+    bc = "/".join(code[pr.bc[2 * a]] + code[pr.bc[2 * a + 1]] for a in range(3))
+    grid = "uniform z" if np.allclose(pr.dzf, pr.dzf[0]) else "tanh-stretched z (a=1.5)"
+    rhs = ("divergence of a seeded N(0,1) staggered velocity" if pr.rhs_kind == "divergence"
+           else "seeded U[-1,1]" + (", projected" if all(b in (0, 1) for b in pr.bc) else ""))
+    xf = {"auto": "FFT", "fft": "FFT", "dense": "dense split-bf16 matrix-core"}[xform_x]
+    return (f"{name}: {pr.nx}x{pr.ny}x{pr.nz}, bc {bc}, {grid}, rhs {rhs}; FP32 transforms ({xf} x), "
+            f"FP64 Thomas + residual, refined to rel. residual 1e-10")
+
+
 def run_stage(plan, stage, fd, pd, a32, reps, torch):
     """One kernel of the refinement plan in the order of a solve (reps = 0:
     a single untimed launch).  Stages 6 and 8 test the residual of pd, so the
@@ -260,9 +274,7 @@ def main():
         "metric": METRIC, "value": npts / (ms * 1e-3), "unit": "grid pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {pr.nx}x{pr.ny}x{pr.nz} channel slab, bc P/P/N, tanh z a=1.5, "
-                               f"rhs = divergence of seeded N(0,1) staggered velocity; FP32 transforms, FP64 "
-                               f"Thomas + residual, refined to rel. residual 1e-10",
+        "config": {"workload": workload_text(args.config, pr, args.xform_x),
                    "grid_points": npts, "corrections": info["iterations"],
                    "residual": info["residual"], "residual_inf": info["residual_inf"], "wall_s": wall},
     }
