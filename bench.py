@@ -82,6 +82,42 @@ def time_stage(plan, stage, a, b, reps, torch):
     return s.elapsed_time(e) / reps
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3.txt")
+
+
+def source_digest() -> str:
+    """Hash of the kernel sources (paper_2001_05234_amd/csrc), so counter
+    readings taken with other kernels are not reported as current."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2001_05234_amd", "csrc")
+    for n in sorted(os.listdir(d)):
+        if n.endswith((".h", ".hip")):
+            h.update(n.encode())
+            with open(os.path.join(d, n), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
+    by a device copy) from the committed counter summary, or None when there is
+    none or it was taken with other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [l.rstrip("\n") for l in fh if l.strip() and not l.startswith("#")]
+    except OSError:
+        return None
+    if not lines or lines[0] != "source-digest: " + source_digest():
+        return None
+    for l in lines[1:]:
+        name, fetch, write = l.split("\t")
+        if name == kernel:
+            return float(fetch) + float(write)
+    return None
+
+
 def workload_text(name, pr, xform_x):
     """What is solved: sizes, boundary pairs, grid and rhs of the problem."""
     import numpy as np
@@ -297,8 +333,11 @@ def main():
     dom = max(times, key=lambda s: counts[s] * times[s])
     dname, dbpp = [(n, b) for s, n, b in KERNELS32 if s == dom][0]
     achieved = dbpp * npts / (times[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dname) if args.config == "c3" and args.xform_x == "auto" else None
     out["roofline"] = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                       "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                       "algorithmic_bytes_per_launch": dbpp * npts,
                        "algorithmic_bytes_per_point": dbpp, "kernel_ms": times[dom]}
     out["kernels_ms"] = {n: round(times[s], 4) for s, n, _ in KERNELS32}
     plan.close()
