@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0, metavar="STAGE",
                     help="time one kernel (debug stage of the refinement plan, or of the FP64 plan with "
                          "--fp64-only) exactly as the full run times it, nothing else (profiling runs)")
+    ap.add_argument("--graph", action="store_true",
+                    help="plans replay each solve as one recorded HIP graph (cans_opts.graph)")
     ap.add_argument("--xform-x", default="auto", choices=["auto", "fft", "dense"],
                     help="x transform form of the refinement plan (dense: split-bf16 matrix-core products)")
     args = ap.parse_args()
@@ -277,7 +279,7 @@ def main():
 
     if args.fp64_only:
         plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
-                           autotune=not args.no_autotune)
+                           autotune=not args.no_autotune, graph=args.graph)
         if args.kernel_only:
             name = [n for s, n, _ in KERNELS64 if s == args.kernel_only][0]
             b = torch.zeros_like(fd)
@@ -290,7 +292,7 @@ def main():
         return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
-                     tol=1e-10, max_iter=4, autotune=not args.no_autotune, xform_x=args.xform_x)
+                     tol=1e-10, max_iter=4, autotune=not args.no_autotune, xform_x=args.xform_x, graph=args.graph)
     if args.kernel_only:
         # the stages before it fill the plan's spectral field as in a solve
         a32 = torch.zeros_like(fd)
@@ -311,7 +313,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": workload_text(args.config, pr, args.xform_x),
-                   "grid_points": npts, "corrections": info["iterations"],
+                   "grid_points": npts, "corrections": info["iterations"], "graph": args.graph,
                    "residual": info["residual"], "residual_inf": info["residual_inf"], "wall_s": wall},
     }
     if args.solve_only:
@@ -346,7 +348,7 @@ def main():
     # plain FP64 solve of the same rhs
     say("[bench] fp64 plan")
     plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
-                       autotune=not args.no_autotune)
+                       autotune=not args.no_autotune, graph=args.graph)
     ms64, _ = time_solves(plan64, fd, pd, max(1, args.steps // 2), 2, torch)
     k64 = {}
     b = torch.zeros_like(fd)

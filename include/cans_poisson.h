@@ -82,6 +82,14 @@ typedef struct cans_opts {
                            current device and keep the fastest (allocates a
                            temporary field and synchronises); 0: built-in
                            choice.  Default 0. */
+    int graph;          /* 1: cans_poisson_solve records the solve's kernel
+                           sequence into a HIP graph on its first call with a
+                           given (rhs, p) pair and replays it on later calls
+                           with the same pair (one launch per solve instead of
+                           some 5 to 35); a new pair records again.  The
+                           recording allocates graph resources on the first
+                           call.  0: kernels are launched one by one.  Batched
+                           plans always use a graph.  Default 0. */
 } cans_opts;
 
 #define CANS_HISTORY 17

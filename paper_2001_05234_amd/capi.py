@@ -34,7 +34,8 @@ EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "ca
 
 class CansOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("xform_x", ctypes.c_int), ("xform_y", ctypes.c_int),
-                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class CansInfo(ctypes.Structure):
@@ -134,7 +135,7 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, nz: int, bc, dx: float, dy: float, dzf,
                  precision: str = "fp64", tol: float = 1e-10, max_iter: int = 4, xform_x: str = "auto",
-                 autotune: bool = False):
+                 autotune: bool = False, graph: bool = False):
         lib = load()
         self._lib = lib
         self.shape = (nz, ny, nx)
@@ -145,6 +146,7 @@ class Plan:
         o.max_iter = max_iter
         o.xform_x = {"auto": XFORM_AUTO, "fft": XFORM_FFT, "dense": XFORM_DENSE}[xform_x]
         o.autotune = int(bool(autotune))
+        o.graph = int(bool(graph))
         dz = np.ascontiguousarray(np.asarray(dzf, dtype=np.float64))
         if dz.shape != (nz,):
             raise ValueError("dzf must hold nz cell widths")

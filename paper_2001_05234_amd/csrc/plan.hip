@@ -256,6 +256,7 @@ int check_opts(const cans_opts &o)
     if (o.max_iter < 0 || o.max_iter > CANS_HISTORY - 1) return CANS_ERR_INVALID_ARG;
     if (!(o.tol >= 0) || !std::isfinite(o.tol)) return CANS_ERR_INVALID_ARG;
     if (o.autotune != 0 && o.autotune != 1) return CANS_ERR_INVALID_ARG;
+    if (o.graph != 0 && o.graph != 1) return CANS_ERR_INVALID_ARG;
     for (int m : {o.xform_x, o.xform_y})
         if (m != CANS_XFORM_AUTO && m != CANS_XFORM_FFT && m != CANS_XFORM_DENSE) return CANS_ERR_INVALID_ARG;
     // the matrix-core form exists for the x axis of the refinement path
@@ -382,6 +383,7 @@ void cans_default_opts(cans_opts *o)
     o->tol = 1e-10;
     o->max_iter = 4;
     o->autotune = 0;
+    o->graph = 0;
 }
 
 const char *cans_status_string(int code)
@@ -444,6 +446,7 @@ int cans_poisson_plan_batched(cans_plan_t *out, int count, const cans_desc *desc
 int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream)
 {
     if (!plan || !rhs || !p || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
+    if (plan->opts.graph) return cans_poisson_solve_batched(plan, &rhs, &p, stream);
     const Problem &pb = plan->probs[0];
     if (plan->opts.precision == CANS_PREC_FP64) return solve_fp64(pb, rhs, p, stream);
     if ((const void *)rhs == (const void *)p) return CANS_ERR_ALIAS;

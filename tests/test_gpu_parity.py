@@ -319,3 +319,47 @@ def test_autotuned_plans(name):
     pg, info = gpu_solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine", autotune=True)
     assert info["converged"] and info["residual"] <= 1e-10
     assert rel(demean(pg, pr.bc, pr.dzf), po) < TOL_REF
+
+
+def test_graph_mode_matches_direct_launches():
+    """opts.graph: the first solve with a (rhs, p) pair records the kernel
+    sequence into a HIP graph and later solves replay it.  Replays (with
+    unrelated eager work and host synchronisations between them), a new
+    recording for new arrays, and the in-place FP64 form all give the bits of
+    direct launches."""
+    nx, ny, nz = 96, 64, 40
+    bc = (P, P, N, N, N, D)
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    f = np.random.default_rng(17).standard_normal((nz, ny, nx))
+    fd = torch.from_numpy(f).cuda()
+    for precision in ("fp64", "fp32_refine"):
+        say("graph mode", precision)
+        direct = capi.Plan(nx, ny, nz, bc, 1 / nx, 1 / ny, dzf, precision=precision)
+        graph = capi.Plan(nx, ny, nz, bc, 1 / nx, 1 / ny, dzf, precision=precision, graph=True)
+        p0 = torch.zeros_like(fd)
+        direct.solve(fd, p0)
+        torch.cuda.synchronize()
+        ref, ref_info = p0.cpu().numpy(), direct.info()
+        pg = torch.zeros_like(fd)
+        for rep in range(3):
+            pg.zero_()
+            junk = torch.randn(256, 256, device="cuda") @ torch.randn(256, 256, device="cuda")
+            torch.cuda.synchronize()
+            graph.solve(fd, pg)
+            torch.cuda.synchronize()
+            assert np.array_equal(pg.cpu().numpy(), ref), (precision, rep)
+            assert graph.info() == ref_info
+            del junk
+        pg2 = torch.zeros_like(fd)
+        graph.solve(fd, pg2)
+        torch.cuda.synchronize()
+        assert np.array_equal(pg2.cpu().numpy(), ref)
+        if precision == "fp64":
+            x = fd.clone()
+            graph.solve(x, x)
+            torch.cuda.synchronize()
+            assert np.array_equal(x.cpu().numpy(), ref)
+        po, _ = O.solve(f, bc, 1 / nx, 1 / ny, dzf)
+        assert rel(ref, po) < (1e-12 if precision == "fp64" else TOL_REF)
+        direct.close()
+        graph.close()

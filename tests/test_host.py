@@ -73,7 +73,7 @@ def test_plan_validation_spacing():
 
 def test_options_validation():
     o = capi.default_opts()
-    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4 and o.autotune == 0
+    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4 and o.autotune == 0 and o.graph == 0
     o.max_iter = 99
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.precision = 7
@@ -81,6 +81,8 @@ def test_options_validation():
     o = capi.default_opts(); o.tol = -1.0
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.autotune = 2
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.graph = 2
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.xform_y = 2
     assert _plan(128, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -2
@@ -104,3 +106,23 @@ def test_product_path_has_no_oracle_dependency():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert not pat.search(text), fn
+
+
+def _struct_fields(header: str, name: str):
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), header, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        if not decl.strip():
+            continue
+        for part in decl.split(","):  # "int nx, ny, nz" declares three fields
+            names.append(re.search(r"(\w+)\s*(\[\w+\])?\s*$", part.strip()).group(1))
+    return names
+
+
+def test_binding_structs_match_header():
+    """The ctypes structures list the header's fields in the header's order."""
+    with open(os.path.join(ROOT, "include", "cans_poisson.h")) as fh:
+        header = fh.read()
+    for cname, cls in [("cans_opts", capi.CansOpts), ("cans_info", capi.CansInfo), ("cans_desc", capi.CansDesc)]:
+        assert _struct_fields(header, cname) == [f[0] for f in cls._fields_], cname
