@@ -331,9 +331,13 @@ CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
 template <typename Coef, typename OutU, typename OutV>
 CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo)
 {
+    // forward: v_s = y2 - g2 u_{s+1}; the next segment's coefficients are
+    // read one step ahead so their latency overlaps the recurrence
     double g2p = 0, y2p = 0;
+    double A = c(0, 0), B = c(0, 1), C = c(0, 2), D = c(0, 3), E = c(0, 4), F = c(0, 5);
     for (int s = 0; s < S; ++s) {
-        const double A = c(s, 0), B = c(s, 1), C = c(s, 2), D = c(s, 3), E = c(s, 4), F = c(s, 5);
+        const int sn = s + 1 < S ? s + 1 : s;
+        const double An = c(sn, 0), Bn = c(sn, 1), Cn = c(sn, 2), Dn = c(sn, 3), En = c(sn, 4), Fn = c(sn, 5);
         const double inv = rcp64(1.0 - A * g2p);
         const double y1 = (D - A * y2p) * inv;
         const double y2 = (F - C * y2p) + C * g2p * y1;
@@ -342,14 +346,19 @@ CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo)
         c(s, 0) = y1; c(s, 1) = y2; c(s, 2) = g1; c(s, 3) = g2;
         g2p = g2;
         y2p = y2;
+        A = An; B = Bn; C = Cn; D = Dn; E = En; F = Fn;
     }
+    // backward: u_s = y1 - g1 u_{s+1}, v_s = y2 - g2 u_{s+1}
     double un = 0;
+    double y1 = c(S - 1, 0), y2 = c(S - 1, 1), g1 = c(S - 1, 2), g2 = c(S - 1, 3);
     for (int s = S - 1; s >= 0; --s) {
-        const double u = c(s, 0) - c(s, 2) * un;
-        const double v = c(s, 1) - c(s, 3) * un;
+        const int sp = s > 0 ? s - 1 : 0;
+        const double y1n = c(sp, 0), y2n = c(sp, 1), g1n = c(sp, 2), g2n = c(sp, 3);
+        const double u = y1 - g1 * un;
         uo(s) = u;
-        vo(s) = v;
+        vo(s) = y2 - g2 * un;
         un = u;
+        y1 = y1n; y2 = y2n; g1 = g1n; g2 = g2n;
     }
 }
 
