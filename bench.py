@@ -250,6 +250,7 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0, metavar="STAGE",
                     help="time one kernel (debug stage of the refinement plan, or of the FP64 plan with "
                          "--fp64-only) exactly as the full run times it, nothing else (profiling runs)")
+    ap.add_argument("--batched-only", action="store_true", help="time the 64-problem batch only (profiling runs)")
     ap.add_argument("--graph", action="store_true",
                     help="plans replay each solve as one recorded HIP graph (cans_opts.graph)")
     ap.add_argument("--xform-x", default="auto", choices=["auto", "fft", "dense"],
@@ -270,6 +271,9 @@ def main():
         print(json.dumps({"copy_GBps": copy_gbs(torch, 1 << 30), "bytes_per_copy": 2 * (1 << 30)}), flush=True)
         return
     capi.load()
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(torch, capi, inputs, args)}), flush=True)
+        return
     pr = inputs.config(args.config)
     say(f"[bench] generating {args.config} rhs {pr.nx}x{pr.ny}x{pr.nz}")
     f = pr.rhs()

@@ -394,12 +394,14 @@ static ZArgs zargs(const Problem &pb, double *removed);
 // Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
 // into S segments of at most MMAX levels held in registers; a wave holds
 // 64/CPB segments of the same columns (see zsolve_core.h).
-template <typename T, int MMAX, int CPB, int NTMAX, bool FULL>
+template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC>
 __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const int *__restrict__ done)
 {
     if (done && *done) return;
-    __shared__ double coef[6 * 1024];
+    constexpr int NQ = CYC ? 8 : 6;  // interface coefficients per segment
+    __shared__ double coef[NQ * 1024];
     __shared__ double zabc[3 * 512];  // the z coefficients, staged once per block
+    __shared__ double ends[CYC ? 4 * 64 : 1];  // CYC: first/last values per column
     constexpr int SPW = 64 / CPB;  // segments per wave
     for (int i = threadIdx.x; i < ag.nz; i += blockDim.x) {
         zabc[i] = ag.za[i];
@@ -418,22 +420,37 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     auto C = [&](int q, int s) -> double & { return coef[q * 1024 + s * CPB + c]; };
     const size_t col = (size_t)blockIdx.x * CPB + c;
     const ZSeg sg = zseg(a.nz, S, seg);
-    ZLane<MMAX> L;
+    ZLane<MMAX, CYC> L;
     zp_load<MMAX, FULL>(L, data, a, col, sg);
-    double out[6];
+    double out[NQ];
     zp_reduce<MMAX, FULL>(L, a, sg, out);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) C(q, seg) = out[q];
+    for (int q = 0; q < NQ; ++q) C(q, seg) = out[q];
     __syncthreads();
     if (w == 0 && lane < CPB) {
-        zp_interface(
+        zp_interface<CYC>(
             S, [&](int s, int q) -> double & { return C(q, s); }, [&](int s) -> double & { return C(4, s); },
-            [&](int s) -> double & { return C(5, s); });
+            [&](int s) -> double & { return C(5, s); }, [&](int s) -> double & { return C(6, s); },
+            [&](int s) -> double & { return C(7, s); });
     }
     __syncthreads();
     const double xL = seg > 0 ? C(5, seg - 1) : 0.0;
     const double xR = seg < S - 1 ? C(4, seg + 1) : 0.0;
-    zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
+    if constexpr (CYC) {
+        const double xL2 = seg > 0 ? C(7, seg - 1) : 0.0;
+        const double xR2 = seg < S - 1 ? C(6, seg + 1) : 0.0;
+        zp_finish<MMAX, FULL>(L, a, sg, xL, xR, xL2, xR2);
+        // Sherman-Morrison: the column's first and last values of A'^-1 f and
+        // A'^-1 u come from its first and last segment
+        double y0, z0, yl, zl;
+        zp_ends<MMAX, FULL>(L, sg, &y0, &z0, &yl, &zl);
+        if (seg == 0) { ends[c] = y0; ends[64 + c] = z0; }
+        if (seg == S - 1) { ends[128 + c] = yl; ends[192 + c] = zl; }
+        __syncthreads();
+        zp_sherman_morrison<MMAX, FULL>(L, a, sg, ends[c], ends[64 + c], ends[128 + c], ends[192 + c]);
+    } else {
+        zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
+    }
     zp_store<MMAX, FULL>(L, data, a, col, sg);
     if (a.singular && blockIdx.x == 0) {
         // the singular column, left out above: projected rhs, pinned last
@@ -447,7 +464,7 @@ template <typename T>
 static int launch_zsolve(const Problem &pb, T *data, double *removed, const int *done, hipStream_t s)
 {
     const size_t plane = (size_t)pb.nx * pb.ny;
-    const ZPart zp = pb.cyclic ? ZPart{0, 0, 0} : zpart_shape(pb.nz);
+    const ZPart zp = zpart_shape(pb.nz, pb.cyclic != 0);
     ZArgs za = zargs(pb, removed);
     if (zp.mmax == 0) {
         hipLaunchKernelGGL(k_zsolve<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data, za, done);
@@ -459,8 +476,15 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
     // a FULL 16-level kernel keeps both segment sweeps unrolled in registers;
     // with at most 768 threads per block its register limit is 168, not 128
     const bool small = zp.threads <= 768;
+#define CANS_ZP(MM, CPB, NT, FULLV, CYCV) \
+    hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, FULLV, CYCV>), grid, block, 0, s, data, za, done)
+    if (pb.cyclic) {  // nz <= 128: 8-level segments of 64 columns
+        if (full) CANS_ZP(8, 64, 1024, true, true); else CANS_ZP(8, 64, 1024, false, true);
+        return check_launch();
+    }
+#undef CANS_ZP
 #define CANS_ZP(MM, CPB, NT, FULLV) \
-    hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, FULLV>), grid, block, 0, s, data, za, done)
+    hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, FULLV, false>), grid, block, 0, s, data, za, done)
     if (zp.mmax == 8) {
         if (full) CANS_ZP(8, 64, 1024, true); else CANS_ZP(8, 64, 1024, false);
     } else if (zp.cpb == 64) {

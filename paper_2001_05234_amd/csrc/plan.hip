@@ -228,10 +228,10 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     CANS_TRY(upload(pl, &pb.d_zaf, af.data(), nz));
     CANS_TRY(upload(pl, &pb.d_zcf, cf.data(), nz));
     CANS_TRY(upload(pl, &pb.d_dzf, pb.dzf.data(), nz));
-    // workspace of the plain elimination (periodic z, or nz beyond the
-    // register-resident partitioned solve): multipliers and modified rhs
+    // workspace of the plain elimination (nz beyond the register-resident
+    // partitioned solve): multipliers and modified rhs
     const size_t N = pb.npts();
-    if (pb.cyclic || zpart_shape(nz).mmax == 0) {
+    if (zpart_shape(nz, pb.cyclic != 0).mmax == 0) {
         CANS_TRY(alloc(pl, &pb.wc, N));
         CANS_TRY(alloc(pl, &pb.wd, N));
         if (pb.cyclic) CANS_TRY(alloc(pl, &pb.wz, N));

@@ -249,26 +249,36 @@ CANS_HD ZSeg zseg(int nz, int S, int w)
     return s;
 }
 
-// row coefficients of level k for a lane
-CANS_HD void zrow(const ZArgs &a, int k, double lam, double &ak, double &bk, double &ck)
+// Row coefficients of level k for a lane.  CYC (periodic z): the rows of the
+// tridiagonal part A' of the cyclic matrix A = A' + u v^T (Sherman-Morrison,
+// u = (gam, 0.., c_{n-1}), v = (1, 0.., a_0/gam), gam = -(b_0 + lam)): the
+// wrap couplings dropped and folded into the first and last diagonals.
+template <bool CYC>
+CANS_HD void zrow(const ZArgs &a, int k, double lam, double gam, double &ak, double &bk, double &ck)
 {
     ak = a.za[k];
     bk = a.zb[k] + lam;
     ck = a.zc[k];
+    if (CYC) {
+        if (k == 0) { ak = 0.0; bk -= gam; }
+        if (k == a.nz - 1) { ck = 0.0; bk -= a.zc[k] * a.za[0] / gam; }
+    }
 }
 
 // FULL: every segment has exactly MMAX levels, so the level guards fold away.
-template <int MMAX>
+// CYC: a second right-hand side u (Sherman-Morrison) is carried beside f.
+template <int MMAX, bool CYC = false>
 struct ZLane {
-    double f[MMAX];   // rhs, later the forward-swept rhs, later x
-    double r[MMAX];   // reciprocal pivots of the top-down sweep
-    double lam;
+    double f[MMAX];                // rhs, later the forward-swept rhs, later x
+    double r[MMAX];                // reciprocal pivots of the top-down sweep
+    double u[CYC ? MMAX : 1];      // CYC: u, later A'^{-1} u
+    double lam, gam;
     bool valid;
 };
 
 // load the segment's rhs (scaled) and the column's lambda
-template <int MMAX, bool FULL, typename T>
-CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, ZSeg sg)
+template <int MMAX, bool FULL, typename T, bool CYC>
+CANS_HD void zp_load(ZLane<MMAX, CYC> &L, const T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
     const size_t plane = (size_t)a.nx * a.ny;
     // the singular column (singular problems, column 0) is solved apart
@@ -276,32 +286,44 @@ CANS_HD void zp_load(ZLane<MMAX> &L, const T *data, const ZArgs &a, size_t col, 
     // 32-bit index arithmetic: a plane holds at most 4096 x 4096 columns
     const unsigned cu = L.valid ? (unsigned)col : 0u, nxu = (unsigned)a.nx;
     L.lam = L.valid ? a.lamx[cu % nxu] + a.lamy[cu / nxu] : -1.0;
+    L.gam = -(a.zb[0] + L.lam);
     const T *ptr = data + (L.valid ? col : 0) + plane * sg.k0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
-        if (FULL || t < sg.m) L.f[t] = L.valid ? a.scale * (double)ptr[0] : 0.0;
+        if (FULL || t < sg.m) {
+            L.f[t] = L.valid ? a.scale * (double)ptr[0] : 0.0;
+            if constexpr (CYC) {
+                const int k = sg.k0 + t;
+                L.u[t] = (k == 0 ? L.gam : 0.0) + (k == a.nz - 1 ? a.zc[a.nz - 1] : 0.0);
+            }
+        }
         ptr += plane;
     }
 }
 
-// step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F.
+// step 1: both sweeps over the segment; out[0..5] = A, B, C, D, E, F, and
+// for CYC out[6], out[7] = D, F of the second right-hand side.
 // The top-down sweep (level i) and the bottom-up sweep (level MMAX-1-i, live
 // once it is below m) run in one unrolled loop: two independent dependency
 // chains for the scheduler to interleave.
-template <int MMAX, bool FULL>
-CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
+template <int MMAX, bool FULL, bool CYC>
+CANS_HD void zp_reduce(ZLane<MMAX, CYC> &L, const ZArgs &a, ZSeg sg, double *out)
 {
-    double cp = 0, d = 0, g = 0;    // top-down: c', d', fill-in of xL
-    double ep = 0, dd = 0, h = 0;   // bottom-up: a'', d'', fill-in of xR
+    double cp = 0, d = 0, g = 0, d2 = 0;    // top-down: c', d' (f, u), fill-in of xL
+    double ep = 0, dd = 0, h = 0, dd2 = 0;  // bottom-up: a'', d'' (f, u), fill-in of xR
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) {
         const int t = i;
         if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, ak, bk, ck);
+            zrow<CYC>(a, sg.k0 + t, L.lam, L.gam, ak, bk, ck);
             const double rr = rcp64(t == 0 ? bk : bk - ak * cp);
             L.r[t] = rr;
             d = (t == 0 ? L.f[t] : L.f[t] - ak * d) * rr;
+            if constexpr (CYC) {
+                d2 = (t == 0 ? L.u[t] : L.u[t] - ak * d2) * rr;
+                zp_pin(d2);  // u is zero inside: a running product
+            }
             g = (t == 0 ? ak : -ak * g) * rr;
             zp_pin(g);
             cp = ck * rr;
@@ -309,10 +331,14 @@ CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
         const int u = MMAX - 1 - i;
         if (FULL || u < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + u, L.lam, ak, bk, ck);
+            zrow<CYC>(a, sg.k0 + u, L.lam, L.gam, ak, bk, ck);
             const bool last = FULL ? (u == MMAX - 1) : (u == sg.m - 1);
             const double rr = rcp64(last ? bk : bk - ck * ep);
             dd = (last ? L.f[u] : L.f[u] - ck * dd) * rr;
+            if constexpr (CYC) {
+                dd2 = (last ? L.u[u] : L.u[u] - ck * dd2) * rr;
+                zp_pin(dd2);
+            }
             h = (last ? ck : -ck * h) * rr;
             zp_pin(h);
             ep = ak * rr;
@@ -324,72 +350,137 @@ CANS_HD void zp_reduce(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double *out)
     out[3] = dd;  // D
     out[4] = cp;  // E
     out[5] = d;   // F
+    if constexpr (CYC) {
+        out[6] = dd2;
+        out[7] = d2;
+    }
 }
 
 // step 2: the reduced system of one column over its S segments.
-// c(s, q) addresses coefficient q of segment s; u(s), v(s) receive the ends.
-template <typename Coef, typename OutU, typename OutV>
-CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo)
+// c(s, q) addresses coefficient q of segment s; u(s), v(s) receive the ends
+// (CYC: u2(s), v2(s) those of the second right-hand side, whose D, F are
+// c(s, 6), c(s, 7)).
+template <bool CYC, typename Coef, typename OutU, typename OutV, typename OutU2, typename OutV2>
+CANS_HD void zp_interface(int S, Coef c, OutU uo, OutV vo, OutU2 uo2, OutV2 vo2)
 {
     // forward: v_s = y2 - g2 u_{s+1}; the next segment's coefficients are
     // read one step ahead so their latency overlaps the recurrence
-    double g2p = 0, y2p = 0;
+    double g2p = 0, y2p = 0, w2p = 0;
     double A = c(0, 0), B = c(0, 1), C = c(0, 2), D = c(0, 3), E = c(0, 4), F = c(0, 5);
+    double D2 = CYC ? c(0, 6) : 0.0, F2 = CYC ? c(0, 7) : 0.0;
     for (int s = 0; s < S; ++s) {
         const int sn = s + 1 < S ? s + 1 : s;
         const double An = c(sn, 0), Bn = c(sn, 1), Cn = c(sn, 2), Dn = c(sn, 3), En = c(sn, 4), Fn = c(sn, 5);
+        const double D2n = CYC ? c(sn, 6) : 0.0, F2n = CYC ? c(sn, 7) : 0.0;
         const double inv = rcp64(1.0 - A * g2p);
         const double y1 = (D - A * y2p) * inv;
         const double y2 = (F - C * y2p) + C * g2p * y1;
         const double g1 = B * inv;
         const double g2 = E + C * g2p * g1;
         c(s, 0) = y1; c(s, 1) = y2; c(s, 2) = g1; c(s, 3) = g2;
+        if constexpr (CYC) {
+            const double w1 = (D2 - A * w2p) * inv;
+            const double w2 = (F2 - C * w2p) + C * g2p * w1;
+            c(s, 6) = w1; c(s, 7) = w2;
+            w2p = w2;
+        }
         g2p = g2;
         y2p = y2;
-        A = An; B = Bn; C = Cn; D = Dn; E = En; F = Fn;
+        A = An; B = Bn; C = Cn; D = Dn; E = En; F = Fn; D2 = D2n; F2 = F2n;
     }
     // backward: u_s = y1 - g1 u_{s+1}, v_s = y2 - g2 u_{s+1}
-    double un = 0;
+    double un = 0, un2 = 0;
     double y1 = c(S - 1, 0), y2 = c(S - 1, 1), g1 = c(S - 1, 2), g2 = c(S - 1, 3);
+    double w1 = CYC ? c(S - 1, 6) : 0.0, w2 = CYC ? c(S - 1, 7) : 0.0;
     for (int s = S - 1; s >= 0; --s) {
         const int sp = s > 0 ? s - 1 : 0;
         const double y1n = c(sp, 0), y2n = c(sp, 1), g1n = c(sp, 2), g2n = c(sp, 3);
+        const double w1n = CYC ? c(sp, 6) : 0.0, w2n = CYC ? c(sp, 7) : 0.0;
         const double u = y1 - g1 * un;
         uo(s) = u;
         vo(s) = y2 - g2 * un;
         un = u;
-        y1 = y1n; y2 = y2n; g1 = g1n; g2 = g2n;
+        if constexpr (CYC) {
+            const double u2 = w1 - g1 * un2;
+            uo2(s) = u2;
+            vo2(s) = w2 - g2 * un2;
+            un2 = u2;
+        }
+        y1 = y1n; y2 = y2n; g1 = g1n; g2 = g2n; w1 = w1n; w2 = w2n;
     }
 }
 
-// step 3: x of the segment from its outside neighbours xL, xR
-template <int MMAX, bool FULL>
-CANS_HD void zp_finish(ZLane<MMAX> &L, const ZArgs &a, ZSeg sg, double xL, double xR)
+// step 3: x of the segment from its outside neighbours xL, xR (CYC: also the
+// second right-hand side's, xL2, xR2)
+template <int MMAX, bool FULL, bool CYC>
+CANS_HD void zp_finish(ZLane<MMAX, CYC> &L, const ZArgs &a, ZSeg sg, double xL, double xR, double xL2 = 0.0,
+                       double xR2 = 0.0)
 {
-    double d = xL;
+    double d = xL, d2 = xL2;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
         if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, ak, bk, ck);
+            zrow<CYC>(a, sg.k0 + t, L.lam, L.gam, ak, bk, ck);
             d = (L.f[t] - ak * d) * L.r[t];
             L.f[t] = d;
+            if constexpr (CYC) {
+                d2 = (L.u[t] - ak * d2) * L.r[t];
+                zp_pin(d2);
+                L.u[t] = d2;
+            }
         }
     }
-    double x = xR;
+    double x = xR, x2 = xR2;
 #pragma unroll
     for (int t = MMAX - 1; t >= 0; --t) {
         if (FULL || t < sg.m) {
             double ak, bk, ck;
-            zrow(a, sg.k0 + t, L.lam, ak, bk, ck);
+            zrow<CYC>(a, sg.k0 + t, L.lam, L.gam, ak, bk, ck);
             x = L.f[t] - ck * L.r[t] * x;
             L.f[t] = x;
+            if constexpr (CYC) {
+                x2 = L.u[t] - ck * L.r[t] * x2;
+                zp_pin(x2);
+                L.u[t] = x2;
+            }
         }
     }
 }
 
-template <int MMAX, bool FULL, typename T>
-CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col, ZSeg sg)
+// CYC: first and last values of y = A'^{-1} f and z = A'^{-1} u in this
+// segment (meaningful in the first and the last segment)
+template <int MMAX, bool FULL, bool CYC>
+CANS_HD void zp_ends(const ZLane<MMAX, CYC> &L, ZSeg sg, double *y0, double *z0, double *yl, double *zl)
+{
+    *y0 = L.f[0];
+    *z0 = CYC ? L.u[0] : 0.0;
+    *yl = 0.0;
+    *zl = 0.0;
+#pragma unroll
+    for (int t = 0; t < MMAX; ++t)
+        if ((FULL && t == MMAX - 1) || (!FULL && t == sg.m - 1)) {
+            *yl = L.f[t];
+            if constexpr (CYC) *zl = L.u[t];
+        }
+}
+
+// CYC: x = y - z (v.y) / (1 + v.z) with v = (1, 0.., a_0/gam)
+template <int MMAX, bool FULL, bool CYC>
+CANS_HD void zp_sherman_morrison(ZLane<MMAX, CYC> &L, const ZArgs &a, ZSeg sg, double y0, double z0, double yl,
+                                 double zl)
+{
+    if constexpr (CYC) {
+        const double w = a.za[0] / L.gam;
+        const double fac = (y0 + w * yl) / (1.0 + z0 + w * zl);
+#pragma unroll
+        for (int t = 0; t < MMAX; ++t)
+            if (FULL || t < sg.m) L.f[t] -= fac * L.u[t];
+    }
+}
+
+template <int MMAX, bool FULL, typename T, bool CYC>
+CANS_HD void zp_store(const ZLane<MMAX, CYC> &L, T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
     if (!L.valid) return;
     const size_t plane = (size_t)a.nx * a.ny;
@@ -407,7 +498,7 @@ CANS_HD void zp_store(const ZLane<MMAX> &L, T *data, const ZArgs &a, size_t col,
 //   nz <= 256: 64 columns, segments of <= 16 levels;
 //   nz <= 512: 32 columns (two segments per wave), segments of <= 16 levels.
 // mmax = 0 when nz > 512 (the plain elimination with a workspace is used
-// then, and for periodic z).
+// then).  Periodic z uses the same shapes with the cyclic (CYC) form.
 struct ZPart {
     int mmax, cpb, threads;
 };
@@ -422,6 +513,19 @@ inline ZPart zpart_shape(int nz)
     }
     return ZPart{0, 0, 0};
 }
+
+// Periodic z carries a second right-hand side (Sherman-Morrison): segments of
+// <= 8 levels, 64 columns, up to nz = 128.  Deeper periodic columns use the
+// plain elimination: there the combination of the two partitioned solutions
+// lost up to 3x the accuracy of the sequential one on the ill-conditioned
+// low-wavenumber columns (measured against the long-double oracle).
+inline ZPart zpart_shape_cyc(int nz)
+{
+    if (nz <= 128) return ZPart{8, 64, 64 * ((nz + 7) / 8)};
+    return ZPart{0, 0, 0};
+}
+
+inline ZPart zpart_shape(int nz, bool cyclic) { return cyclic ? zpart_shape_cyc(nz) : zpart_shape(nz); }
 
 inline int zpart_mmax(int nz) { return zpart_shape(nz).mmax; }
 

@@ -162,33 +162,48 @@ void solve_pass(Setup &s, std::vector<T> &a, double *removed)
 
 // the partitioned z kernel, phase by phase over all segments and columns of a
 // block (CPB columns, S segments); the singular column is solved apart
-template <int MMAX, bool FULL, typename T>
+template <int MMAX, bool FULL, bool CYC, typename T>
 void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
 {
     const ZArgs &a = s.z;
     const size_t plane = (size_t)s.nx * s.ny;
-    std::vector<ZLane<MMAX>> L((size_t)S * cpb);
-    std::vector<double> coef(6 * 1024);
+    constexpr int NQ = CYC ? 8 : 6;
+    std::vector<ZLane<MMAX, CYC>> L((size_t)S * cpb);
+    std::vector<double> coef(NQ * 1024);
     auto C = [&](int q, int seg, int c) -> double & { return coef[q * 1024 + seg * cpb + c]; };
-    auto lane = [&](int seg, int c) -> ZLane<MMAX> & { return L[(size_t)seg * cpb + c]; };
+    auto lane = [&](int seg, int c) -> ZLane<MMAX, CYC> & { return L[(size_t)seg * cpb + c]; };
     for (size_t blk = 0; blk * cpb < plane; ++blk) {
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) zp_load<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
-                double out[6];
+                double out[NQ];
                 zp_reduce<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), out);
-                for (int q = 0; q < 6; ++q) C(q, w, c) = out[q];
+                for (int q = 0; q < NQ; ++q) C(q, w, c) = out[q];
             }
         for (int c = 0; c < cpb; ++c)
-            zp_interface(
+            zp_interface<CYC>(
                 S, [&](int sg, int q) -> double & { return C(q, sg, c); },
-                [&](int sg) -> double & { return C(4, sg, c); }, [&](int sg) -> double & { return C(5, sg, c); });
+                [&](int sg) -> double & { return C(4, sg, c); }, [&](int sg) -> double & { return C(5, sg, c); },
+                [&](int sg) -> double & { return C(6 % NQ, sg, c); }, [&](int sg) -> double & { return C(7 % NQ, sg, c); });
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
                 const double xL = w > 0 ? C(5, w - 1, c) : 0.0, xR = w < S - 1 ? C(4, w + 1, c) : 0.0;
-                zp_finish<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
+                if constexpr (CYC) {
+                    const double xL2 = w > 0 ? C(7, w - 1, c) : 0.0, xR2 = w < S - 1 ? C(6, w + 1, c) : 0.0;
+                    zp_finish<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), xL, xR, xL2, xR2);
+                } else {
+                    zp_finish<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
+                }
             }
+        if constexpr (CYC) {
+            for (int c = 0; c < cpb; ++c) {
+                double y0, z0, yl, zl, t0, t1;
+                zp_ends<MMAX, FULL>(lane(0, c), zseg(s.nz, S, 0), &y0, &z0, &t0, &t1);
+                zp_ends<MMAX, FULL>(lane(S - 1, c), zseg(s.nz, S, S - 1), &t0, &t1, &yl, &zl);
+                for (int w = 0; w < S; ++w) zp_sherman_morrison<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), y0, z0, yl, zl);
+            }
+        }
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) zp_store<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
         if (a.singular && blk == 0) {
@@ -204,16 +219,19 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
 template <typename T>
 bool zsolve_part_any(Setup &s, T *data, double *removed)
 {
-    const ZPart zp = s.z.cyclic ? ZPart{0, 0, 0} : zpart_shape(s.nz);
+    const ZPart zp = zpart_shape(s.nz, s.z.cyclic != 0);
     if (zp.mmax == 0) return false;
     const int S = (zp.threads / 64) * (64 / zp.cpb);
     const bool full = s.nz == S * zp.mmax;
-    if (zp.mmax == 8) {
-        if (full) zsolve_part_mm<8, true>(s, data, removed, zp.cpb, S);
-        else zsolve_part_mm<8, false>(s, data, removed, zp.cpb, S);
+    if (s.z.cyclic) {
+        if (full) zsolve_part_mm<8, true, true>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<8, false, true>(s, data, removed, zp.cpb, S);
+    } else if (zp.mmax == 8) {
+        if (full) zsolve_part_mm<8, true, false>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<8, false, false>(s, data, removed, zp.cpb, S);
     } else {
-        if (full) zsolve_part_mm<16, true>(s, data, removed, zp.cpb, S);
-        else zsolve_part_mm<16, false>(s, data, removed, zp.cpb, S);
+        if (full) zsolve_part_mm<16, true, false>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<16, false, false>(s, data, removed, zp.cpb, S);
     }
     return true;
 }

@@ -122,8 +122,25 @@ def test_zsolve_partitioned(nz):
             phl, _ = O.spectral_solve(fh, bc, 0.3, 0.5, dzf, ld=True)
             assert rel(pe * s, phl) < 2 * rel(ph, phl), (nz, bc, e)
         assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
-    # periodic z (and nz > 512) use the plain elimination
-    assert emu.zsolve_part(fh, (P, P, N, N, P, P), 0.3, 0.5, np.full(nz, 0.1)) is None
+    # periodic z: the cyclic (Sherman-Morrison) form of the same kernel, uniform
+    # z, nz <= 128 (deeper periodic columns use the plain elimination)
+    if 3 <= nz <= 128:
+        for bc in [(P, P, N, N, P, P), (P, P, P, P, P, P), (D, N, D, D, P, P)]:
+            dzf = np.full(nz, 2.0 / nz)
+            fh = rng.standard_normal((nz, 6, 22))
+            ph, rem = O.spectral_solve(fh, bc, 0.3, 0.5, dzf)
+            kx, ky = O.axis_kind(bc[0], bc[1]), O.axis_kind(bc[2], bc[3])
+            res = emu.zsolve_part(fh, bc, 0.3, 0.5, dzf)
+            assert res is not None
+            pe, reme = res
+            s = scale(kx, 22) * scale(ky, 6)
+            e = rel(pe * s, ph)
+            if e >= 1e-12:
+                phl, _ = O.spectral_solve(fh, bc, 0.3, 0.5, dzf, ld=True)
+                assert rel(pe * s, phl) < 2 * rel(ph, phl), (nz, bc, e)
+            assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
+    if nz > 128:
+        assert emu.zsolve_part(fh, (P, P, N, N, P, P), 0.3, 0.5, np.full(nz, 0.1)) is None
 
 
 def test_c1_refine_converges():

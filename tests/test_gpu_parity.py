@@ -147,13 +147,24 @@ def test_fp64_shapes(shape):
         check_fp64(pg, f, bc, 0.3, 0.7, dzf)
 
 
-def test_periodic_z_cyclic():
-    rng = np.random.default_rng(9)
+@pytest.mark.parametrize("nz", [3, 12, 64, 97, 128, 200])
+def test_periodic_z_cyclic(nz):
+    """Periodic z: the cyclic (Sherman-Morrison) partitioned kernel up to 128
+    levels (full and ragged segments, partial column blocks), the plain
+    elimination beyond; singular and nonsingular columns; refinement too."""
+    rng = np.random.default_rng(9 + nz)
+    dzf = np.full(nz, 1.0 / nz)
     for bc in [(D, D, N, D, P, P), (P, P, P, P, P, P), (N, N, P, P, P, P)]:
-        f = rng.standard_normal((12, 10, 8))
-        say("cyclic z", bc)
-        pg, _ = gpu_solve(f, bc, 0.3, 0.2, np.full(12, 0.25))
-        check_fp64(pg, f, bc, 0.3, 0.2, np.full(12, 0.25))
+        f = rng.standard_normal((nz, 10, 12))
+        say("cyclic z", nz, bc)
+        pg, _ = gpu_solve(f, bc, 0.3, 0.2, dzf)
+        check_fp64(pg, f, bc, 0.3, 0.2, dzf)
+    bc = (P, P, N, N, P, P)
+    f = rng.standard_normal((nz, 10, 12))
+    po, _ = O.solve(f, bc, 0.3, 0.2, dzf)
+    pg, info = gpu_solve(f, bc, 0.3, 0.2, dzf, precision="fp32_refine", tol=1e-10, max_iter=6)
+    assert info["converged"] and info["residual"] <= 1e-10, info
+    assert rel(demean(pg, bc, dzf), po) < TOL_REF
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
