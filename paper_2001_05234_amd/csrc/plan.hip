@@ -20,7 +20,7 @@ using namespace cans;
 // kBranches capture streams (largest first, each to the least loaded branch)
 // so independent problems execute concurrently, and the whole batch is a
 // single hipGraphLaunch on the caller's stream.
-constexpr int kBranches = 4;
+constexpr int kBranches = 8;
 
 struct BatchGraph {
     hipGraphExec_t exec = nullptr;
@@ -295,7 +295,7 @@ std::vector<int> assign_branches(const std::vector<Problem> &probs)
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return probs[a].npts() > probs[b].npts(); });
-    double load[kBranches] = {0, 0, 0, 0};
+    double load[kBranches] = {};
     for (int i : order) {
         int best = 0;
         for (int b = 1; b < kBranches; ++b)
