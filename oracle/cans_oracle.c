@@ -302,7 +302,9 @@ void SYM(oracle_transform)(int axis, int inverse, int kind, int nx, int ny, int 
 /*
  * Solve the tridiagonal systems of eq. (poi_reduced) for every (i,j) column
  * of a spectral field fh (x and y already transformed), in place.
- *   lambda(i,j) = mu_x(i)/dx^2 + mu_y(j)/dy^2 is added to the z diagonal.
+ *   lambda(i,j) = mu_x(i)/dx^2 + mu_y(j)/dy^2 + shift is added to the z
+ *   diagonal (shift: the Helmholtz form (L_h + shift) p = f of implicit
+ *   diffusion, the same expansion with the diagonal moved; shift <= 0).
  * Singular column: all three axes are P or NN and (i,j) is the constant row
  * of both x and y.  Then the column is projected onto the range
  * (fh_k -= sum_k w_k fh_k / sum_k w_k, w = dzf, the left null vector of the
@@ -311,7 +313,7 @@ void SYM(oracle_transform)(int axis, int inverse, int kind, int nx, int ny, int 
  * spectral column is returned in *removed (0 when nothing is singular).
  */
 static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double dx, double dy,
-                               const double *dzf, REAL *fh, REAL *removed)
+                               const double *dzf, double shift, REAL *fh, REAL *removed)
 {
     int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
     int kz = SYM(oracle_axis_kind)(bc[4], bc[5]);
@@ -323,7 +325,8 @@ static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double d
     REAL *za = malloc(sizeof(REAL) * 3 * nz), *zb = za + nz, *zc = za + 2 * nz;
     zcoef_real(nz, bc[4], bc[5], dzf, za, zb, zc);
     int zx = zero_row(kx), zy = zero_row(ky);
-    int z_singular = (kz == K_P || kz == K_NN);
+    /* a nonzero shift (Helmholtz) leaves no singular column */
+    int z_singular = (kz == K_P || kz == K_NN) && shift == 0.0;
     int cyclic = (kz == K_P);
     REAL wsum = 0;
     for (int k = 0; k < nz; ++k) wsum += dzf[k];
@@ -336,7 +339,7 @@ static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double d
         #pragma omp for schedule(static)
         for (long col = 0; col < (long)plane; ++col) {
             int i = (int)(col % nx), j = (int)(col / nx);
-            REAL lam = mux[i] / ((REAL)dx * dx) + muy[j] / ((REAL)dy * dy);
+            REAL lam = mux[i] / ((REAL)dx * dx) + muy[j] / ((REAL)dy * dy) + (REAL)shift;
             for (int k = 0; k < nz; ++k) { d[k] = fh[col + plane * k]; bb[k] = zb[k] + lam; }
             int singular = z_singular && i == zx && j == zy;
             if (singular) {
@@ -384,11 +387,11 @@ static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double d
 }
 
 int SYM(oracle_spectral_solve)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
-                               const double *dzf, const double *fh, double *ph, double *removed)
+                               const double *dzf, double shift, const double *fh, double *ph, double *removed)
 {
     size_t N = (size_t)nx * ny * nz;
     REAL *a = to_real(fh, N), rem = 0;
-    int rc = spectral_solve_real(nx, ny, nz, bc, dx, dy, dzf, a, &rem);
+    int rc = spectral_solve_real(nx, ny, nz, bc, dx, dy, dzf, shift, a, &rem);
     from_real(a, ph, N);
     if (removed) *removed = (double)rem;
     free(a);
@@ -403,7 +406,7 @@ int SYM(oracle_spectral_solve)(int nx, int ny, int nz, const int bc[6], double d
  * rows of P and NN are all ones.
  */
 int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
-                      const double *dzf, const double *f, double *p, double *info)
+                      const double *dzf, double shift, const double *f, double *p, double *info)
 {
     int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
     if (kx < 0 || ky < 0 || SYM(oracle_axis_kind)(bc[4], bc[5]) < 0) return -1;
@@ -416,7 +419,7 @@ int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double
     REAL *a = to_real(f, N), *b = malloc(sizeof(REAL) * N), rem = 0;
     apply_along(0, nx, ny, nz, Tx, a, b);
     apply_along(1, nx, ny, nz, Ty, b, a);
-    int rc = spectral_solve_real(nx, ny, nz, bc, dx, dy, dzf, a, &rem);
+    int rc = spectral_solve_real(nx, ny, nz, bc, dx, dy, dzf, shift, a, &rem);
     apply_along(1, nx, ny, nz, Tiy, a, b);
     apply_along(0, nx, ny, nz, Tix, b, a);
     from_real(a, p, N);
@@ -426,11 +429,11 @@ int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double
 }
 
 /*
- * out = L_h p, the 7-point operator of eq. (poi) with the z part in the
- * conservative form above and the ghost rules of each face.
+ * out = L_h p + shift p, the 7-point operator of eq. (poi) with the z part
+ * in the conservative form above and the ghost rules of each face.
  */
 void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
-                         const double *dzf, const double *p, double *out)
+                         const double *dzf, double shift, const double *p, double *out)
 {
     REAL *zaf = malloc(sizeof(REAL) * 2 * nz), *zcf = zaf + nz;
     /* full (unfolded) z coefficients: a/c before the ghost is folded in */
@@ -458,7 +461,7 @@ void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, dou
             zp = k < nz - 1 ? P3(i, j, k + 1) : bc[5] == BC_P ? P3(i, j, 0) : bc[5] == BC_N ? c0 : -c0;
 #undef P3
             REAL v = (xm - 2 * c0 + xp) * ix2 + (ym - 2 * c0 + yp) * iy2
-                   + zcf[k] * (zp - c0) - zaf[k] * (c0 - zm);
+                   + zcf[k] * (zp - c0) - zaf[k] * (c0 - zm) + (REAL)shift * c0;
             out[i + (size_t)nx * (j + (size_t)ny * k)] = (double)v;
         }
     }

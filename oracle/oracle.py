@@ -59,9 +59,9 @@ def _lib(ld: bool = False):
             "oracle_zcoef": ([i, i, i, dp, dp, dp, dp], i),
             "oracle_tridiag": ([i, dp, dp, dp, dp, dp, i], None),
             "oracle_transform": ([i, i, i, i, i, i, dp, dp], None),
-            "oracle_spectral_solve": ([i, i, i, ip, d, d, dp, dp, dp, dp], i),
-            "oracle_solve": ([i, i, i, ip, d, d, dp, dp, dp, dp], i),
-            "oracle_apply_L": ([i, i, i, ip, d, d, dp, dp, dp], None),
+            "oracle_spectral_solve": ([i, i, i, ip, d, d, dp, d, dp, dp, dp], i),
+            "oracle_solve": ([i, i, i, ip, d, d, dp, d, dp, dp, dp], i),
+            "oracle_apply_L": ([i, i, i, ip, d, d, dp, d, dp, dp], None),
             "oracle_set_threads": ([i], None),
             "oracle_threads": ([], i),
         }
@@ -134,47 +134,50 @@ def transform(field, axis: int, kind: int, inverse: bool = False, ld: bool = Fal
     return out
 
 
-def spectral_solve(fhat, bc, dx: float, dy: float, dzf, ld: bool = False):
-    """Column-wise tridiagonal solves of eq. (poi_reduced) on a spectral field.
+def spectral_solve(fhat, bc, dx: float, dy: float, dzf, ld: bool = False, shift: float = 0.0):
+    """Column-wise tridiagonal solves of eq. (poi_reduced) on a spectral field
+    (shift: added to every column's diagonal, the Helmholtz form).
 
     Returns (phat, removed) where removed is the dzf-weighted mean taken out of
     the singular column (spectral units) or 0."""
     f = _f64(fhat); dzf = _f64(dzf)
     nz, ny, nx = f.shape
     out = np.zeros_like(f); rem = ctypes.c_double(0.0)
-    rc = _lib(ld).oracle_spectral_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), _dp(f), _dp(out),
+    rc = _lib(ld).oracle_spectral_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), float(shift), _dp(f), _dp(out),
                                         ctypes.pointer(rem))
     if rc:
         raise ValueError("invalid boundary conditions")
     return out, rem.value
 
 
-def solve(f, bc, dx: float, dy: float, dzf, ld: bool = False):
-    """Direct solve of L_h p = f.  Returns (p, removed_mean).
+def solve(f, bc, dx: float, dy: float, dzf, ld: bool = False, shift: float = 0.0):
+    """Direct solve of (L_h + shift) p = f (shift <= 0; 0 is eq. (poi)).
+    Returns (p, removed_mean).
 
-    For singular problems (every axis P or NN) f is projected by its
+    For singular problems (every axis P or NN, shift 0) f is projected by its
     dzf-weighted mean, which is returned, and p has zero weighted mean."""
     f = _f64(f); dzf = _f64(dzf)
     nz, ny, nx = f.shape
     assert dzf.shape == (nz,)
     p = np.zeros_like(f); info = np.zeros(4)
-    rc = _lib(ld).oracle_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), _dp(f), _dp(p), _dp(info))
+    rc = _lib(ld).oracle_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), float(shift), _dp(f), _dp(p), _dp(info))
     if rc:
         raise ValueError("invalid boundary conditions")
     return p, float(info[0])
 
 
-def apply_L(p, bc, dx: float, dy: float, dzf) -> np.ndarray:
-    """The discrete operator L_h of eq. (poi), z in conservative form."""
+def apply_L(p, bc, dx: float, dy: float, dzf, shift: float = 0.0) -> np.ndarray:
+    """The discrete operator L_h of eq. (poi), z in conservative form, plus
+    shift times p."""
     p = _f64(p); dzf = _f64(dzf)
     nz, ny, nx = p.shape
     out = np.zeros_like(p)
-    _lib().oracle_apply_L(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), _dp(p), _dp(out))
+    _lib().oracle_apply_L(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), float(shift), _dp(p), _dp(out))
     return out
 
 
-def is_singular(bc) -> bool:
-    return all(axis_kind(bc[2 * a], bc[2 * a + 1]) in (K_P, K_NN) for a in range(3))
+def is_singular(bc, shift: float = 0.0) -> bool:
+    return shift == 0.0 and all(axis_kind(bc[2 * a], bc[2 * a + 1]) in (K_P, K_NN) for a in range(3))
 
 
 def weighted_mean(p, dzf) -> float:
@@ -183,20 +186,20 @@ def weighted_mean(p, dzf) -> float:
     return float((p.sum(axis=(1, 2)) * w).sum() / (w.sum() * p.shape[1] * p.shape[2]))
 
 
-def residual(p, f, bc, dx, dy, dzf):
-    """Relative residual ||Pi f - L_h p||_2 / ||Pi f||_2 (Pi = projection
-    removing the weighted mean when the problem is singular)."""
+def residual(p, f, bc, dx, dy, dzf, shift: float = 0.0):
+    """Relative residual ||Pi f - (L_h + shift) p||_2 / ||Pi f||_2 (Pi =
+    projection removing the weighted mean when the problem is singular)."""
     f = _f64(f)
-    if is_singular(bc):
+    if is_singular(bc, shift):
         f = f - weighted_mean(f, dzf)
-    r = f - apply_L(p, bc, dx, dy, dzf)
+    r = f - apply_L(p, bc, dx, dy, dzf, shift)
     return float(np.linalg.norm(r) / np.linalg.norm(f))
 
 
-def residual_inf(p, f, bc, dx, dy, dzf):
-    """Max-norm form of `residual`: max|Pi f - L_h p| / max|Pi f|."""
+def residual_inf(p, f, bc, dx, dy, dzf, shift: float = 0.0):
+    """Max-norm form of `residual`: max|Pi f - (L_h + shift) p| / max|Pi f|."""
     f = _f64(f)
-    if is_singular(bc):
+    if is_singular(bc, shift):
         f = f - weighted_mean(f, dzf)
-    r = f - apply_L(p, bc, dx, dy, dzf)
+    r = f - apply_L(p, bc, dx, dy, dzf, shift)
     return float(np.abs(r).max() / np.abs(f).max())

@@ -406,3 +406,53 @@ def test_spectral_solve_consistent_with_solve():
     p = O.transform(O.transform(ph, 1, ky, inverse=True), 0, kx, inverse=True)
     p2, _ = O.solve(f, bc, 0.3, 0.4, dzf)
     assert rel(p, p2) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Helmholtz form (L_h + s) p = f, s <= 0: the same expansion with every
+# column's diagonal moved by s (implicit diffusion)
+
+@pytest.mark.parametrize("zp", ALL_PAIRS)
+@pytest.mark.parametrize("xp", ALL_PAIRS)
+def test_helmholtz_dense_lu(xp, zp):
+    """(L_h + s) p = f equals a dense solve of the assembled operator plus s I,
+    uniform and stretched z; singular boundary sets become regular (no
+    projection, nothing removed)."""
+    nx, ny, nz = 4, 3, 5
+    for yp in [(P, P), (N, N), (D, N)]:
+        bc = xp + yp + zp
+        rng = np.random.default_rng(sum(xp) * 25 + sum(yp) * 5 + sum(zp) + 7)
+        dzfs = [np.full(nz, 0.3)] + ([inputs.tanh_dzf(nz, 1.5, 2.0)] if zp != (P, P) else [])
+        for dzf in dzfs:
+            for s in (-0.5, -37.0):
+                f = rng.standard_normal((nz, ny, nx))
+                p, rem = O.solve(f, bc, 0.7, 1.3, dzf, shift=s)
+                A = dense_L(nx, ny, nz, bc, 0.7, 1.3, dzf) + s * np.eye(nx * ny * nz)
+                pd = np.linalg.solve(A, f.ravel()).reshape(f.shape)
+                assert rel(p, pd) < 1e-12, (bc, s, rel(p, pd))
+                assert rem == 0.0
+                assert O.residual(p, f, bc, 0.7, 1.3, dzf, shift=s) < 1e-13
+                assert not O.is_singular(bc, s)
+
+
+def test_helmholtz_closed_form_and_operator():
+    """Uniform grid, f = product of 1-D eigenvectors: p = f / (sum mu/h^2 + s);
+    apply_L with a shift is the dense operator plus s I."""
+    nx, ny, nz = 12, 10, 8
+    hx, hy, hz = 0.1, 0.2, 0.125
+    x = np.arange(nx) + 0.5; y = np.arange(ny) + 0.5; z = np.arange(nz) + 0.5
+    bc = (P, P, N, N, D, D)
+    s = -3.5
+    for qx, qy, qz in [(0, 0, 0), (1, 2, 3), (3, 0, 1)]:
+        ex = np.cos(2 * np.pi * qx * (x - 0.5) / nx); lx = -4 * np.sin(np.pi * qx / nx) ** 2
+        ey = np.cos(np.pi * qy * y / ny); ly = -4 * np.sin(np.pi * qy / (2 * ny)) ** 2
+        ez = np.sin(np.pi * (qz + 1) * z / nz); lz = -4 * np.sin(np.pi * (qz + 1) / (2 * nz)) ** 2
+        f = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        p, _ = O.solve(f, bc, hx, hy, np.full(nz, hz), shift=s)
+        assert rel(p, f / (lx / hx**2 + ly / hy**2 + lz / hz**2 + s)) < 1e-12
+    rng = np.random.default_rng(3)
+    dzf = inputs.tanh_dzf(6, 1.4, 1.0)
+    p = rng.standard_normal((6, 3, 5))
+    Ld = dense_L(5, 3, 6, (D, N, P, P, N, D), 0.4, 0.6, dzf)
+    np.testing.assert_allclose(O.apply_L(p, (D, N, P, P, N, D), 0.4, 0.6, dzf, shift=s).ravel(),
+                               Ld @ p.ravel() + s * p.ravel(), rtol=1e-12, atol=1e-10)
