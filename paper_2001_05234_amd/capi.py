@@ -35,7 +35,7 @@ EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "ca
 class CansOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("xform_x", ctypes.c_int), ("xform_y", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("shift", ctypes.c_double)]
 
 
 class CansInfo(ctypes.Structure):
@@ -135,7 +135,7 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, nz: int, bc, dx: float, dy: float, dzf,
                  precision: str = "fp64", tol: float = 1e-10, max_iter: int = 4, xform_x: str = "auto",
-                 autotune: bool = False, graph: bool = False):
+                 autotune: bool = False, graph: bool = False, shift: float = 0.0):
         lib = load()
         self._lib = lib
         self.shape = (nz, ny, nx)
@@ -147,6 +147,7 @@ class Plan:
         o.xform_x = {"auto": XFORM_AUTO, "fft": XFORM_FFT, "dense": XFORM_DENSE}[xform_x]
         o.autotune = int(bool(autotune))
         o.graph = int(bool(graph))
+        o.shift = float(shift)
         dz = np.ascontiguousarray(np.asarray(dzf, dtype=np.float64))
         if dz.shape != (nz,):
             raise ValueError("dzf must hold nz cell widths")
@@ -189,7 +190,7 @@ class BatchedPlan:
     """Many independent problems in one plan (``cans_poisson_plan_batched``)."""
 
     def __init__(self, problems, precision: str = "fp32_refine", tol: float = 1e-10, max_iter: int = 4,
-                 autotune: bool = False):
+                 autotune: bool = False, shift: float = 0.0):
         lib = load()
         self._lib = lib
         o = default_opts()
@@ -197,6 +198,7 @@ class BatchedPlan:
         o.tol = tol
         o.max_iter = max_iter
         o.autotune = int(bool(autotune))
+        o.shift = float(shift)
         self._dz = []
         descs = (CansDesc * len(problems))()
         for d, pr in zip(descs, problems):

@@ -50,6 +50,7 @@ struct Problem {
     std::vector<double> dzf;
     double wsum = 0;
     int cyclic = 0, singular = 0;
+    double shift = 0;              // Helmholtz shift s of (L_h + s) p = f
     double scale = 1;
     double *d_za = nullptr, *d_zb = nullptr, *d_zc = nullptr;
     double *d_zaf = nullptr, *d_zcf = nullptr, *d_dzf = nullptr;

@@ -716,6 +716,7 @@ static LapArgs lapargs(const Problem &pb)
     la.idx2 = 1.0 / (pb.ax.h * pb.ax.h);
     la.idy2 = 1.0 / (pb.ay.h * pb.ay.h);
     la.zaf = pb.d_zaf; la.zcf = pb.d_zcf;
+    la.shift = pb.shift;
     return la;
 }
 

@@ -85,7 +85,7 @@ int validate(int nx, int ny, int nz, const int *bc, double dx, double dy, const 
     return CANS_OK;
 }
 
-int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
+int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h, double shift = 0.0)
 {
     a.kind = kind;
     a.n = n;
@@ -101,6 +101,7 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h)
     CANS_TRY(upload(pl, &a.d_tw64, t64.data(), t64.size()));
     CANS_TRY(upload(pl, &a.d_tw32, t32.data(), t32.size()));
     std::vector<double> lam = lambdas(kind, n, h);
+    for (double &v : lam) v += shift;  // the Helmholtz shift rides on one axis's eigenvalues
     CANS_TRY(upload(pl, &a.d_lam, lam.data(), n));
     return CANS_OK;
 }
@@ -212,10 +213,12 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     pb.dzf.assign(dz, dz + nz);
     const int kx = axis_kind(bc[0], bc[1]), ky = axis_kind(bc[2], bc[3]), kz = axis_kind(bc[4], bc[5]);
     CANS_TRY(build_axis(pl, pb.ax, kx, nx, dx));
-    CANS_TRY(build_axis(pl, pb.ay, ky, ny, dy));
+    CANS_TRY(build_axis(pl, pb.ay, ky, ny, dy, pl->opts.shift));
     if (pl->opts.xform_x == CANS_XFORM_DENSE) CANS_TRY(build_dense(pl, pb.ax));
     pb.cyclic = kz == K_P;
-    pb.singular = (kx == K_P || kx == K_NN) && (ky == K_P || ky == K_NN) && (kz == K_P || kz == K_NN);
+    pb.shift = pl->opts.shift;
+    pb.singular = (kx == K_P || kx == K_NN) && (ky == K_P || ky == K_NN) && (kz == K_P || kz == K_NN) &&
+                  pb.shift == 0.0;
     pb.scale = 1.0 / ((double)pb.ax.s * (double)pb.ay.s);
     long double ws = 0;
     for (int k = 0; k < nz; ++k) ws += dz[k];
@@ -257,6 +260,8 @@ int check_opts(const cans_opts &o)
     if (!(o.tol >= 0) || !std::isfinite(o.tol)) return CANS_ERR_INVALID_ARG;
     if (o.autotune != 0 && o.autotune != 1) return CANS_ERR_INVALID_ARG;
     if (o.graph != 0 && o.graph != 1) return CANS_ERR_INVALID_ARG;
+    if (!std::isfinite(o.shift)) return CANS_ERR_INVALID_ARG;
+    if (o.shift > 0) return CANS_ERR_UNSUPPORTED;  // indefinite: elimination without pivoting does not apply
     for (int m : {o.xform_x, o.xform_y})
         if (m != CANS_XFORM_AUTO && m != CANS_XFORM_FFT && m != CANS_XFORM_DENSE) return CANS_ERR_INVALID_ARG;
     // the matrix-core form exists for the x axis of the refinement path
@@ -384,6 +389,7 @@ void cans_default_opts(cans_opts *o)
     o->max_iter = 4;
     o->autotune = 0;
     o->graph = 0;
+    o->shift = 0.0;
 }
 
 const char *cans_status_string(int code)

@@ -159,6 +159,7 @@ struct LapArgs {
     double idx2, idy2;
     const double *zaf;  // 1/(dzc_{k-1} dzf_k), unfolded (ghost spacing at walls)
     const double *zcf;  // 1/(dzc_k dzf_k), unfolded
+    double shift;       // Helmholtz shift s: the operator is L_h + s
 };
 
 CANS_HD double ghost(int bc, double inner, double wrap)
@@ -175,7 +176,7 @@ CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
         const double *q = p + e;
         const double c = q[0];
         return (q[-1] - 2.0 * c + q[1]) * a.idx2 + (q[-(long)sy] - 2.0 * c + q[sy]) * a.idy2
-             + a.zcf[k] * (q[sz] - c) - a.zaf[k] * (c - q[-(long)sz]);
+             + a.zcf[k] * (q[sz] - c) - a.zaf[k] * (c - q[-(long)sz]) + a.shift * c;
     }
     const double c = p[e];
     const double xm = i > 0 ? p[e - sx] : ghost(a.bc[0], c, p[e + (a.nx - 1) * sx]);
@@ -185,7 +186,7 @@ CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
     const double zm = k > 0 ? p[e - sz] : ghost(a.bc[4], c, p[e + (a.nz - 1) * sz]);
     const double zp = k < a.nz - 1 ? p[e + sz] : ghost(a.bc[5], c, p[e - (a.nz - 1) * sz]);
     return (xm - 2.0 * c + xp) * a.idx2 + (ym - 2.0 * c + yp) * a.idy2
-         + a.zcf[k] * (zp - c) - a.zaf[k] * (c - zm);
+         + a.zcf[k] * (zp - c) - a.zaf[k] * (c - zm) + a.shift * c;
 }
 
 }  // namespace cans

@@ -135,6 +135,7 @@ int setup(Setup &s, int nx, int ny, int nz, const int *bc, double dx, double dy,
     for (int i = 0; i < 6; ++i) la.bc[i] = bc[i];
     la.idx2 = 1.0 / (dx * dx); la.idy2 = 1.0 / (dy * dy);
     la.zaf = s.zaf.data(); la.zcf = s.zcf.data();
+    la.shift = 0.0;
     return 0;
 }
 

@@ -73,7 +73,7 @@ def test_plan_validation_spacing():
 
 def test_options_validation():
     o = capi.default_opts()
-    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4 and o.autotune == 0 and o.graph == 0
+    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 4 and o.autotune == 0 and o.graph == 0 and o.shift == 0.0
     o.max_iter = 99
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.precision = 7
@@ -84,6 +84,10 @@ def test_options_validation():
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
     o = capi.default_opts(); o.graph = 2
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.shift = float("nan")
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -1
+    o = capi.default_opts(); o.shift = 0.5  # indefinite Helmholtz form
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -2
     o = capi.default_opts(); o.xform_y = 2
     assert _plan(128, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -2
 
