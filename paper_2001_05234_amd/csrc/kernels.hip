@@ -293,8 +293,6 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
             sff += fv * fv;
             rmax = fmax(rmax, fabs(r));
             fmx = fmax(fmx, fabs(fv));
-        rmax = fmax(rmax, fabs(r));
-        fmx = fmax(fmx, fabs(fv));
             spw += wk * p[gi];
         }
     }
