@@ -91,10 +91,11 @@ typedef struct cans_opts {
                            call.  0: kernels are launched one by one.  Batched
                            plans always use a graph.  Default 0. */
     double shift;       /* s <= 0: solve the Helmholtz form (L_h + s) p = f of
-                           implicit diffusion for a cell-centred quantity (the
-                           same expansion, every column's diagonal moved by s;
-                           no singular case when s < 0).  s > 0 (indefinite)
-                           is unsupported.  Default 0: eq. (poi). */
+                           implicit diffusion (eq. (up_id_2): s = -2/(gamma_k
+                           nu dt)) for a cell-centred quantity: the same
+                           expansion, every column's diagonal moved by s; no
+                           singular case when s < 0.  s > 0 (indefinite) is
+                           unsupported.  Default 0: eq. (poi). */
 } cans_opts;
 
 #define CANS_HISTORY 17
