@@ -257,7 +257,7 @@ def main():
                     help="x transform form of the refinement plan (dense: split-bf16 matrix-core products)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solver has no multi-GPU path in this build "
+        print("bench.py measures one GPU: the solver has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

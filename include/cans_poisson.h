@@ -42,7 +42,7 @@ enum cans_bc {
 enum cans_status {
     CANS_OK = 0,
     CANS_ERR_INVALID_ARG = -1,  /* bad size, spacing, pointer or boundary pair */
-    CANS_ERR_UNSUPPORTED = -2,  /* valid problem this build does not handle
+    CANS_ERR_UNSUPPORTED = -2,  /* valid problem the library does not handle
                                    (odd, > 4096 or non-{2,3,5}-smooth x/y length,
                                    periodic z that is stretched or shorter
                                    than 3 cells) */

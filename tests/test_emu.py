@@ -118,7 +118,7 @@ def test_zsolve_partitioned(nz):
         pe, reme = res
         s = scale(kx, nx) * scale(ky, ny)
         e = rel(pe * s, ph)
-        if e >= 1e-12:  # conditioning: judge both FP64 results against long double
+        if e >= 1e-12:  # conditioning: compare both FP64 results with long double
             phl, _ = O.spectral_solve(fh, bc, 0.3, 0.5, dzf, ld=True)
             assert rel(pe * s, phl) < 2 * rel(ph, phl), (nz, bc, e)
         assert abs(reme * s - rem) < 1e-12 * max(1, abs(rem))
