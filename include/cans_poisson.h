@@ -45,7 +45,8 @@ enum cans_status {
     CANS_ERR_UNSUPPORTED = -2,  /* valid problem the library does not handle
                                    (odd, > 4096 or non-{2,3,5}-smooth x/y length,
                                    periodic z that is stretched or shorter
-                                   than 3 cells) */
+                                   than 3 cells, a transform form the options
+                                   do not allow, shift > 0) */
     CANS_ERR_ALLOC = -3,        /* device or host allocation failed */
     CANS_ERR_HIP = -4,          /* HIP runtime or launch error */
     CANS_ERR_ALIAS = -5         /* rhs == p where the mode forbids it */
