@@ -752,11 +752,21 @@ int launch_resid_norm(const Problem &pb, const double *f, const double *p, const
     return check_launch();
 }
 
+// Up to this many block partials the last-level kernel reads them directly
+// (one launch per check instead of two; small problems are launch-bound).
+constexpr int kDirectReduce = 4096;
+
 int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
-    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, resid_blocks(pb),
-                       pb.sums, pb.d_flag);
+    const int nblk = resid_blocks(pb);
+    if (nblk <= kDirectReduce) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.partials, nblk, check, max_iter, tol,
+                           inv_wvol, pb.singular, pb.d_info, pb.d_flag);
+        return check_launch();
+    }
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, nblk, pb.sums,
+                       pb.d_flag);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, check, max_iter, tol,
                        inv_wvol, pb.singular, pb.d_info, pb.d_flag);
     return check_launch();
@@ -765,8 +775,13 @@ int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipS
 int launch_mean_rhs(const Problem &pb, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
-    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, xfwd_blocks(pb),
-                       pb.sums, nullptr);
+    const int nblk = xfwd_blocks(pb);
+    if (nblk <= kDirectReduce) {
+        hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.partials, nblk, inv_wvol, pb.singular,
+                           pb.d_info);
+        return check_launch();
+    }
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, nblk, pb.sums, nullptr);
     hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, inv_wvol, pb.singular,
                        pb.d_info);
     return check_launch();
