@@ -36,7 +36,12 @@
  *
  * Layout: every 3-D field is x fastest, a[i + nx*(j + ny*k)].
  * Boundary codes per face: 0 = periodic, 1 = Neumann, 2 = Dirichlet;
- * bc[6] = {x-, x+, y-, y+, z-, z+}.
+ * bc[6] = {x-, x+, y-, y+, z-, z+}.  Code 3 (z only, on both z faces) is
+ * Dirichlet for a field located on the z faces rather than the cell centres,
+ * as the wall-normal velocity of a channel is in the implicit diffusion
+ * steps of eq. (up_id_2): the unknowns are the nz interior faces of a grid
+ * of nz+1 cells, dzf then holds those nz+1 cell widths, and the field is
+ * zero on the two wall faces.
  */
 #include <math.h>
 #include <omp.h>
@@ -57,19 +62,21 @@ typedef double REAL;
 #define SYM(name) name
 #endif
 
-enum { BC_P = 0, BC_N = 1, BC_D = 2 };
+enum { BC_P = 0, BC_N = 1, BC_D = 2, BC_DF = 3 };
 
 /* Threads of the OpenMP loops below (for timing the oracle on n cores), and
  * the number a parallel loop will use. */
 void SYM(oracle_set_threads)(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int SYM(oracle_threads)(void) { return omp_get_max_threads(); }
 /* transform kinds of one axis, named by the (lower, upper) boundary pair */
-enum { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4 };
+enum { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4, K_FD = 5 };
 
 /* Axis kind from its two face conditions; -1 when the pair is invalid
- * (periodic must be paired with periodic). */
+ * (periodic must be paired with periodic, a face-located field has code 3 at
+ * both ends).  K_FD (face-located Dirichlet) is a z kind only. */
 int SYM(oracle_axis_kind)(int lo, int hi)
 {
+    if (lo == BC_DF || hi == BC_DF) return (lo == BC_DF && hi == BC_DF) ? K_FD : -1;
     if (lo == BC_P || hi == BC_P) return (lo == BC_P && hi == BC_P) ? K_P : -1;
     if (lo == BC_N && hi == BC_N) return K_NN;
     if (lo == BC_D && hi == BC_D) return K_DD;
@@ -144,10 +151,29 @@ static int zero_row(int kind) { return (kind == K_P || kind == K_NN) ? 0 : -1; }
  * Periodic: the corner entries a[0] (couples to p_{nz-1}) and c[nz-1]
  * (couples to p_0) are kept.  Wall rows fold the ghost into the diagonal and
  * zero the outer coefficient.  Returns 0, or -1 on an invalid pair.
+ *
+ * Face-located field (code 3 at both ends): unknown k sits on the face
+ * between cells k and k+1 of a grid of nz+1 cells with widths dzf[0..nz].
+ * The neighbouring unknowns are dzf[k] below and dzf[k+1] above, and the
+ * control volume reaches from the centre of cell k to that of cell k+1:
+ *   [(w_{k+1}-w_k)/dzf_{k+1} - (w_k-w_{k-1})/dzf_k] / ((dzf_k + dzf_{k+1})/2).
+ * The two wall faces hold w = 0, so their couplings drop out of the end rows
+ * while the diagonal keeps both terms.
  */
 static int zcoef_real(int nz, int lo, int hi, const double *dzf, REAL *a, REAL *b, REAL *c)
 {
     if (SYM(oracle_axis_kind)(lo, hi) < 0) return -1;
+    if (lo == BC_DF) {
+        for (int k = 0; k < nz; ++k) {
+            REAL below = dzf[k], above = dzf[k + 1], cv = (below + above) / 2;
+            a[k] = 1 / (below * cv);
+            c[k] = 1 / (above * cv);
+            b[k] = -(a[k] + c[k]);
+        }
+        a[0] = 0;
+        c[nz - 1] = 0;
+        return 0;
+    }
     for (int k = 0; k < nz; ++k) {
         REAL f = dzf[k], cm, cp;
         if (k > 0) cm = ((REAL)dzf[k - 1] + f) / 2;
@@ -317,7 +343,7 @@ static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double d
 {
     int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
     int kz = SYM(oracle_axis_kind)(bc[4], bc[5]);
-    if (kx < 0 || ky < 0 || kz < 0) return -1;
+    if (kx < 0 || ky < 0 || kz < 0 || kx == K_FD || ky == K_FD) return -1;
     REAL *T = malloc(sizeof(REAL) * ((size_t)nx * nx + (size_t)ny * ny));
     REAL *mux = malloc(sizeof(REAL) * (nx + ny)), *muy = mux + nx;
     eigen_real(kx, nx, T, mux);
@@ -409,7 +435,7 @@ int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double
                       const double *dzf, double shift, const double *f, double *p, double *info)
 {
     int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
-    if (kx < 0 || ky < 0 || SYM(oracle_axis_kind)(bc[4], bc[5]) < 0) return -1;
+    if (kx < 0 || ky < 0 || kx == K_FD || ky == K_FD || SYM(oracle_axis_kind)(bc[4], bc[5]) < 0) return -1;
     size_t N = (size_t)nx * ny * nz;
     REAL *Tx = malloc(sizeof(REAL) * (size_t)nx * nx), *Tix = malloc(sizeof(REAL) * (size_t)nx * nx);
     REAL *Ty = malloc(sizeof(REAL) * (size_t)ny * ny), *Tiy = malloc(sizeof(REAL) * (size_t)ny * ny);
@@ -430,7 +456,8 @@ int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double
 
 /*
  * out = L_h p + shift p, the 7-point operator of eq. (poi) with the z part
- * in the conservative form above and the ghost rules of each face.
+ * in the conservative form above and the ghost rules of each face (a
+ * face-located z field: the form of zcoef_real, zero on the wall faces).
  */
 void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
                          const double *dzf, double shift, const double *p, double *out)
@@ -443,6 +470,11 @@ void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, dou
         cp = k < nz - 1 ? (f + (REAL)dzf[k + 1]) / 2 : (bc[5] == BC_P ? (f + (REAL)dzf[0]) / 2 : f);
         zaf[k] = 1 / (cm * f);
         zcf[k] = 1 / (cp * f);
+        if (bc[4] == BC_DF) {
+            REAL below = dzf[k], above = dzf[k + 1], cv = (below + above) / 2;
+            zaf[k] = 1 / (below * cv);
+            zcf[k] = 1 / (above * cv);
+        }
     }
     REAL ix2 = 1 / ((REAL)dx * dx), iy2 = 1 / ((REAL)dy * dy);
     #pragma omp parallel for schedule(static)
@@ -457,8 +489,10 @@ void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, dou
             xp = i < nx - 1 ? P3(i + 1, j, k) : bc[1] == BC_P ? P3(0, j, k) : bc[1] == BC_N ? c0 : -c0;
             ym = j > 0 ? P3(i, j - 1, k) : bc[2] == BC_P ? P3(i, ny - 1, k) : bc[2] == BC_N ? c0 : -c0;
             yp = j < ny - 1 ? P3(i, j + 1, k) : bc[3] == BC_P ? P3(i, 0, k) : bc[3] == BC_N ? c0 : -c0;
-            zm = k > 0 ? P3(i, j, k - 1) : bc[4] == BC_P ? P3(i, j, nz - 1) : bc[4] == BC_N ? c0 : -c0;
-            zp = k < nz - 1 ? P3(i, j, k + 1) : bc[5] == BC_P ? P3(i, j, 0) : bc[5] == BC_N ? c0 : -c0;
+            zm = k > 0 ? P3(i, j, k - 1) : bc[4] == BC_P ? P3(i, j, nz - 1) : bc[4] == BC_N ? c0
+                 : bc[4] == BC_DF ? 0 : -c0;
+            zp = k < nz - 1 ? P3(i, j, k + 1) : bc[5] == BC_P ? P3(i, j, 0) : bc[5] == BC_N ? c0
+                 : bc[5] == BC_DF ? 0 : -c0;
 #undef P3
             REAL v = (xm - 2 * c0 + xp) * ix2 + (ym - 2 * c0 + yp) * iy2
                    + zcf[k] * (zp - c0) - zaf[k] * (c0 - zm) + (REAL)shift * c0;

@@ -11,7 +11,9 @@ x and y, Gauss elimination (Thomas) along z, inverse transforms.
 
 Fields are numpy float64 arrays of shape (nz, ny, nx) (x fastest).
 Boundary codes: 0 periodic, 1 Neumann, 2 Dirichlet; bc = (x-, x+, y-, y+, z-, z+).
-Axis kinds: 0 P, 1 NN, 2 DD, 3 ND, 4 DN.
+Code 3 on both z faces: Dirichlet for a field on the z faces (the unknowns are
+the nz interior faces of an (nz+1)-cell grid, dzf holds those nz+1 widths).
+Axis kinds: 0 P, 1 NN, 2 DD, 3 ND, 4 DN, 5 face-located DD (z only).
 """
 from __future__ import annotations
 
@@ -25,8 +27,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cans_oracle.c")
 _LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_ld.so")}
 
-P, N, D = 0, 1, 2
-K_P, K_NN, K_DD, K_ND, K_DN = 0, 1, 2, 3, 4
+P, N, D, DF = 0, 1, 2, 3
+K_P, K_NN, K_DD, K_ND, K_DN, K_FD = 0, 1, 2, 3, 4, 5
+
+
+def n_dz(bc, nz: int) -> int:
+    """Length of the z spacing array: nz cell widths, or nz+1 for a
+    face-located z field (code 3)."""
+    return nz + 1 if bc[4] == DF else nz
 
 
 def build(force: bool = False) -> None:
@@ -111,6 +119,7 @@ def eigen(kind: int, n: int, ld: bool = False):
 
 def zcoef(nz: int, lo: int, hi: int, dzf):
     dzf = _f64(dzf)
+    assert dzf.shape == (nz + 1 if lo == DF else nz,)
     a, b, c = np.zeros(nz), np.zeros(nz), np.zeros(nz)
     rc = _lib().oracle_zcoef(nz, lo, hi, _dp(dzf), _dp(a), _dp(b), _dp(c))
     if rc:
@@ -142,6 +151,7 @@ def spectral_solve(fhat, bc, dx: float, dy: float, dzf, ld: bool = False, shift:
     the singular column (spectral units) or 0."""
     f = _f64(fhat); dzf = _f64(dzf)
     nz, ny, nx = f.shape
+    assert dzf.shape == (n_dz(bc, nz),)
     out = np.zeros_like(f); rem = ctypes.c_double(0.0)
     rc = _lib(ld).oracle_spectral_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), float(shift), _dp(f), _dp(out),
                                         ctypes.pointer(rem))
@@ -158,7 +168,7 @@ def solve(f, bc, dx: float, dy: float, dzf, ld: bool = False, shift: float = 0.0
     dzf-weighted mean, which is returned, and p has zero weighted mean."""
     f = _f64(f); dzf = _f64(dzf)
     nz, ny, nx = f.shape
-    assert dzf.shape == (nz,)
+    assert dzf.shape == (n_dz(bc, nz),)
     p = np.zeros_like(f); info = np.zeros(4)
     rc = _lib(ld).oracle_solve(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), float(shift), _dp(f), _dp(p), _dp(info))
     if rc:
@@ -171,6 +181,7 @@ def apply_L(p, bc, dx: float, dy: float, dzf, shift: float = 0.0) -> np.ndarray:
     shift times p."""
     p = _f64(p); dzf = _f64(dzf)
     nz, ny, nx = p.shape
+    assert dzf.shape == (n_dz(bc, nz),)
     out = np.zeros_like(p)
     _lib().oracle_apply_L(nx, ny, nz, _bc(bc), dx, dy, _dp(dzf), float(shift), _dp(p), _dp(out))
     return out

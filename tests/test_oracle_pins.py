@@ -456,3 +456,118 @@ def test_helmholtz_closed_form_and_operator():
     Ld = dense_L(5, 3, 6, (D, N, P, P, N, D), 0.4, 0.6, dzf)
     np.testing.assert_allclose(O.apply_L(p, (D, N, P, P, N, D), 0.4, 0.6, dzf, shift=s).ravel(),
                                Ld @ p.ravel() + s * p.ravel(), rtol=1e-12, atol=1e-10)
+
+
+# --------------------------------------------------------------------------- #
+# Dirichlet on a z-face-located field (code 3 on both z faces): the unknowns
+# are the nz interior faces of an (nz+1)-cell grid and the field is zero on
+# the two wall faces (the wall-normal velocity of the implicit diffusion
+# steps, eq. (up_id_2)).
+DF = 3
+
+
+def op_z_face(cells):
+    """z operator on the interior faces, from its flux form: face k lies
+    between cells k and k+1, the faces next to it are cells[k] below and
+    cells[k+1] above, and its control volume is half of each cell."""
+    cells = np.asarray(cells, float)
+    nz = cells.size - 1
+    A = np.zeros((nz, nz))
+    for k in range(nz):
+        vol = 0.5 * (cells[k] + cells[k + 1])
+        down, up = 1.0 / (cells[k] * vol), 1.0 / (cells[k + 1] * vol)
+        A[k, k] = -(down + up)
+        if k > 0:
+            A[k, k - 1] = down
+        if k < nz - 1:
+            A[k, k + 1] = up
+    return A
+
+
+def dense_L_facez(nx, ny, nz, bcxy, dx, dy, cells):
+    """Kronecker sum of the x/y operator of one plane (dense_L on a single
+    Neumann cell, whose z terms cancel) and the face-located z operator."""
+    Lxy = dense_L(nx, ny, 1, tuple(bcxy) + (N, N), dx, dy, [1.0])
+    return np.kron(np.eye(nz), Lxy) + np.kron(op_z_face(cells), np.eye(nx * ny))
+
+
+def stretched_cells(ncell, seed):
+    rng = np.random.default_rng(seed)
+    return inputs.tanh_dzf(ncell, 1.5, 2.0) * rng.uniform(0.7, 1.3, ncell)
+
+
+def test_face_z_kinds_and_validation():
+    assert O.axis_kind(DF, DF) == O.K_FD
+    assert O.axis_kind(DF, D) == -1 and O.axis_kind(N, DF) == -1
+    assert not O.is_singular((P, P, P, P, DF, DF))
+    f = np.ones((4, 2, 2))
+    with pytest.raises(ValueError):
+        O.solve(f, (DF, DF, P, P, DF, DF), 1.0, 1.0, np.ones(5))
+    with pytest.raises(AssertionError):
+        O.solve(f, (P, P, P, P, DF, DF), 1.0, 1.0, np.ones(4))  # needs nz+1 widths
+
+
+@pytest.mark.parametrize("bcxy", [(P, P, P, P), (N, N, P, P), (N, N, N, N)])
+def test_face_z_quadratic_exact(bcxy):
+    """The three-point flux form is exact for quadratics on any node spacing:
+    w = z (Lz - z), zero on both walls, maps to -2 on a stretched grid, and
+    solving with f = -2 gives it back (a field constant in x and y)."""
+    nz, ny, nx = 11, 4, 6
+    cells = stretched_cells(nz + 1, 17)
+    Lz = cells.sum()
+    zf = np.cumsum(cells)[:nz]
+    w = np.broadcast_to((zf * (Lz - zf))[:, None, None], (nz, ny, nx)).copy()
+    bc = tuple(bcxy) + (DF, DF)
+    np.testing.assert_allclose(O.apply_L(w, bc, 0.3, 0.7, cells), -2.0, rtol=0, atol=1e-11)
+    p, rem = O.solve(np.full((nz, ny, nx), -2.0), bc, 0.3, 0.7, cells)
+    assert rem == 0.0
+    assert rel(p, w) < 1e-13
+
+
+def test_face_z_closed_form_uniform():
+    """Uniform z of spacing h: the face-located Dirichlet operator has the
+    DST-I eigenvectors sin(pi q (k+1)/(nz+1)) with mu = -4 sin^2(pi q /
+    (2 (nz+1))), q = 1..nz; p = f / (sum mu/h^2 + s) for f a product of 1-D
+    eigenvectors, with and without a shift."""
+    nx, ny, nz, h = 8, 6, 9, 0.2
+    x = np.arange(nx) + 0.5; y = np.arange(ny) + 0.5; k = np.arange(nz) + 1.0
+    bc = (P, P, D, N, DF, DF)
+    for qx, qy, qz, s in [(0, 0, 1, 0.0), (2, 1, 4, 0.0), (3, 2, 9, -6.0), (1, 0, 5, -40.0)]:
+        ex = np.cos(2 * np.pi * qx * (x - 0.5) / nx); lx = -4 * np.sin(np.pi * qx / nx) ** 2
+        ey = np.sin(np.pi * (2 * qy + 1) * y / (2 * ny)); ly = -4 * np.sin(np.pi * (2 * qy + 1) / (4 * ny)) ** 2
+        ez = np.sin(np.pi * qz * k / (nz + 1)); lz = -4 * np.sin(np.pi * qz / (2 * (nz + 1))) ** 2
+        f = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        p, _ = O.solve(f, bc, 0.1, 0.3, np.full(nz + 1, h), shift=s)
+        assert rel(p, f / (lx / 0.1**2 + ly / 0.3**2 + lz / h**2 + s)) < 1e-12, (qx, qy, qz, s)
+
+
+@pytest.mark.parametrize("yp", [(P, P), (N, N), (D, N)])
+@pytest.mark.parametrize("xp", ALL_PAIRS)
+def test_face_z_dense_lu(xp, yp):
+    """Face-located z field: the oracle's solve equals a dense solve of the
+    operator assembled here, stretched z, with and without a shift; apply_L
+    equals the dense operator."""
+    nx, ny, nz = 4, 3, 6
+    bc = xp + yp + (DF, DF)
+    rng = np.random.default_rng(sum(xp) * 5 + sum(yp) + 101)
+    cells = stretched_cells(nz + 1, sum(xp) + 3 * sum(yp))
+    A0 = dense_L_facez(nx, ny, nz, xp + yp, 0.7, 1.3, cells)
+    for s in (0.0, -4.0):
+        f = rng.standard_normal((nz, ny, nx))
+        p, rem = O.solve(f, bc, 0.7, 1.3, cells, shift=s)
+        pd = np.linalg.solve(A0 + s * np.eye(A0.shape[0]), f.ravel()).reshape(f.shape)
+        assert rel(p, pd) < 1e-12, (bc, s, rel(p, pd))
+        assert rem == 0.0
+        assert O.residual(p, f, bc, 0.7, 1.3, cells, shift=s) < 1e-13
+        np.testing.assert_allclose(O.apply_L(f, bc, 0.7, 1.3, cells, shift=s).ravel(),
+                                   A0 @ f.ravel() + s * f.ravel(), rtol=1e-12, atol=1e-9)
+
+
+def test_face_z_long_double_agrees():
+    nx, ny, nz = 6, 4, 10
+    bc = (N, D, P, P, DF, DF)
+    cells = stretched_cells(nz + 1, 5)
+    f = np.random.default_rng(9).standard_normal((nz, ny, nx))
+    p, _ = O.solve(f, bc, 0.2, 0.5, cells, shift=-2.0)
+    pl, _ = O.solve(f, bc, 0.2, 0.5, cells, ld=True, shift=-2.0)
+    assert rel(p, pl) < 1e-13
