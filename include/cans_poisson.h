@@ -15,6 +15,8 @@
  *     dzc_k = (dzf_k + dzf_{k+1})/2, mirror ghost cell at a wall.
  * Boundary conditions are homogeneous and located on the cell faces
  * (staggered): periodic p_0 = p_n; Neumann p_0 = p_1; Dirichlet p_0 = -p_1.
+ * Along z a field may instead live on the cell faces themselves, with zero
+ * on the wall faces (CANS_BC_DIRICHLET_FACE below).
  *
  * Layout of every field: double, x fastest, element (i,j,k) at
  * i + nx*(j + ny*k), i.e. a C array [nz][ny][nx].
@@ -36,7 +38,17 @@ extern "C" {
 enum cans_bc {
     CANS_BC_PERIODIC = 0,
     CANS_BC_NEUMANN = 1,
-    CANS_BC_DIRICHLET = 2
+    CANS_BC_DIRICHLET = 2,
+    /* z only, on both z faces: Dirichlet for a field located on the z faces
+       instead of the cell centres, zero on the two wall faces -- the
+       wall-normal velocity of the implicit diffusion steps, eq. (up_id_2).
+       The nz unknowns of a column are the interior faces of a grid of nz+1
+       cells, and dz then holds those nz+1 cell widths.  Row k of the z
+       operator is
+         [(w_{k+1}-w_k)/dz_{k+1} - (w_k-w_{k-1})/dz_k] / ((dz_k + dz_{k+1})/2)
+       with w_{-1} = w_nz = 0.  Never singular; element (i,j,k) of rhs and p
+       is the value on face k (between cells k and k+1). */
+    CANS_BC_DIRICHLET_FACE = 3
 };
 
 enum cans_status {
@@ -128,7 +140,8 @@ void cans_default_opts(cans_opts *opts);
  *            with periodic on the same axis.
  *   dx, dy = uniform spacings (> 0).
  *   dz     = host array of nz cell widths dzf (> 0), copied into the plan; a
- *            periodic z must be uniform.
+ *            periodic z must be uniform.  With CANS_BC_DIRICHLET_FACE on z:
+ *            the nz+1 widths of the cells around the face-located unknowns.
  *   nx, ny even, at most 4096, with nx/2, ny/2 products of 2, 3 and 5;
  *   nz >= 1 (>= 3 if periodic).
  * The plan owns its tables and device workspace (allocated on the current
@@ -195,7 +208,7 @@ typedef struct cans_desc {
     int nx, ny, nz;
     int bc[6];
     double dx, dy;
-    const double *dz;   /* host, nz cell widths */
+    const double *dz;   /* host, nz cell widths (nz+1 for a face-located z) */
 } cans_desc;
 
 /* Build one plan holding `count` problems (each validated as above). */

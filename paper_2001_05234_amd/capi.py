@@ -23,7 +23,14 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported problem", -3: "alloc
           -4: "HIP runtime error", -5: "rhs and p alias"}
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 XFORM_AUTO, XFORM_FFT, XFORM_DENSE = 0, 1, 2
+BC_PERIODIC, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET_FACE = 0, 1, 2, 3
 HISTORY = 17
+
+
+def z_widths(nz: int, bc) -> int:
+    """z widths a problem takes: nz cells, or the nz+1 cells around a
+    face-located z field (BC_DIRICHLET_FACE)."""
+    return nz + 1 if int(bc[4]) == BC_DIRICHLET_FACE else nz
 
 # every symbol the header declares
 EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "cans_poisson_solve",
@@ -149,8 +156,8 @@ class Plan:
         o.graph = int(bool(graph))
         o.shift = float(shift)
         dz = np.ascontiguousarray(np.asarray(dzf, dtype=np.float64))
-        if dz.shape != (nz,):
-            raise ValueError("dzf must hold nz cell widths")
+        if dz.shape != (z_widths(nz, bc),):
+            raise ValueError("dzf must hold nz cell widths (nz+1 for a face-located z)")
         bca = (ctypes.c_int * 6)(*[int(b) for b in bc])
         h = ctypes.c_void_p()
         _check(lib.cans_poisson_plan_ex(ctypes.byref(h), nx, ny, nz, bca, float(dx), float(dy),
@@ -203,6 +210,8 @@ class BatchedPlan:
         descs = (CansDesc * len(problems))()
         for d, pr in zip(descs, problems):
             dz = np.ascontiguousarray(np.asarray(pr.dzf, dtype=np.float64))
+            if dz.shape != (z_widths(pr.nz, pr.bc),):
+                raise ValueError("dzf must hold nz cell widths (nz+1 for a face-located z)")
             self._dz.append(dz)
             d.nx, d.ny, d.nz = pr.nx, pr.ny, pr.nz
             for k in range(6):

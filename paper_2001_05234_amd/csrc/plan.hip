@@ -68,10 +68,11 @@ int validate(int nx, int ny, int nz, const int *bc, double dx, double dy, const 
     if (!bc || !dz || nx < 1 || ny < 1 || nz < 1) return CANS_ERR_INVALID_ARG;
     if (!(dx > 0) || !(dy > 0) || !std::isfinite(dx) || !std::isfinite(dy)) return CANS_ERR_INVALID_ARG;
     for (int i = 0; i < 6; ++i)
-        if (bc[i] < 0 || bc[i] > 2) return CANS_ERR_INVALID_ARG;
-    if (axis_kind(bc[0], bc[1]) < 0 || axis_kind(bc[2], bc[3]) < 0 || axis_kind(bc[4], bc[5]) < 0)
+        if (bc[i] < 0 || bc[i] > 3) return CANS_ERR_INVALID_ARG;
+    // a face-located field only along z (axis_kind rejects code 3)
+    if (axis_kind(bc[0], bc[1]) < 0 || axis_kind(bc[2], bc[3]) < 0 || z_kind(bc[4], bc[5]) < 0)
         return CANS_ERR_INVALID_ARG;
-    for (int k = 0; k < nz; ++k)
+    for (int k = 0; k < z_widths(nz, bc[4]); ++k)
         if (!(dz[k] > 0) || !std::isfinite(dz[k])) return CANS_ERR_INVALID_ARG;
     // even lengths up to 4096 (an FP64 line tile of two LDS buffers fits 64 KiB)
     if (nx % 2 || ny % 2 || nx > 4096 || ny > 4096) return CANS_ERR_UNSUPPORTED;
@@ -210,8 +211,8 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
 {
     pb.nx = nx; pb.ny = ny; pb.nz = nz;
     for (int i = 0; i < 6; ++i) pb.bc[i] = bc[i];
-    pb.dzf.assign(dz, dz + nz);
-    const int kx = axis_kind(bc[0], bc[1]), ky = axis_kind(bc[2], bc[3]), kz = axis_kind(bc[4], bc[5]);
+    pb.dzf = z_weights(nz, bc[4], dz);
+    const int kx = axis_kind(bc[0], bc[1]), ky = axis_kind(bc[2], bc[3]), kz = z_kind(bc[4], bc[5]);
     CANS_TRY(build_axis(pl, pb.ax, kx, nx, dx));
     CANS_TRY(build_axis(pl, pb.ay, ky, ny, dy, pl->opts.shift));
     if (pl->opts.xform_x == CANS_XFORM_DENSE) CANS_TRY(build_dense(pl, pb.ax));
@@ -221,10 +222,10 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
                   pb.shift == 0.0;
     pb.scale = 1.0 / ((double)pb.ax.s * (double)pb.ay.s);
     long double ws = 0;
-    for (int k = 0; k < nz; ++k) ws += dz[k];
+    for (int k = 0; k < nz; ++k) ws += pb.dzf[k];
     pb.wsum = (double)ws;
     std::vector<double> a, b, c, af, cf;
-    zcoef(nz, bc[4], bc[5], pb.dzf, a, b, c, af, cf);
+    zcoef(nz, bc[4], bc[5], std::vector<double>(dz, dz + z_widths(nz, bc[4])), a, b, c, af, cf);
     CANS_TRY(upload(pl, &pb.d_za, a.data(), nz));
     CANS_TRY(upload(pl, &pb.d_zb, b.data(), nz));
     CANS_TRY(upload(pl, &pb.d_zc, c.data(), nz));

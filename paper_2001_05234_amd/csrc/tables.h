@@ -143,15 +143,57 @@ inline std::vector<double> lambdas(int kind, int n, double h)
     return lam;
 }
 
+// Kind of the z axis: as axis_kind, plus a face-located field
+// (CANS_BC_DIRICHLET_FACE at both ends), which solves as Dirichlet-Dirichlet:
+// neither periodic nor singular.
+inline int z_kind(int lo, int hi)
+{
+    if (lo == CANS_BC_DIRICHLET_FACE || hi == CANS_BC_DIRICHLET_FACE)
+        return (lo == CANS_BC_DIRICHLET_FACE && hi == CANS_BC_DIRICHLET_FACE) ? K_DD : -1;
+    return axis_kind(lo, hi);
+}
+
+// z widths a problem is given: nz cells, or the nz+1 cells whose interior
+// faces carry a face-located field
+inline int z_widths(int nz, int lo) { return lo == CANS_BC_DIRICHLET_FACE ? nz + 1 : nz; }
+
+// z volume weight of each of the nz unknowns: its cell width, or for a
+// face-located field the centre-to-centre span around the face
+inline std::vector<double> z_weights(int nz, int lo, const double *dz)
+{
+    std::vector<double> w(dz, dz + nz);
+    if (lo == CANS_BC_DIRICHLET_FACE)
+        for (int k = 0; k < nz; ++k) w[k] = (double)(((long double)dz[k] + dz[k + 1]) / 2);
+    return w;
+}
+
 // Conservative z coefficients of cells 0..nz-1.  Folded (a, b, c): wall
 // ghost rules applied to the diagonal, for the tridiagonal solve.  Unfolded
 // (af, cf): bare face couplings with ghost spacing at walls, for the
-// residual stencil.
+// residual stencil.  A face-located field (lo == hi ==
+// CANS_BC_DIRICHLET_FACE) takes the nz+1 widths of its cells in dzf.
 inline void zcoef(int nz, int lo, int hi, const std::vector<double> &dzf, std::vector<double> &a,
                   std::vector<double> &b, std::vector<double> &c, std::vector<double> &af,
                   std::vector<double> &cf)
 {
     a.assign(nz, 0); b.assign(nz, 0); c.assign(nz, 0); af.assign(nz, 0); cf.assign(nz, 0);
+    if (lo == CANS_BC_DIRICHLET_FACE) {
+        // unknown k on the face between cells k and k+1: couplings across
+        // one cell width, control volume of half of each cell; the wall
+        // faces hold zero, so the end rows drop their outer coupling and keep
+        // the full diagonal (the residual stencil keeps af[0], cf[nz-1] and
+        // multiplies them by the zero wall value)
+        for (int k = 0; k < nz; ++k) {
+            const long double below = dzf[k], above = dzf[k + 1], cv = (below + above) / 2;
+            const long double ak = 1 / (below * cv), ck = 1 / (above * cv);
+            af[k] = a[k] = (double)ak;
+            cf[k] = c[k] = (double)ck;
+            b[k] = (double)-(ak + ck);
+        }
+        a[0] = 0;
+        c[nz - 1] = 0;
+        return;
+    }
     for (int k = 0; k < nz; ++k) {
         const long double f = dzf[k];
         long double cm, cp;

@@ -162,9 +162,11 @@ struct LapArgs {
     double shift;       // Helmholtz shift s: the operator is L_h + s
 };
 
+// neighbour across a wall by its ghost rule: periodic wraps, Neumann
+// mirrors, Dirichlet is antisymmetric, a face-located field is zero there
 CANS_HD double ghost(int bc, double inner, double wrap)
 {
-    return bc == 0 ? wrap : (bc == 1 ? inner : -inner);
+    return bc == 0 ? wrap : (bc == 1 ? inner : (bc == 3 ? 0.0 : -inner));
 }
 
 CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)

@@ -109,10 +109,10 @@ int setup(Setup &s, int nx, int ny, int nz, const int *bc, double dx, double dy,
 {
     s.nx = nx; s.ny = ny; s.nz = nz; s.dx = dx; s.dy = dy;
     for (int i = 0; i < 6; ++i) s.bc[i] = bc[i];
-    s.kx = axis_kind(bc[0], bc[1]); s.ky = axis_kind(bc[2], bc[3]); s.kz = axis_kind(bc[4], bc[5]);
+    s.kx = axis_kind(bc[0], bc[1]); s.ky = axis_kind(bc[2], bc[3]); s.kz = z_kind(bc[4], bc[5]);
     if (s.kx < 0 || s.ky < 0 || s.kz < 0) return -1;
-    s.dzf.assign(dz, dz + nz);
-    zcoef(nz, bc[4], bc[5], s.dzf, s.za, s.zb, s.zc, s.zaf, s.zcf);
+    s.dzf = z_weights(nz, bc[4], dz);
+    zcoef(nz, bc[4], bc[5], std::vector<double>(dz, dz + z_widths(nz, bc[4])), s.za, s.zb, s.zc, s.zaf, s.zcf);
     s.lamx = lambdas(s.kx, nx, dx);
     s.lamy = lambdas(s.ky, ny, dy);
     const size_t N = (size_t)nx * ny * nz;
@@ -123,7 +123,7 @@ int setup(Setup &s, int nx, int ny, int nz, const int *bc, double dx, double dy,
     z.lamx = s.lamx.data(); z.lamy = s.lamy.data();
     z.dzf = s.dzf.data();
     long double ws = 0;
-    for (int k = 0; k < nz; ++k) ws += dz[k];
+    for (int k = 0; k < nz; ++k) ws += s.dzf[k];
     z.wsum = (double)ws;
     z.scale = 1.0 / ((double)xform_scale(s.kx, nx) * (double)xform_scale(s.ky, ny));
     z.cyclic = s.kz == K_P;

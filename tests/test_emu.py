@@ -87,6 +87,24 @@ def test_solve_every_bc(xp, yp, zp):
     assert rel(pr, po) < 1e-10
 
 
+@pytest.mark.parametrize("xy", [(P, P, P, P), (N, N, D, N), (D, D, N, D)])
+def test_solve_face_located_z(xy):
+    """z-face-located field (code 3): the library's plan tables, z solve
+    and residual stencil against the oracle, stretched, with and without a
+    Helmholtz shift in the oracle (the emulated solve takes none)."""
+    bc = xy + (3, 3)
+    nx, ny, nz = 12, 10, 9
+    cells = inputs.tanh_dzf(nz + 1, 1.5, 2.0)
+    f = np.random.default_rng(sum(bc) + 40).standard_normal((nz, ny, nx))
+    po, mo = O.solve(f, bc, 0.3, 0.4, cells)
+    assert mo == 0.0
+    pe, info = emu.solve(f, bc, 0.3, 0.4, cells)
+    assert rel(pe, po) < 1e-12 and info[0] == 0.0
+    pr, info = emu.solve(f, bc, 0.3, 0.4, cells, max_iter=6, tol=1e-12)
+    assert info[2] == 1 and info[3] <= 1e-12
+    assert rel(pr, po) < 1e-10
+
+
 def test_zsolve_stage():
     rng = np.random.default_rng(4)
     for bc in [(P, P, N, N, N, N), (D, N, P, P, D, D), (P, P, P, P, P, P), (N, N, N, N, N, D)]:

@@ -105,3 +105,36 @@ def test_batched_fp64(c5):
             assert rel(pg, pl) < 2 * rel(po, pl), (i, e)
         assert abs(plan.info(i)["removed_mean"] - mo) < 1e-12
     plan.close()
+
+
+def test_batched_face_located_z():
+    """Face-located z fields (code 3, nz+1 cell widths) batched with
+    cell-centred ones and with each other, FP64 and FP32 + refinement."""
+    P, N, D, DF = 0, 1, 2, 3
+    shapes = [(32, 24, 17, (P, P, P, P, DF, DF)), (48, 32, 40, (N, N, D, N, DF, DF)),
+              (24, 16, 12, (P, P, P, P, N, N)), (40, 20, 70, (D, D, P, P, DF, DF))]
+    probs, rhs = [], []
+    for i, (nx, ny, nz, bc) in enumerate(shapes):
+        nw = nz + 1 if bc[4] == DF else nz
+        probs.append(inputs.Problem(nx, ny, nz, bc, 1.0 / nx, 2.0 / ny, inputs.tanh_dzf(nw, 1.5, 2.0)))
+        f = np.random.default_rng(70 + i).standard_normal((nz, ny, nx))
+        if O.is_singular(bc):
+            f -= O.weighted_mean(f, probs[-1].dzf)
+        rhs.append(f)
+    for precision in ("fp64", "fp32_refine"):
+        say("batched face-located z", precision)
+        plan = capi.BatchedPlan(probs, precision=precision, tol=1e-10, max_iter=6)
+        fs = [torch.from_numpy(f).cuda() for f in rhs]
+        ps = [torch.zeros_like(f) for f in fs]
+        plan.solve(fs, ps)
+        torch.cuda.synchronize()
+        for i, (pr, f) in enumerate(zip(probs, rhs)):
+            po, _ = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
+            pg = demean(ps[i].cpu().numpy(), pr.bc, pr.dzf)
+            if precision == "fp64":
+                assert rel(pg, po) < 1e-12, (i, rel(pg, po))
+            else:
+                info = plan.info(i)
+                assert info["converged"] and info["residual"] <= 1e-10, (i, info)
+                assert rel(pg, po) < 1e-8, (i, rel(pg, po))
+        plan.close()

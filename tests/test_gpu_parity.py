@@ -410,3 +410,42 @@ def test_helmholtz(bc):
             ro = O.residual(pg, f, bc, 1 / nx, 1 / ny, dzf, shift=s)
             assert ro <= 1.5e-10 and abs(info["residual"] - ro) <= 1e-3 * ro + 1e-16
             assert rel(pg, po) < TOL_REF
+
+
+@pytest.mark.parametrize("nz,bc", [(7, (P, P, P, P, 3, 3)), (40, (N, N, P, P, 3, 3)), (200, (D, N, N, D, 3, 3)),
+                                   (300, (P, P, N, N, 3, 3)), (600, (P, P, P, P, 3, 3))])
+def test_face_located_z(nz, bc):
+    """A field on the z faces with zero on the wall faces (the wall-normal
+    velocity of the implicit diffusion steps): nz interior faces of a
+    stretched (nz+1)-cell grid, Poisson and Helmholtz, FP64 and FP32 +
+    refinement, through every z-solve form (partitioned segments of 8 and 16
+    levels, two segments per wave, and the plain elimination beyond 512)."""
+    nx, ny = (48, 40) if nz <= 200 else (24, 20)
+    cells = inputs.tanh_dzf(nz + 1, 1.5, 2.0)
+    dx, dy = 2 * np.pi / nx, np.pi / ny
+    rng = np.random.default_rng(nz + sum(bc))
+    f = rng.standard_normal((nz, ny, nx))
+    for s in (0.0, -25.0):
+        say("face-located z", nz, bc, "shift", s)
+        po, mo = O.solve(f, bc, dx, dy, cells, shift=s)
+        assert mo == 0.0
+        for precision in ("fp64", "fp32_refine"):
+            plan = capi.Plan(nx, ny, nz, bc, dx, dy, cells, precision=precision, tol=1e-10, max_iter=6, shift=s)
+            fd = torch.from_numpy(f).cuda()
+            pd = torch.zeros_like(fd)
+            plan.solve(fd, pd)
+            torch.cuda.synchronize()
+            pg, info = pd.cpu().numpy(), plan.info()
+            plan.close()
+            assert info["removed_mean"] == 0.0
+            if precision == "fp64":
+                e = rel(pg, po)
+                if e >= TOL64:
+                    pl, _ = O.solve(f, bc, dx, dy, cells, ld=True, shift=s)
+                    assert rel(pg, pl) < 2 * rel(po, pl), (nz, bc, s, e)
+                assert O.residual(pg, f, bc, dx, dy, cells, shift=s) < 1e-12
+            else:
+                assert info["converged"] and info["residual"] <= 1e-10, info
+                ro = O.residual(pg, f, bc, dx, dy, cells, shift=s)
+                assert ro <= 1.5e-10 and abs(info["residual"] - ro) <= 1e-3 * ro + 1e-16
+                assert rel(pg, po) < TOL_REF

@@ -50,7 +50,9 @@ def _plan(nx, ny, nz, bc, dx=1.0, dy=1.0, dz=None, opts=None):
 
 @pytest.mark.parametrize("args,code", [
     ((8, 8, 8, (0, 1, 0, 0, 1, 1)), -1),      # periodic paired with Neumann
-    ((8, 8, 8, (0, 0, 0, 0, 3, 1)), -1),      # unknown boundary code
+    ((8, 8, 8, (0, 0, 0, 0, 3, 1)), -1),      # face-located z paired with Neumann
+    ((8, 8, 8, (3, 3, 0, 0, 1, 1)), -1),      # a face-located field only along z
+    ((8, 8, 8, (0, 0, 0, 0, 4, 4)), -1),      # unknown boundary code
     ((0, 8, 8, (0, 0, 0, 0, 1, 1)), -1),      # empty axis
     ((8, 8, 0, (0, 0, 0, 0, 1, 1)), -1),
     ((7, 8, 8, (0, 0, 0, 0, 1, 1)), -2),      # odd length
@@ -69,6 +71,10 @@ def test_plan_validation_spacing():
     assert _plan(8, 8, 4, (0, 0, 0, 0, 1, 1), dz=[0.1, 0.2, np.nan, 0.3]) == -1
     # periodic z must be uniform
     assert _plan(8, 8, 4, (0, 0, 0, 0, 0, 0), dz=[0.1, 0.2, 0.1, 0.3]) == -2
+    # a face-located z reads nz+1 widths: the last one is checked too
+    assert _plan(8, 8, 4, (0, 0, 0, 0, 3, 3), dz=[0.1, 0.2, 0.1, 0.3, -0.2]) == -1
+    with pytest.raises(ValueError):
+        capi.Plan(8, 8, 4, (0, 0, 0, 0, 3, 3), 1.0, 1.0, np.full(4, 0.5))
 
 
 def test_options_validation():
