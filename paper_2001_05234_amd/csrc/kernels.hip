@@ -392,7 +392,7 @@ static ZArgs zargs(const Problem &pb, double *removed);
 // Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
 // into S segments of at most MMAX levels held in registers; a wave holds
 // 64/CPB segments of the same columns (see zsolve_core.h).
-template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC>
+template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC, bool PAD = false>
 __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const int *__restrict__ done)
 {
     if (done && *done) return;
@@ -401,11 +401,11 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     __shared__ double zabc[3 * 512];  // the z coefficients, staged once per block
     __shared__ double ends[CYC ? 4 * 64 : 1];  // CYC: first/last values per column
     constexpr int SPW = 64 / CPB;  // segments per wave
-    for (int i = threadIdx.x; i < ag.nz; i += blockDim.x) {
-        zabc[i] = ag.za[i];
-        zabc[512 + i] = ag.zb[i];
-        zabc[1024 + i] = ag.zc[i];
-    }
+    // PAD: S * MMAX levels (<= 512 for every launched shape), padding rows
+    // beyond nz
+    const int nzp = PAD ? (int)(blockDim.x >> 6) * SPW * MMAX : ag.nz;
+    for (int i = threadIdx.x; i < nzp; i += blockDim.x)
+        zpad_row(ag, i, zabc[i], zabc[512 + i], zabc[1024 + i]);
     ZArgs a = ag;
     a.za = zabc;
     a.zb = zabc + 512;
@@ -417,9 +417,9 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     const int S = (int)(blockDim.x >> 6) * SPW;
     auto C = [&](int q, int s) -> double & { return coef[q * 1024 + s * CPB + c]; };
     const size_t col = (size_t)blockIdx.x * CPB + c;
-    const ZSeg sg = zseg(a.nz, S, seg);
+    const ZSeg sg = zseg(nzp, S, seg);
     ZLane<MMAX, CYC> L;
-    zp_load<MMAX, FULL>(L, data, a, col, sg);
+    zp_load<MMAX, FULL, PAD>(L, data, a, col, sg);
     double out[NQ];
     zp_reduce<MMAX, FULL>(L, a, sg, out);
 #pragma unroll
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     } else {
         zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
     }
-    zp_store<MMAX, FULL>(L, data, a, col, sg);
+    zp_store<MMAX, FULL, PAD>(L, data, a, col, sg);
     if (a.singular && blockIdx.x == 0) {
         // the singular column, left out above: projected rhs, pinned last
         // row, zero weighted mean, by one thread with coef as workspace
@@ -481,19 +481,20 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
         return check_launch();
     }
 #undef CANS_ZP
-#define CANS_ZP(MM, CPB, NT, FULLV) \
-    hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, FULLV, false>), grid, block, 0, s, data, za, done)
+    // non-periodic z always runs full segments: a ragged nz is padded to
+    // S * mmax levels with decoupled rows (the level guards of a ragged
+    // split cost ~15 % at nz = 383)
+#define CANS_ZP(MM, CPB, NT, PADV) \
+    hipLaunchKernelGGL((k_zsolve_part<T, MM, CPB, NT, true, false, PADV>), grid, block, 0, s, data, za, done)
+#define CANS_ZP2(MM, CPB, NT) do { if (full) CANS_ZP(MM, CPB, NT, false); else CANS_ZP(MM, CPB, NT, true); } while (0)
     if (zp.mmax == 8) {
-        if (full) CANS_ZP(8, 64, 1024, true); else CANS_ZP(8, 64, 1024, false);
+        CANS_ZP2(8, 64, 1024);
     } else if (zp.cpb == 64) {
-        if (full && small) CANS_ZP(16, 64, 768, true);
-        else if (full) CANS_ZP(16, 64, 1024, true);
-        else CANS_ZP(16, 64, 1024, false);
+        if (small) CANS_ZP2(16, 64, 768); else CANS_ZP2(16, 64, 1024);
     } else {
-        if (full && small) CANS_ZP(16, 32, 768, true);
-        else if (full) CANS_ZP(16, 32, 1024, true);
-        else CANS_ZP(16, 32, 1024, false);
+        if (small) CANS_ZP2(16, 32, 768); else CANS_ZP2(16, 32, 1024);
     }
+#undef CANS_ZP2
 #undef CANS_ZP
     return check_launch();
 }

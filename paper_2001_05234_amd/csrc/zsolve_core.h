@@ -268,7 +268,22 @@ CANS_HD void zrow(const ZArgs &a, int k, double lam, double gam, double &ak, dou
     }
 }
 
+// Level k of a column padded to whole segments (non-periodic z): beyond nz
+// the rows (0, -1, 0) with a zero rhs.  The last real row has c = 0, so the
+// padding decouples exactly, solves to zero (its pivot -1 + lam has modulus
+// >= 1 as lam <= 0) and leaves the real levels as they are.
+CANS_HD void zpad_row(const ZArgs &a, int k, double &ak, double &bk, double &ck)
+{
+    const bool real = k < a.nz;
+    ak = real ? a.za[k] : 0.0;
+    bk = real ? a.zb[k] : -1.0;
+    ck = real ? a.zc[k] : 0.0;
+}
+
 // FULL: every segment has exactly MMAX levels, so the level guards fold away.
+// PAD (with FULL, non-periodic): the segments cover S*MMAX >= nz levels, the
+// tables hold the padding rows of zpad_row, and only the loads and stores
+// test k < nz.
 // CYC: a second right-hand side u (Sherman-Morrison) is carried beside f.
 template <int MMAX, bool CYC = false>
 struct ZLane {
@@ -280,9 +295,10 @@ struct ZLane {
 };
 
 // load the segment's rhs (scaled) and the column's lambda
-template <int MMAX, bool FULL, typename T, bool CYC>
+template <int MMAX, bool FULL, bool PAD = false, typename T, bool CYC>
 CANS_HD void zp_load(ZLane<MMAX, CYC> &L, const T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
+    static_assert(!PAD || (FULL && !CYC), "padding is for full non-periodic segments");
     const size_t plane = (size_t)a.nx * a.ny;
     // the singular column (singular problems, column 0) is solved apart
     L.valid = col < plane && !(a.singular && col == 0);
@@ -294,7 +310,7 @@ CANS_HD void zp_load(ZLane<MMAX, CYC> &L, const T *data, const ZArgs &a, size_t 
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
         if (FULL || t < sg.m) {
-            L.f[t] = L.valid ? a.scale * (double)ptr[0] : 0.0;
+            L.f[t] = L.valid && (!PAD || sg.k0 + t < a.nz) ? a.scale * (double)ptr[0] : 0.0;
             if constexpr (CYC) {
                 const int k = sg.k0 + t;
                 L.u[t] = (k == 0 ? L.gam : 0.0) + (k == a.nz - 1 ? a.zc[a.nz - 1] : 0.0);
@@ -482,7 +498,7 @@ CANS_HD void zp_sherman_morrison(ZLane<MMAX, CYC> &L, const ZArgs &a, ZSeg sg, d
     }
 }
 
-template <int MMAX, bool FULL, typename T, bool CYC>
+template <int MMAX, bool FULL, bool PAD = false, typename T, bool CYC>
 CANS_HD void zp_store(const ZLane<MMAX, CYC> &L, T *data, const ZArgs &a, size_t col, ZSeg sg)
 {
     if (!L.valid) return;
@@ -490,7 +506,7 @@ CANS_HD void zp_store(const ZLane<MMAX, CYC> &L, T *data, const ZArgs &a, size_t
     T *ptr = data + col + plane * sg.k0;
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) {
-        if (FULL || t < sg.m) ptr[0] = (T)L.f[t];
+        if ((FULL || t < sg.m) && (!PAD || sg.k0 + t < a.nz)) ptr[0] = (T)L.f[t];
         ptr += plane;
     }
 }

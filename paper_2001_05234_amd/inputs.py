@@ -102,7 +102,8 @@ class Problem:
 def _axis_kind(lo, hi):
     if lo == P or hi == P:
         return "P" if lo == hi == P else None
-    return {(N, N): "NN", (D, D): "DD", (N, D): "ND", (D, N): "DN"}[(lo, hi)]
+    # code 3 on both z faces: a z-face-located field, zero on the walls
+    return {(N, N): "NN", (D, D): "DD", (N, D): "ND", (D, N): "DN", (3, 3): "FD"}.get((lo, hi))
 
 
 def _is_singular(bc) -> bool:

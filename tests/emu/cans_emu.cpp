@@ -163,10 +163,15 @@ void solve_pass(Setup &s, std::vector<T> &a, double *removed)
 
 // the partitioned z kernel, phase by phase over all segments and columns of a
 // block (CPB columns, S segments); the singular column is solved apart
-template <int MMAX, bool FULL, bool CYC, typename T>
+template <int MMAX, bool FULL, bool CYC, bool PAD, typename T>
 void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
 {
-    const ZArgs &a = s.z;
+    // PAD: S * MMAX levels with the kernel's padding rows in the tables
+    const int nzp = PAD ? S * MMAX : s.nz;
+    std::vector<double> pa(nzp), pb(nzp), pc(nzp);
+    for (int k = 0; k < nzp; ++k) zpad_row(s.z, k, pa[k], pb[k], pc[k]);
+    ZArgs a = s.z;
+    a.za = pa.data(); a.zb = pb.data(); a.zc = pc.data();
     const size_t plane = (size_t)s.nx * s.ny;
     constexpr int NQ = CYC ? 8 : 6;
     std::vector<ZLane<MMAX, CYC>> L((size_t)S * cpb);
@@ -175,11 +180,11 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
     auto lane = [&](int seg, int c) -> ZLane<MMAX, CYC> & { return L[(size_t)seg * cpb + c]; };
     for (size_t blk = 0; blk * cpb < plane; ++blk) {
         for (int w = 0; w < S; ++w)
-            for (int c = 0; c < cpb; ++c) zp_load<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
+            for (int c = 0; c < cpb; ++c) zp_load<MMAX, FULL, PAD>(lane(w, c), data, a, blk * cpb + c, zseg(nzp, S, w));
         for (int w = 0; w < S; ++w)
             for (int c = 0; c < cpb; ++c) {
                 double out[NQ];
-                zp_reduce<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), out);
+                zp_reduce<MMAX, FULL>(lane(w, c), a, zseg(nzp, S, w), out);
                 for (int q = 0; q < NQ; ++q) C(q, w, c) = out[q];
             }
         for (int c = 0; c < cpb; ++c)
@@ -192,21 +197,21 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
                 const double xL = w > 0 ? C(5, w - 1, c) : 0.0, xR = w < S - 1 ? C(4, w + 1, c) : 0.0;
                 if constexpr (CYC) {
                     const double xL2 = w > 0 ? C(7, w - 1, c) : 0.0, xR2 = w < S - 1 ? C(6, w + 1, c) : 0.0;
-                    zp_finish<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), xL, xR, xL2, xR2);
+                    zp_finish<MMAX, FULL>(lane(w, c), a, zseg(nzp, S, w), xL, xR, xL2, xR2);
                 } else {
-                    zp_finish<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), xL, xR);
+                    zp_finish<MMAX, FULL>(lane(w, c), a, zseg(nzp, S, w), xL, xR);
                 }
             }
         if constexpr (CYC) {
             for (int c = 0; c < cpb; ++c) {
                 double y0, z0, yl, zl, t0, t1;
-                zp_ends<MMAX, FULL>(lane(0, c), zseg(s.nz, S, 0), &y0, &z0, &t0, &t1);
-                zp_ends<MMAX, FULL>(lane(S - 1, c), zseg(s.nz, S, S - 1), &t0, &t1, &yl, &zl);
-                for (int w = 0; w < S; ++w) zp_sherman_morrison<MMAX, FULL>(lane(w, c), a, zseg(s.nz, S, w), y0, z0, yl, zl);
+                zp_ends<MMAX, FULL>(lane(0, c), zseg(nzp, S, 0), &y0, &z0, &t0, &t1);
+                zp_ends<MMAX, FULL>(lane(S - 1, c), zseg(nzp, S, S - 1), &t0, &t1, &yl, &zl);
+                for (int w = 0; w < S; ++w) zp_sherman_morrison<MMAX, FULL>(lane(w, c), a, zseg(nzp, S, w), y0, z0, yl, zl);
             }
         }
         for (int w = 0; w < S; ++w)
-            for (int c = 0; c < cpb; ++c) zp_store<MMAX, FULL>(lane(w, c), data, a, blk * cpb + c, zseg(s.nz, S, w));
+            for (int c = 0; c < cpb; ++c) zp_store<MMAX, FULL, PAD>(lane(w, c), data, a, blk * cpb + c, zseg(nzp, S, w));
         if (a.singular && blk == 0) {
             std::vector<double> wc(s.nz), wd(s.nz);
             ZArgs as = a;
@@ -224,15 +229,17 @@ bool zsolve_part_any(Setup &s, T *data, double *removed)
     if (zp.mmax == 0) return false;
     const int S = (zp.threads / 64) * (64 / zp.cpb);
     const bool full = s.nz == S * zp.mmax;
+    // as the kernel launch: non-periodic z runs full segments, a ragged nz
+    // padded with decoupled rows
     if (s.z.cyclic) {
-        if (full) zsolve_part_mm<8, true, true>(s, data, removed, zp.cpb, S);
-        else zsolve_part_mm<8, false, true>(s, data, removed, zp.cpb, S);
+        if (full) zsolve_part_mm<8, true, true, false>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<8, false, true, false>(s, data, removed, zp.cpb, S);
     } else if (zp.mmax == 8) {
-        if (full) zsolve_part_mm<8, true, false>(s, data, removed, zp.cpb, S);
-        else zsolve_part_mm<8, false, false>(s, data, removed, zp.cpb, S);
+        if (full) zsolve_part_mm<8, true, false, false>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<8, true, false, true>(s, data, removed, zp.cpb, S);
     } else {
-        if (full) zsolve_part_mm<16, true, false>(s, data, removed, zp.cpb, S);
-        else zsolve_part_mm<16, false, false>(s, data, removed, zp.cpb, S);
+        if (full) zsolve_part_mm<16, true, false, false>(s, data, removed, zp.cpb, S);
+        else zsolve_part_mm<16, true, false, true>(s, data, removed, zp.cpb, S);
     }
     return true;
 }
