@@ -18,6 +18,7 @@ the CPU oracle's rate on a bounded sample of the same grid.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -122,7 +123,7 @@ def workload_text(name, pr, xform_x):
     """What is solved: sizes, boundary pairs, grid and rhs of the problem."""
     import numpy as np
 
-    code = "PND"
+    code = "PNDF"  # F: Dirichlet on a z-face-located field
     bc = "/".join(code[pr.bc[2 * a]] + code[pr.bc[2 * a + 1]] for a in range(3))
     grid = "uniform z" if np.allclose(pr.dzf, pr.dzf[0]) else "tanh-stretched z (a=1.5)"
     rhs = ("divergence of a seeded N(0,1) staggered velocity" if pr.rhs_kind == "divergence"
@@ -255,7 +256,15 @@ def main():
                     help="plans replay each solve as one recorded HIP graph (cans_opts.graph)")
     ap.add_argument("--xform-x", default="auto", choices=["auto", "fft", "dense"],
                     help="x transform form of the refinement plan (dense: split-bf16 matrix-core products)")
+    ap.add_argument("--shift", type=float, default=0.0,
+                    help="Helmholtz shift s <= 0 of (L_h + s) p = f (a side workload: with --solve-only "
+                         "or --fp64-only)")
+    ap.add_argument("--face-z", action="store_true",
+                    help="the field on the nz-1 interior z faces of the config's grid, zero on the walls, "
+                         "uniform random rhs (a side workload: with --solve-only or --fp64-only)")
     args = ap.parse_args()
+    if (args.shift != 0.0 or args.face_z) and not (args.solve_only or args.fp64_only):
+        ap.error("--shift and --face-z time side workloads: add --solve-only or --fp64-only")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -281,6 +290,11 @@ def main():
     if not (args.no_batched or args.solve_only or args.fp64_only or args.kernel_only):
         batched = bench_batched(torch, capi, inputs, args)
     pr = inputs.config(args.config)
+    if args.face_z:
+        # the wall-normal velocity's grid: the interior faces of the config's
+        # cells (the nz cell widths stay the plan's dz)
+        pr = dataclasses.replace(pr, nz=pr.nz - 1, bc=tuple(pr.bc[:4]) + (3, 3), rhs_kind="uniform",
+                                 seed=pr.seed + 1000)
     say(f"[bench] generating {args.config} rhs {pr.nx}x{pr.ny}x{pr.nz}")
     f = pr.rhs()
     fd = torch.from_numpy(f).cuda()
@@ -289,7 +303,7 @@ def main():
 
     if args.fp64_only:
         plan64 = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
-                           autotune=not args.no_autotune, graph=args.graph)
+                           autotune=not args.no_autotune, graph=args.graph, shift=args.shift)
         if args.kernel_only:
             name = [n for s, n, _ in KERNELS64 if s == args.kernel_only][0]
             b = torch.zeros_like(fd)
@@ -298,11 +312,13 @@ def main():
             print(json.dumps({"kernel": name, "kernel_ms": t, "plan": "fp64"}), flush=True)
             return
         ms64, _ = time_solves(plan64, fd, pd, args.steps, args.warmup, torch)
-        print(json.dumps({"fp64_ms_per_step": ms64, "value": npts / (ms64 * 1e-3)}), flush=True)
+        print(json.dumps({"fp64_ms_per_step": ms64, "value": npts / (ms64 * 1e-3), "shift": args.shift,
+                          "face_z": args.face_z, "grid": [pr.nx, pr.ny, pr.nz]}), flush=True)
         return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
-                     tol=1e-10, max_iter=4, autotune=not args.no_autotune, xform_x=args.xform_x, graph=args.graph)
+                     tol=1e-10, max_iter=4, autotune=not args.no_autotune, xform_x=args.xform_x, graph=args.graph,
+                     shift=args.shift)
     if args.kernel_only:
         # the stages before it fill the plan's spectral field as in a solve
         a32 = torch.zeros_like(fd)
@@ -326,6 +342,8 @@ def main():
                    "grid_points": npts, "corrections": info["iterations"], "graph": args.graph,
                    "residual": info["residual"], "residual_inf": info["residual_inf"], "wall_s": wall},
     }
+    if args.shift != 0.0 or args.face_z:
+        out["config"].update({"shift": args.shift, "face_z": args.face_z, "grid": [pr.nx, pr.ny, pr.nz]})
     if args.solve_only:
         print(json.dumps(out), flush=True)
         return
