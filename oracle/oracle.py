@@ -214,3 +214,71 @@ def residual_inf(p, f, bc, dx, dy, dzf, shift: float = 0.0):
         f = f - weighted_mean(f, dzf)
     r = f - apply_L(p, bc, dx, dy, dzf, shift)
     return float(np.abs(r).max() / np.abs(f).max())
+
+
+# --------------------------------------------------------------------------- #
+# Pressure-correction (projection) step around the solve, the equations that
+# follow eq. (up): Phi solves L_h Phi = D u* / (gamma dt), then
+# u = u* - gamma dt G Phi and p = p + Phi.  Staggered velocity: u on the +x
+# face of each cell, v on the +y face, w on the +z face (arrays (nz, ny, nx),
+# x fastest).  Every axis is periodic or bounded by walls (pressure Neumann):
+# there the normal velocity below the first cell is zero and the entries on
+# the last (wall) face are boundary values, left as given.
+
+def _axis_periodic(bc, axis: int) -> bool:
+    lo, hi = bc[2 * axis], bc[2 * axis + 1]
+    assert (lo, hi) in ((P, P), (N, N)), "projection needs periodic or wall (Neumann) pressure boundaries"
+    return lo == P
+
+
+def _face_below(a, arr_axis: int, periodic: bool):
+    """Value on the face below each cell: the previous face, wrapping when
+    periodic, zero at a wall."""
+    if periodic:
+        return np.roll(a, 1, arr_axis)
+    out = np.zeros_like(a)
+    dst = [slice(None)] * 3; src = [slice(None)] * 3
+    dst[arr_axis] = slice(1, None); src[arr_axis] = slice(0, -1)
+    out[tuple(dst)] = a[tuple(src)]
+    return out
+
+
+def divergence(u, v, w, bc, dx: float, dy: float, dzf):
+    """D u at the cell centres: (u - u_below)/dx + (v - v_below)/dy +
+    (w - w_below)/dzf_k."""
+    u, v, w = _f64(u), _f64(v), _f64(w)
+    dzf = _f64(dzf)
+    px, py, pz = (_axis_periodic(bc, a) for a in range(3))
+    return ((u - _face_below(u, 2, px)) / dx + (v - _face_below(v, 1, py)) / dy
+            + (w - _face_below(w, 0, pz)) / dzf[:, None, None])
+
+
+def gradient(phi, bc, dx: float, dy: float, dzf):
+    """G Phi on the +faces: (Phi_next - Phi) over the centre distance (dx,
+    dy, dzc_k = (dzf_k + dzf_{k+1})/2); the next cell wraps across a periodic
+    boundary, and the gradient is zero on a wall face."""
+    phi = _f64(phi)
+    dzf = _f64(dzf)
+    nz = phi.shape[0]
+    px, py, pz = (_axis_periodic(bc, a) for a in range(3))
+    gx = (np.roll(phi, -1, 2) - phi) / dx
+    gy = (np.roll(phi, -1, 1) - phi) / dy
+    dzc = 0.5 * (dzf + np.roll(dzf, -1))
+    gz = (np.roll(phi, -1, 0) - phi) / dzc[:, None, None]
+    if not px:
+        gx[:, :, -1] = 0.0
+    if not py:
+        gy[:, -1, :] = 0.0
+    if not pz:
+        gz[nz - 1] = 0.0
+    return gx, gy, gz
+
+
+def project(u, v, w, p, bc, dx: float, dy: float, dzf, gdt: float):
+    """One projection step with gdt = gamma dt: returns (u, v, w, p, Phi)
+    after Phi = L_h^{-1} (D u / gdt) (zero weighted mean), u -= gdt G Phi,
+    p += Phi."""
+    f = divergence(u, v, w, bc, dx, dy, dzf) / gdt
+    phi, _ = solve(f, bc, dx, dy, dzf)
+    gx, gy, gz = gradient(phi, bc, dx, dy, dzf)
+    return (_f64(u) - gdt * gx, _f64(v) - gdt * gy, _f64(w) - gdt * gz, _f64(p) + phi, phi)

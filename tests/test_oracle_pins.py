@@ -571,3 +571,80 @@ def test_face_z_long_double_agrees():
     p, _ = O.solve(f, bc, 0.2, 0.5, cells, shift=-2.0)
     pl, _ = O.solve(f, bc, 0.2, 0.5, cells, ld=True, shift=-2.0)
     assert rel(p, pl) < 1e-13
+
+
+# --------------------------------------------------------------------------- #
+# projection step (pressure correction after the solve)
+PROJ_BCS = [(P, P, P, P, N, N), (N, N, P, P, N, N), (P, P, N, N, P, P), (N, N, N, N, N, N)]
+
+
+def _walls_zero(u, v, w, bc):
+    """Zero normal velocity on the wall faces (the last face of a bounded axis)."""
+    if bc[0] == N:
+        u[:, :, -1] = 0
+    if bc[2] == N:
+        v[:, -1, :] = 0
+    if bc[4] == N:
+        w[-1] = 0
+    return u, v, w
+
+
+def _proj_grid(bc, nz):
+    return np.full(nz, 2.0 / nz) if bc[4] == P else inputs.tanh_dzf(nz, 1.5, 2.0)
+
+
+@pytest.mark.parametrize("bc", PROJ_BCS)
+def test_projection_step_divergence_free(bc):
+    """After the step the velocity is discretely divergence free (D G = L_h
+    with these ghost rules, whatever the solver), the wall faces keep their
+    zero normal velocity and p moves by Phi."""
+    nx, ny, nz = 12, 10, 9
+    dx, dy, dzf = 0.4, 0.3, _proj_grid(bc, nz)
+    rng = np.random.default_rng(sum(bc) + 60)
+    u, v, w = _walls_zero(*(rng.standard_normal((nz, ny, nx)) for _ in range(3)), bc)
+    p = rng.standard_normal((nz, ny, nx))
+    d0 = O.divergence(u, v, w, bc, dx, dy, dzf)
+    u1, v1, w1, p1, phi = O.project(u, v, w, p, bc, dx, dy, dzf, 0.02)
+    d1 = O.divergence(u1, v1, w1, bc, dx, dy, dzf)
+    assert np.abs(d1).max() < 1e-11 * np.abs(d0).max()
+    if bc[0] == N:
+        assert np.all(u1[:, :, -1] == 0)
+    if bc[4] == N:
+        assert np.all(w1[-1] == 0)
+    np.testing.assert_allclose(p1 - p, phi, rtol=0, atol=1e-13 * np.abs(phi).max())
+
+
+@pytest.mark.parametrize("bc", PROJ_BCS)
+def test_projection_removes_a_gradient(bc):
+    """u = G q (a pure gradient, zero on wall faces by construction) is
+    removed entirely, and Phi = q / gdt up to a constant."""
+    nx, ny, nz = 10, 8, 12
+    dx, dy, dzf = 0.5, 0.25, _proj_grid(bc, nz)
+    q = np.random.default_rng(sum(bc) + 61).standard_normal((nz, ny, nx))
+    u, v, w = O.gradient(q, bc, dx, dy, dzf)
+    gdt = 0.05
+    u1, v1, w1, p1, phi = O.project(u, v, w, np.zeros_like(q), bc, dx, dy, dzf, gdt)
+    scale = max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    for a in (u1, v1, w1):
+        assert np.abs(a).max() < 1e-12 * scale
+    d = phi - q / gdt
+    assert np.ptp(d) < 1e-11 * np.abs(q / gdt).max()
+
+
+def test_projection_keeps_a_divergence_free_field():
+    """A discrete curl (streamfunction on the cell edges, periodic x and y)
+    has zero discrete divergence: the step leaves it as it is, Phi = 0."""
+    nx, ny, nz = 12, 10, 6
+    dx, dy = 0.3, 0.7
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    bc = (P, P, P, P, N, N)
+    psi = np.random.default_rng(62).standard_normal((nz, ny, nx))  # at (i+1/2, j+1/2, k)
+    u = (psi - np.roll(psi, 1, 1)) / dy       # on the +x faces
+    v = -(psi - np.roll(psi, 1, 2)) / dx      # on the +y faces
+    w = np.zeros((nz, ny, nx))
+    assert np.abs(O.divergence(u, v, w, bc, dx, dy, dzf)).max() < 1e-12 * np.abs(u).max() / dx
+    u1, v1, w1, p1, phi = O.project(u, v, w, np.zeros_like(u), bc, dx, dy, dzf, 0.1)
+    assert np.abs(phi).max() < 1e-10
+    np.testing.assert_allclose(u1, u, rtol=0, atol=1e-11 * np.abs(u).max())
+    np.testing.assert_allclose(v1, v, rtol=0, atol=1e-11 * np.abs(v).max())
+    assert np.abs(w1).max() < 1e-11
