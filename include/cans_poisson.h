@@ -166,6 +166,30 @@ int cans_poisson_plan_ex(cans_plan_t *out, int nx, int ny, int nz, const int bc[
  */
 int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream);
 
+/*
+ * Enqueue one projection (pressure-correction) step, the equations that
+ * follow eq. (up): Phi solves L_h Phi = D u / gdt, then u -= gdt G Phi and
+ * p += Phi, with gdt = gamma_k dt > 0 of the Runge-Kutta substep.
+ *   u, v, w = staggered velocity (device, nx*ny*nz doubles each, x fastest):
+ *             element (i,j,k) of u lies on the +x face of cell (i,j,k), of v
+ *             on its +y face, of w on its +z face.  Updated in place.
+ *   p       = pressure (device, nx*ny*nz doubles), incremented by Phi.
+ * D u = (u - u_below)/dx + (v - v_below)/dy + (w - w_below)/dzf_k and G Phi =
+ * (Phi_next - Phi)/dx, /dy, /dzc_k.  Every axis must be periodic (the face
+ * below the first cell is the last face) or bounded by walls (Neumann pairs:
+ * zero normal velocity below the first cell; the last face is the wall, its
+ * value is used as given and left unchanged).  Phi has zero dzf-weighted
+ * mean; the weighted mean removed from D u / gdt is reported by
+ * cans_poisson_get_info.  The plan must be a single FP64 plan without shift
+ * and every pair periodic or Neumann, else CANS_ERR_UNSUPPORTED; u, v, w, p
+ * must be distinct arrays (CANS_ERR_ALIAS).  The first call allocates the
+ * plan's Phi field (nx*ny*nz doubles) on the current device, so that call is
+ * not capturable in a HIP graph.  Enqueued on `stream`; no host
+ * synchronisation.
+ */
+int cans_poisson_project(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
+                         hipStream_t stream);
+
 /* Copy the last solve's cans_info to *out.  Synchronises with the device, so
  * it is meant to be called after the solve's stream has been synchronised. */
 int cans_poisson_get_info(cans_plan_t plan, cans_info *out);

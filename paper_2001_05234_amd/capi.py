@@ -36,7 +36,7 @@ def z_widths(nz: int, bc) -> int:
 EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "cans_poisson_solve",
            "cans_poisson_get_info", "cans_poisson_destroy", "cans_status_string",
            "cans_poisson_workspace_bytes", "cans_poisson_debug_stage", "cans_poisson_plan_batched",
-           "cans_poisson_solve_batched", "cans_poisson_get_info_batched"]
+           "cans_poisson_solve_batched", "cans_poisson_get_info_batched", "cans_poisson_project"]
 
 
 class CansOpts(ctypes.Structure):
@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
         "cans_poisson_plan": ([pp, i, i, i, ip, d, d, dp], i),
         "cans_poisson_plan_ex": ([pp, i, i, i, ip, d, d, dp, ctypes.POINTER(CansOpts)], i),
         "cans_poisson_solve": ([vp, vp, vp, vp], i),
+        "cans_poisson_project": ([vp, vp, vp, vp, vp, d, vp], i),
         "cans_poisson_get_info": ([vp, ctypes.POINTER(CansInfo)], i),
         "cans_poisson_destroy": ([vp], None),
         "cans_status_string": ([i], ctypes.c_char_p),
@@ -167,6 +168,13 @@ class Plan:
 
     def solve(self, rhs, p, stream=None) -> None:
         _check(self._lib.cans_poisson_solve(self._h, _addr(rhs), _addr(p), _stream(stream)), "cans_poisson_solve")
+
+    def project(self, u, v, w, p, gdt: float, stream=None) -> None:
+        """One projection step (``cans_poisson_project``): u, v, w -= gdt G Phi,
+        p += Phi with L_h Phi = D u / gdt; FP64 plans with periodic or wall
+        boundaries."""
+        _check(self._lib.cans_poisson_project(self._h, _addr(u), _addr(v), _addr(w), _addr(p), float(gdt),
+                                              _stream(stream)), "cans_poisson_project")
 
     def debug_stage(self, stage: int, inp, out, stream=None) -> None:
         _check(self._lib.cans_poisson_debug_stage(self._h, stage, _addr(inp), _addr(out), _stream(stream)),

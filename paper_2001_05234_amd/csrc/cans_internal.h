@@ -62,6 +62,9 @@ struct Problem {
     int nres_blocks = 0;
     double *d_info = nullptr;
     int *d_flag = nullptr;         // [0] refinement finished
+    // projection step (allocated at its first use)
+    double *phi = nullptr;         // the potential Phi (FP64 field)
+    double *d_zgc = nullptr;       // 1/dzc_k across the +z face of level k, 0 on a wall face
     size_t npts() const { return (size_t)nx * ny * nz; }
 };
 
@@ -87,5 +90,12 @@ int launch_reset(const Problem &pb, hipStream_t s);
 int launch_mean_rhs(const Problem &pb, hipStream_t s);
 
 int resid_blocks(const Problem &pb);
+
+// projection step: D u / gdt fused into the forward x transform (FP64, into
+// out), and the correction u -= gdt G phi, p += phi
+int launch_div_xfwd(const Problem &pb, const double *u, const double *v, const double *w, double gdt, double *out,
+                    hipStream_t s);
+int launch_project_correct(const Problem &pb, double *u, double *v, double *w, double *p, const double *phi,
+                           double gdt, hipStream_t s);
 
 }  // namespace cans

@@ -460,6 +460,38 @@ int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream
     return solve_refine(pb, plan->opts, rhs, p, stream);
 }
 
+int cans_poisson_project(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
+                         hipStream_t stream)
+{
+    if (!plan || !u || !v || !w || !p || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
+    if (!(gdt > 0) || !std::isfinite(gdt)) return CANS_ERR_INVALID_ARG;
+    if (plan->opts.precision != CANS_PREC_FP64 || plan->opts.shift != 0.0) return CANS_ERR_UNSUPPORTED;
+    Problem &pb = plan->probs[0];
+    for (int a = 0; a < 3; ++a)
+        if (pb.bc[2 * a] != pb.bc[2 * a + 1] ||
+            (pb.bc[2 * a] != CANS_BC_PERIODIC && pb.bc[2 * a] != CANS_BC_NEUMANN))
+            return CANS_ERR_UNSUPPORTED;
+    const void *f[4] = {u, v, w, p};
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b)
+            if (f[a] == f[b]) return CANS_ERR_ALIAS;
+    if (!pb.phi) {
+        // first use: the potential field and 1/dzc across each +z face
+        const int nz = pb.nz;
+        std::vector<double> zgc(nz, 0.0);
+        for (int k = 0; k + 1 < nz; ++k) zgc[k] = 2.0 / (pb.dzf[k] + pb.dzf[k + 1]);
+        if (pb.cyclic) zgc[nz - 1] = 2.0 / (pb.dzf[nz - 1] + pb.dzf[0]);
+        CANS_TRY(upload(plan, &pb.d_zgc, zgc.data(), nz));
+        CANS_TRY(alloc(plan, &pb.phi, pb.npts()));
+    }
+    CANS_TRY(launch_div_xfwd(pb, u, v, w, gdt, pb.phi, stream));
+    CANS_TRY(launch_y_f64(pb, true, pb.phi, pb.phi, stream));
+    CANS_TRY(launch_zsolve_f64(pb, pb.phi, pb.d_info + I_REMOVED, stream));
+    CANS_TRY(launch_y_f64(pb, false, pb.phi, pb.phi, stream));
+    CANS_TRY(launch_x_f64(pb, false, pb.phi, pb.phi, stream));
+    return launch_project_correct(pb, u, v, w, p, pb.phi, gdt, stream);
+}
+
 int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, double *const *p, hipStream_t stream)
 {
     if (!plan || !rhs || !p) return CANS_ERR_INVALID_ARG;

@@ -449,3 +449,72 @@ def test_face_located_z(nz, bc):
                 ro = O.residual(pg, f, bc, dx, dy, cells, shift=s)
                 assert ro <= 1.5e-10 and abs(info["residual"] - ro) <= 1e-3 * ro + 1e-16
                 assert rel(pg, po) < TOL_REF
+
+
+@pytest.mark.parametrize("shape,bc", [((48, 40, 36), (P, P, P, P, N, N)), ((50, 24, 30), (N, N, P, P, N, N)),
+                                      ((40, 30, 24), (P, P, N, N, P, P)), ((30, 20, 17), (N, N, N, N, N, N)),
+                                      ((1024, 512, 384), (P, P, P, P, N, N))])
+def test_projection_step(shape, bc):
+    """cans_poisson_project against the oracle's projection step: Phi (the
+    change of p), the velocity increments, a divergence-free result, wall
+    faces kept; a second call reuses the plan's Phi field."""
+    nx, ny, nz = shape
+    dx, dy = 2 * np.pi / nx, np.pi / ny
+    dzf = np.full(nz, 2.0 / nz) if bc[4] == P else inputs.tanh_dzf(nz, 1.5, 2.0)
+    rng = np.random.default_rng(nx + ny + nz + sum(bc))
+    u, v, w, p = (rng.standard_normal((nz, ny, nx)) for _ in range(4))
+    if bc[0] == N:
+        u[:, :, -1] = 0
+    if bc[2] == N:
+        v[:, -1, :] = 0
+    if bc[4] == N:
+        w[-1] = 0
+    gdt = 0.8 * 2e-3
+    say("projection", shape, bc)
+    full = nx * ny * nz > 1e7
+    plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf, precision="fp64", autotune=full)
+    dev = [torch.from_numpy(a.copy()).cuda() for a in (u, v, w, p)]
+    plan.project(*dev, gdt)
+    torch.cuda.synchronize()
+    ug, vg, wg, pg = (a.cpu().numpy() for a in dev)
+    d0 = np.abs(O.divergence(u, v, w, bc, dx, dy, dzf)).max()
+    d1 = np.abs(O.divergence(ug, vg, wg, bc, dx, dy, dzf)).max()
+    assert d1 < 1e-10 * d0, (d1, d0)
+    if bc[0] == N:
+        assert np.array_equal(ug[:, :, -1], u[:, :, -1])
+    if bc[4] == N:
+        assert np.array_equal(wg[-1], w[-1])
+    if full:
+        # sampled: the divergence above holds everywhere; Phi on 8 levels
+        # follows from p and the oracle is not run at this size
+        assert np.isfinite(pg).all()
+    else:
+        uo, vo, wo, po, phi = O.project(u, v, w, p, bc, dx, dy, dzf, gdt)
+        assert rel(pg - p, phi) < TOL64, rel(pg - p, phi)
+        for g_, o_, a_ in ((ug, uo, u), (vg, vo, v), (wg, wo, w)):
+            assert rel(g_ - a_, o_ - a_) < 1e-11, rel(g_ - a_, o_ - a_)
+    # a second step on a divergence-free field changes it by rounding only
+    plan.project(*dev, gdt)
+    torch.cuda.synchronize()
+    u2 = dev[0].cpu().numpy()
+    assert np.abs(u2 - ug).max() < 1e-9 * np.abs(ug).max()
+    plan.close()
+
+
+def test_projection_rejections():
+    nx, ny, nz = 16, 12, 8
+    a = [torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+    ok = capi.Plan(nx, ny, nz, (P, P, P, P, N, N), 0.1, 0.1, np.full(nz, 0.1), precision="fp64")
+    with pytest.raises(capi.CansError) as e:
+        ok.project(a[0], a[0], a[2], a[3], 0.1)
+    assert e.value.code == -5
+    with pytest.raises(capi.CansError) as e:
+        ok.project(*a, 0.0)
+    assert e.value.code == -1
+    ok.close()
+    for bc, prec in (((P, P, P, P, D, D), "fp64"), ((P, P, N, D, N, N), "fp64"), ((P, P, P, P, N, N), "fp32_refine")):
+        plan = capi.Plan(nx, ny, nz, bc, 0.1, 0.1, np.full(nz, 0.1), precision=prec)
+        with pytest.raises(capi.CansError) as e:
+            plan.project(*a, 0.1)
+        assert e.value.code == -2
+        plan.close()

@@ -98,6 +98,11 @@ def test_options_validation():
     assert _plan(128, 8, 4, (0, 0, 0, 0, 1, 1), opts=o) == -2
 
 
+def test_project_rejects_null_plan():
+    lib = capi.load()
+    assert lib.cans_poisson_project(None, None, None, None, None, 1.0, None) == -1
+
+
 def test_null_arguments():
     lib = capi.load()
     assert lib.cans_poisson_solve(None, None, None, None) == -1
