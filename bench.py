@@ -163,6 +163,41 @@ def copy_gbs(torch, nbytes):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def bench_project(torch, capi, pr, args):
+    """The projection step on the config's grid: seeded N(0,1) staggered
+    velocity (zero on wall faces) and pressure, gdt = 1.6e-3, FP64.  Byte
+    model per point: divergence fused into the x transform 24 + 8, the y, z,
+    y and x sweeps 4 x 16, the correction 40 + 32: 168 B."""
+    import numpy as np
+
+    rng = np.random.default_rng(pr.seed + 2000)
+    fields = []
+    for a in range(4):
+        x = rng.standard_normal((pr.nz, pr.ny, pr.nx))
+        if a < 3 and pr.bc[2 * a] != 0:  # wall: the last face of a bounded axis
+            idx = [slice(None)] * 3
+            idx[2 - a] = -1
+            x[tuple(idx)] = 0.0
+        fields.append(torch.from_numpy(x).cuda())
+        del x
+    plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp64",
+                     autotune=not args.no_autotune)
+    for _ in range(args.warmup):
+        plan.project(*fields, 1.6e-3)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(args.steps):
+        plan.project(*fields, 1.6e-3)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / args.steps
+    plan.close()
+    return {"projection_ms_per_step": ms, "grid_pts_per_s": pr.npts / (ms * 1e-3),
+            "algorithmic_GBps": 168 * pr.npts / (ms * 1e-3) / 1e9, "bytes_per_point": 168,
+            "grid": [pr.nx, pr.ny, pr.nz], "steps": args.steps}
+
+
 def bench_batched(torch, capi, inputs, args):
     """64 uneven problems (sizes, boundary sets and stretching drawn from a
     seed) solved as one graph launch, FP32 transforms + FP64 refinement."""
@@ -259,6 +294,8 @@ def main():
     ap.add_argument("--shift", type=float, default=0.0,
                     help="Helmholtz shift s <= 0 of (L_h + s) p = f (a side workload: with --solve-only "
                          "or --fp64-only)")
+    ap.add_argument("--project", action="store_true",
+                    help="time the projection step (cans_poisson_project, FP64) on the config's grid instead")
     ap.add_argument("--face-z", action="store_true",
                     help="the field on the nz-1 interior z faces of the config's grid, zero on the walls, "
                          "uniform random rhs (a side workload: with --solve-only or --fp64-only)")
@@ -287,9 +324,12 @@ def main():
     # the same batch was measured 30-40 % slower (it persists after their
     # memory is freed), so each figure is taken in a fresh state
     batched = None
-    if not (args.no_batched or args.solve_only or args.fp64_only or args.kernel_only):
+    if not (args.no_batched or args.solve_only or args.fp64_only or args.kernel_only or args.project):
         batched = bench_batched(torch, capi, inputs, args)
     pr = inputs.config(args.config)
+    if args.project:
+        print(json.dumps(bench_project(torch, capi, pr, args)), flush=True)
+        return
     if args.face_z:
         # the wall-normal velocity's grid: the interior faces of the config's
         # cells (the nz cell widths stay the plan's dz)

@@ -181,8 +181,9 @@ inline void zcoef(int nz, int lo, int hi, const std::vector<double> &dzf, std::v
         // unknown k on the face between cells k and k+1: couplings across
         // one cell width, control volume of half of each cell; the wall
         // faces hold zero, so the end rows drop their outer coupling and keep
-        // the full diagonal (the residual stencil keeps af[0], cf[nz-1] and
-        // multiplies them by the zero wall value)
+        // the full diagonal.  The residual stencil applies the antisymmetric
+        // ghost at these walls, so its wall couplings af[0], cf[nz-1] are
+        // halved: (a/2)(w - (-w)) = a w, exactly the zero wall value.
         for (int k = 0; k < nz; ++k) {
             const long double below = dzf[k], above = dzf[k + 1], cv = (below + above) / 2;
             const long double ak = 1 / (below * cv), ck = 1 / (above * cv);
@@ -192,6 +193,8 @@ inline void zcoef(int nz, int lo, int hi, const std::vector<double> &dzf, std::v
         }
         a[0] = 0;
         c[nz - 1] = 0;
+        af[0] *= 0.5;
+        cf[nz - 1] *= 0.5;
         return;
     }
     for (int k = 0; k < nz; ++k) {

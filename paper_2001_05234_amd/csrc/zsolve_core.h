@@ -163,10 +163,12 @@ struct LapArgs {
 };
 
 // neighbour across a wall by its ghost rule: periodic wraps, Neumann
-// mirrors, Dirichlet is antisymmetric, a face-located field is zero there
+// mirrors, Dirichlet is antisymmetric.  A face-located field (code 3) takes
+// the antisymmetric ghost too, with its wall coupling halved in the tables:
+// (a/2)(w - (-w)) = a (w - 0) exactly, its zero wall value.
 CANS_HD double ghost(int bc, double inner, double wrap)
 {
-    return bc == 0 ? wrap : (bc == 1 ? inner : (bc == 3 ? 0.0 : -inner));
+    return bc == 0 ? wrap : (bc == 1 ? inner : -inner);
 }
 
 CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
