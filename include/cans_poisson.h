@@ -184,8 +184,9 @@ int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream
  * and every pair periodic or Neumann, else CANS_ERR_UNSUPPORTED; u, v, w, p
  * must be distinct arrays (CANS_ERR_ALIAS).  The first call allocates the
  * plan's Phi field (nx*ny*nz doubles) on the current device, so that call is
- * not capturable in a HIP graph.  Enqueued on `stream`; no host
- * synchronisation.
+ * not capturable in a HIP graph.  It shares the plan's Phi field and info
+ * record, so, as for solves, one call may be in flight per plan.  Enqueued
+ * on `stream`; no host synchronisation.
  */
 int cans_poisson_project(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
                          hipStream_t stream);
