@@ -138,3 +138,36 @@ def test_batched_face_located_z():
                 assert info["converged"] and info["residual"] <= 1e-10, (i, info)
                 assert rel(pg, po) < 1e-8, (i, rel(pg, po))
         plan.close()
+
+
+def test_batched_helmholtz():
+    """A batch with a Helmholtz shift (one shift for the plan): cell-centred
+    and face-located members, FP64 and FP32 + refinement; nothing removed."""
+    P, N, D, DF = 0, 1, 2, 3
+    s = -40.0
+    shapes = [(32, 24, 16, (P, P, P, P, N, N)), (48, 16, 23, (N, N, D, N, DF, DF)), (24, 32, 12, (P, P, N, N, P, P))]
+    probs, rhs = [], []
+    for i, (nx, ny, nz, bc) in enumerate(shapes):
+        nw = nz + 1 if bc[4] == DF else nz
+        dzf = np.full(nw, 2.0 / nw) if bc[4] == P else inputs.tanh_dzf(nw, 1.5, 2.0)
+        probs.append(inputs.Problem(nx, ny, nz, bc, 1.0 / nx, 2.0 / ny, dzf))
+        rhs.append(np.random.default_rng(90 + i).standard_normal((nz, ny, nx)))
+    for precision in ("fp64", "fp32_refine"):
+        say("batched helmholtz", precision)
+        plan = capi.BatchedPlan(probs, precision=precision, tol=1e-10, max_iter=6, shift=s)
+        fs = [torch.from_numpy(f).cuda() for f in rhs]
+        ps = [torch.zeros_like(f) for f in fs]
+        plan.solve(fs, ps)
+        torch.cuda.synchronize()
+        for i, (pr, f) in enumerate(zip(probs, rhs)):
+            po, mo = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, shift=s)
+            assert mo == 0.0
+            pg = ps[i].cpu().numpy()
+            info = plan.info(i)
+            assert info["removed_mean"] == 0.0
+            if precision == "fp64":
+                assert rel(pg, po) < 1e-12, (i, rel(pg, po))
+            else:
+                assert info["converged"] and info["residual"] <= 1e-10, (i, info)
+                assert rel(pg, po) < 1e-8, (i, rel(pg, po))
+        plan.close()

@@ -22,10 +22,10 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def dense_solve(f, bc, dx, dy, dzf, max_iter=6):
+def dense_solve(f, bc, dx, dy, dzf, max_iter=6, shift=0.0):
     nz, ny, nx = f.shape
     plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf, precision="fp32_refine", tol=1e-10, max_iter=max_iter,
-                     xform_x="dense")
+                     xform_x="dense", shift=shift)
     fd = torch.from_numpy(f).cuda()
     pd = torch.zeros_like(fd)
     plan.solve(fd, pd)
@@ -53,6 +53,24 @@ def test_dense_x_every_kind(nx, xp):
     # the first residual shows the dense form's accuracy: split bf16 products
     # carry ~16 significant bits, amplified by the operator to ~1e-3
     assert info["history"][0] < 1e-2 and info["iterations"] <= 4
+
+
+@pytest.mark.parametrize("bc,s", [((D, N, P, P, 3, 3), 0.0), ((D, N, P, P, 3, 3), -25.0),
+                                  ((N, N, P, P, N, N), -25.0)])
+def test_dense_x_helmholtz_and_face_z(bc, s):
+    """The dense x form with a Helmholtz shift and with a z-face-located
+    field (the residual fused into the dense transform uses the halved wall
+    couplings)."""
+    nx, ny, nz = 256, 12, 9
+    cells = inputs.tanh_dzf(nz + 1 if bc[4] == 3 else nz, 1.5, 2.0)
+    f = np.random.default_rng(7 + sum(bc)).standard_normal((nz, ny, nx))
+    say("dense", bc, s)
+    po, mo = O.solve(f, bc, 1 / nx, 1 / ny, cells, shift=s)
+    assert mo == 0.0
+    pg, info = dense_solve(f, bc, 1 / nx, 1 / ny, cells, shift=s)
+    assert info["converged"] and info["residual"] <= 1e-10, info
+    assert O.residual(pg, f, bc, 1 / nx, 1 / ny, cells, shift=s) <= 1.5e-10
+    assert rel(pg, po) < 1e-8
 
 
 def test_dense_c4_full_size():
