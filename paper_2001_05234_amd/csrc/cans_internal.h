@@ -68,7 +68,7 @@ struct Problem {
     size_t npts() const { return (size_t)nx * ny * nz; }
 };
 
-// ---- launchers (kernels.hip) ----------------------------------------------
+// ---- launchers (k_xform.hip, k_zsolve.hip, k_resid.hip, k_project.hip) -----
 // x transform of nlines contiguous lines; dir 1 forward, 0 inverse.
 // Tin/Tout: double or float; epi 0 store, 1 update p += v - info[I_MEANP].
 int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s);

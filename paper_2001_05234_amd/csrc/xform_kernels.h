@@ -1,0 +1,152 @@
+// xform_kernels.h -- the x and y transform kernels (LDS radix FFT) and the
+// dense matrix-core x kernel of Section 2's F^x, F^y (eq. (poi_reduced)),
+// as templates; each k_*.hip translation unit instantiates the ones its
+// launchers use.
+#pragma once
+
+#include "kcommon.h"
+
+namespace cans {
+
+
+// 145 VGPRs and run 3 (the cap costs them a small spill and is faster).
+template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
+                                                      const cx<T> *__restrict__ tw,
+                                                      const double *__restrict__ info,
+                                                      const int *__restrict__ done,
+                                                      const double *__restrict__ dzf, int ny,
+                                                      double *__restrict__ wsum_part)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile<AX_X, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
+    const int n = g.n;
+    const long line0 = (long)blockIdx.x * g.L;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
+    const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
+    auto put = [&](int q, int l, T v) {
+        const long line = line0 + l;
+        if (line < nlines) {
+            const size_t idx = (size_t)line * n + q;
+            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
+            else out[idx] = (Tout)v;
+        }
+    };
+    // inverse real-DFT / DCT / DST synthesis reads every input twice: stage
+    // the lines in LDS with coalesced loads first
+    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
+    if constexpr (STAGED) {
+        for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
+            const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
+            const long line = line0 + l;
+            tile_real(tile, e, l) = line < nlines ? (T)in[line * n + e] : T(0);
+        }
+        __syncthreads();
+        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
+        tile_transform<KIND, FWD, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    } else {
+        double acc = 0;
+        auto src = [&](int e, int l) -> T {
+            const long line = line0 + l;
+            if (line >= nlines) return T(0);
+            const Tin x = in[line * n + e];
+            if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
+            return (T)x;
+        };
+        tile_transform<KIND, FWD, AX_X, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
+                                                     BlockSync());
+        if (wsum_part) {
+            double z1 = 0, z2 = 0;
+            block_sum3(acc, z1, z2);
+            if (threadIdx.x == 0) {
+                wsum_part[kNP * blockIdx.x] = acc;
+            }
+        }
+    }
+}
+
+// y transform: tile (t, k) holds columns i0 .. i0+L-1 of plane k, all ny
+// rows; each global row segment of L elements is contiguous.
+template <int KIND, bool FWD, typename T, typename Tio>
+__global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, int nx, int ny, int ntx, XGeom g,
+                                                      const cx<T> *__restrict__ tw,
+                                                      const int *__restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile<AX_Y, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = (int)(t % ntx) * g.L;
+    const size_t base = (size_t)(t / ntx) * nx * ny;
+    auto put = [&](int q, int l, T v) {
+        const int i = i0 + l;
+        if (i < nx) out[base + (size_t)q * nx + i] = (Tio)v;
+    };
+    // y tiles read their rows directly (staging through LDS measured slower)
+    constexpr bool STAGED = false;
+    if constexpr (STAGED) {
+        for (int idx = threadIdx.x; idx < ny * g.L; idx += kThreads) {
+            const int l = idx & (g.L - 1), e = idx >> g.lgL, i = i0 + l;
+            tile_real(tile, e, l) = i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+        }
+        __syncthreads();
+        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
+        tile_transform<KIND, FWD, AX_Y, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    } else {
+        auto src = [&](int e, int l) -> T {
+            const int i = i0 + l;
+            return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+        };
+        tile_transform<KIND, FWD, AX_Y, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
+                                                     BlockSync());
+    }
+}
+
+// Residual of the current p fused with the forward x transform of it:
+//   r = (f - removed mean) - L_h p   (FP64), out = T_x r (FP32);
+
+// ---------------------------------------------------------------------------
+// Dense (matrix-core) x transforms of the refinement path: the same prologues
+// and epilogues as the FFT kernels around dense_transform (32 lines a block).
+template <bool FWD, typename Tin, typename Tout, int EPI>
+__global__ __launch_bounds__(256) void k_dense_x(const Tin *in, Tout *out, long nlines, int n, unsigned magn,
+                                                 const unsigned short *__restrict__ Wh,
+                                                 const unsigned short *__restrict__ Wl,
+                                                 const double *__restrict__ info, const int *__restrict__ done,
+                                                 const double *__restrict__ dzf, int ny,
+                                                 double *__restrict__ wsum_part)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long line0 = (long)blockIdx.x * kDenseLines;
+    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
+    double acc = 0;
+    auto src = [&](int e, int l) -> float {
+        const long line = line0 + l;
+        if (line >= nlines) return 0.f;
+        const Tin x = in[line * n + e];
+        if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
+        return (float)x;
+    };
+    const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
+    auto put = [&](int q, int l, float v) {
+        const long line = line0 + l;
+        if (line < nlines) {
+            const size_t idx = (size_t)line * n + q;
+            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
+            else out[idx] = (Tout)v;
+        }
+    };
+    dense_transform(n, magn, src, put, Wh, Wl, reinterpret_cast<unsigned short *>(smem));
+    if (wsum_part) {
+        double z1 = 0, z2 = 0;
+        block_sum3(acc, z1, z2);
+        if (threadIdx.x == 0) {
+            wsum_part[kNP * blockIdx.x] = acc;
+        }
+    }
+}
+
+}  // namespace cans
