@@ -155,8 +155,13 @@ int cans_poisson_plan_ex(cans_plan_t *out, int nx, int ny, int nz, const int bc[
                          double dx, double dy, const double *dz, const cans_opts *opts);
 
 /*
- * Enqueue one solve of L_h p = rhs on `stream` and return; no host
- * synchronisation.  rhs and p are device arrays of nx*ny*nz doubles owned by
+ * Enqueue one solve of L_h p = rhs, eq. (poi) of Section 2, by the
+ * eigenfunction expansion that follows it (eq. (poi_reduced)): forward
+ * transform along x, then y; one tridiagonal solve along z per (kx, ky) pair
+ * by Gauss elimination; inverse transforms along y, then x.  FP32_REFINE plans
+ * run the transforms in FP32 and correct p by iterative refinement on the FP64
+ * residual of eq. (poi) until opts.tol (the z elimination stays FP64).
+ * Enqueued on `stream`; the call returns without host synchronisation.  rhs and p are device arrays of nx*ny*nz doubles owned by
  * the caller, alive until the stream work completes.  FP64 mode allows
  * rhs == p (in place); FP32_REFINE re-reads rhs and returns CANS_ERR_ALIAS
  * for rhs == p.  For a singular problem the rhs is projected on the range
@@ -236,12 +241,17 @@ typedef struct cans_desc {
     const double *dz;   /* host, nz cell widths (nz+1 for a face-located z) */
 } cans_desc;
 
-/* Build one plan holding `count` problems (each validated as above). */
+/* Build one plan holding `count` independent problems, each the eq. (poi)
+ * problem of Section 2 with its own sizes, boundary pairs and spacings
+ * (descs[i], validated as for cans_poisson_plan; dz is copied).  Every
+ * problem gets the tables and workspace a single plan would; opts apply to
+ * all of them.  On error nothing is allocated and *out is NULL. */
 int cans_poisson_plan_batched(cans_plan_t *out, int count, const cans_desc *descs,
                               const cans_opts *opts);
 
-/* Solve every problem of a batched plan: rhs[i], p[i] are device arrays of
- * problem i.  The whole batch is one graph launch on `stream` (no host
+/* Solve every problem of a batched plan, each by the expansion of
+ * eq. (poi_reduced) (Section 2) as cans_poisson_solve does: rhs[i], p[i] are
+ * device arrays of nx_i*ny_i*nz_i doubles of problem i.  The whole batch is one graph launch on `stream` (no host
  * synchronisation): the first call, and any call with different array
  * addresses, captures the kernels of all problems into a HIP graph whose
  * independent branches run problems concurrently; later calls replay it.

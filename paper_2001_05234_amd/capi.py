@@ -105,15 +105,29 @@ def _check(code: int, what: str) -> None:
         raise CansError(code, what)
 
 
-def _addr(x) -> int:
+def _addr(x, numel: int = -1, device: int = -1) -> int:
+    """Device address of `x`.  A torch tensor must be a contiguous float64
+    CUDA tensor; with numel / device given it must hold exactly that many
+    elements on that device (the kernels read and write the plan's full grid,
+    so a smaller array or one on another device would be accessed out of
+    bounds).  A raw integer address is passed through unchecked."""
     if isinstance(x, int):
         return x
     if hasattr(x, "data_ptr"):
         import torch
         if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous():
             raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+        if numel >= 0 and x.numel() != numel:
+            raise ValueError(f"device array holds {x.numel()} elements, the plan's grid {numel}")
+        if device >= 0 and x.device.index != device:
+            raise ValueError(f"device array is on cuda:{x.device.index}, the plan on cuda:{device}")
         return x.data_ptr()
     raise TypeError("expected a torch CUDA tensor or a device address")
+
+
+def _current_device() -> int:
+    import torch
+    return torch.cuda.current_device()
 
 
 def _stream(stream) -> int:
@@ -165,19 +179,24 @@ class Plan:
                                         dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o)),
                "cans_poisson_plan_ex")
         self._h = h
+        self.numel = nx * ny * nz
+        self.device = _current_device()
+
+    def _a(self, x) -> int:
+        return _addr(x, self.numel, self.device)
 
     def solve(self, rhs, p, stream=None) -> None:
-        _check(self._lib.cans_poisson_solve(self._h, _addr(rhs), _addr(p), _stream(stream)), "cans_poisson_solve")
+        _check(self._lib.cans_poisson_solve(self._h, self._a(rhs), self._a(p), _stream(stream)), "cans_poisson_solve")
 
     def project(self, u, v, w, p, gdt: float, stream=None) -> None:
         """One projection step (``cans_poisson_project``): u, v, w -= gdt G Phi,
         p += Phi with L_h Phi = D u / gdt; FP64 plans with periodic or wall
         boundaries."""
-        _check(self._lib.cans_poisson_project(self._h, _addr(u), _addr(v), _addr(w), _addr(p), float(gdt),
+        _check(self._lib.cans_poisson_project(self._h, self._a(u), self._a(v), self._a(w), self._a(p), float(gdt),
                                               _stream(stream)), "cans_poisson_project")
 
     def debug_stage(self, stage: int, inp, out, stream=None) -> None:
-        _check(self._lib.cans_poisson_debug_stage(self._h, stage, _addr(inp), _addr(out), _stream(stream)),
+        _check(self._lib.cans_poisson_debug_stage(self._h, stage, self._a(inp), self._a(out), _stream(stream)),
                "cans_poisson_debug_stage")
 
     def info(self) -> dict:
@@ -231,11 +250,15 @@ class BatchedPlan:
                "cans_poisson_plan_batched")
         self._h = h
         self.count = len(problems)
+        self.numels = [pr.nx * pr.ny * pr.nz for pr in problems]
+        self.device = _current_device()
 
     def solve(self, rhs_list, p_list, stream=None) -> None:
         n = self.count
-        ra = (ctypes.c_void_p * n)(*[_addr(r) for r in rhs_list])
-        pa = (ctypes.c_void_p * n)(*[_addr(p) for p in p_list])
+        if len(rhs_list) != n or len(p_list) != n:
+            raise ValueError(f"the plan holds {n} problems: {len(rhs_list)} rhs and {len(p_list)} p arrays given")
+        ra = (ctypes.c_void_p * n)(*[_addr(r, m, self.device) for r, m in zip(rhs_list, self.numels)])
+        pa = (ctypes.c_void_p * n)(*[_addr(p, m, self.device) for p, m in zip(p_list, self.numels)])
         _check(self._lib.cans_poisson_solve_batched(self._h, ra, pa, _stream(stream)), "cans_poisson_solve_batched")
 
     def info(self, index: int) -> dict:

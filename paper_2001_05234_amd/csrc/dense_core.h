@@ -5,8 +5,12 @@
 // the forward transform T (rows in the same order as the FFT path) or the
 // inverse B = s T^{-1}.  FP32 operands are split into bf16 pairs,
 // x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and the product is
-// accumulated in FP32 as hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32
-// resolution), giving close to FP32 accuracy at bf16 matrix-core rate.
+// accumulated in FP32 as hi*hi + hi*lo + lo*hi.  The pair keeps about 16
+// significant bits of x (lo drops what lies beyond bf16's 8), and the dropped
+// lo*lo term is of the same order, 2^-16 to 2^-17 relative: some 2^7 times
+// FP32's own rounding.  The products are therefore well short of FP32
+// accuracy; iterative refinement on the FP64 residual recovers the rest (one
+// more correction than the FFT form needs).
 //
 // Layout of v_mfma_f32_32x32x8 (bf16): lane l holds A[l%32][4(l/32)+i] and
 // B[4(l/32)+i][l%32] for i < 4; accumulator r of lane l is

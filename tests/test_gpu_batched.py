@@ -1,28 +1,14 @@
 """Batched solves (one graph launch for many uneven problems) against the
 oracle, through the C ABI.  Same tolerances as tests/test_gpu_parity.py."""
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2001_05234_amd import capi, inputs
+from tests.parity_checks import check_fp64, demean, rel, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
-def demean(p, bc, dzf):
-    return p - O.weighted_mean(p, dzf) if O.is_singular(bc) else p
 
 
 @pytest.fixture(scope="module")
@@ -99,10 +85,7 @@ def test_batched_fp64(c5):
     for i, (pr, f) in enumerate(zip(probs, rhs)):
         po, mo = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf)
         pg = ps[i].cpu().numpy()
-        e = rel(pg, po)
-        if e >= 1e-12:
-            pl, _ = O.solve(f, pr.bc, pr.dx, pr.dy, pr.dzf, ld=True)
-            assert rel(pg, pl) < 2 * rel(po, pl), (i, e)
+        check_fp64(pg, f, pr.bc, pr.dx, pr.dy, pr.dzf, po, case=f"batched fp64 member {i}")
         assert abs(plan.info(i)["removed_mean"] - mo) < 1e-12
     plan.close()
 

@@ -141,3 +141,41 @@ def test_binding_structs_match_header():
         header = fh.read()
     for cname, cls in [("cans_opts", capi.CansOpts), ("cans_info", capi.CansInfo), ("cans_desc", capi.CansDesc)]:
         assert _struct_fields(header, cname) == [f[0] for f in cls._fields_], cname
+
+
+class _FakeTensor:
+    """Stands in for a CUDA tensor in the binding's argument checks (no GPU here)."""
+
+    def __init__(self, numel, device=0, dtype=None, contiguous=True):
+        import torch
+        self.is_cuda = True
+        self.dtype = torch.float64 if dtype is None else dtype
+        self._numel = numel
+        self.device = type("Dev", (), {"index": device})()
+        self._contiguous = contiguous
+
+    def is_contiguous(self):
+        return self._contiguous
+
+    def numel(self):
+        return self._numel
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_binding_checks_array_size_and_device():
+    """Arrays that do not hold the plan's nx*ny*nz doubles on the plan's device
+    are refused before any call into the library (the kernels would access
+    them out of bounds)."""
+    import torch
+    assert capi._addr(_FakeTensor(60), 60, 0) == 0x1000
+    with pytest.raises(ValueError, match="elements"):
+        capi._addr(_FakeTensor(59), 60, 0)
+    with pytest.raises(ValueError, match="cuda:1"):
+        capi._addr(_FakeTensor(60, device=1), 60, 0)
+    with pytest.raises(ValueError, match="float64"):
+        capi._addr(_FakeTensor(60, dtype=torch.float32), 60, 0)
+    with pytest.raises(ValueError, match="contiguous"):
+        capi._addr(_FakeTensor(60, contiguous=False), 60, 0)
+    assert capi._addr(0x2000, 60, 0) == 0x2000  # raw addresses pass unchecked
