@@ -274,11 +274,90 @@ def gradient(phi, bc, dx: float, dy: float, dzf):
     return gx, gy, gz
 
 
-def project(u, v, w, p, bc, dx: float, dy: float, dzf, gdt: float):
+def project(u, v, w, p, bc, dx: float, dy: float, dzf, gdt: float, alpha: float = 0.0):
     """One projection step with gdt = gamma dt: returns (u, v, w, p, Phi)
-    after Phi = L_h^{-1} (D u / gdt) (zero weighted mean), u -= gdt G Phi,
-    p += Phi."""
+    after Phi = L_h^{-1} (D u / gdt) (zero weighted mean), u -= gdt G Phi and
+    the pressure update p += Phi - alpha L_h Phi.  alpha = gamma nu dt / 2
+    with implicit diffusion (the update after eq. (poi_ns_id)), 0 with
+    explicit diffusion (the update after eq. (poi_ns))."""
     f = divergence(u, v, w, bc, dx, dy, dzf) / gdt
     phi, _ = solve(f, bc, dx, dy, dzf)
     gx, gy, gz = gradient(phi, bc, dx, dy, dzf)
-    return (_f64(u) - gdt * gx, _f64(v) - gdt * gy, _f64(w) - gdt * gz, _f64(p) + phi, phi)
+    pn = _f64(p) + phi
+    if alpha != 0.0:
+        pn = pn - alpha * apply_L(phi, bc, dx, dy, dzf)
+    return (_f64(u) - gdt * gx, _f64(v) - gdt * gy, _f64(w) - gdt * gz, pn, phi)
+
+
+# --------------------------------------------------------------------------- #
+# Time-step criterion, eq. (dt): dt < min(1.65 dl^2 / nu, sqrt(3) dl / max(|u|
+# + |v| + |w|)), dl the smallest spacing.  The advective part is evaluated as
+# the Listing of Section 3 does: at the +x, +y and +z face of every cell, the
+# face-normal component is taken as it is and the two others as the
+# magnitude of the mean of their four nearest values; each is divided by the
+# spacing of its direction (dzf_k at x and y faces, the centre distance dzc_k
+# at z faces), and the sum is the local rate.  sqrt(3) over the largest rate
+# is the advective bound.  Neighbour rules (same layout as the projection
+# step): along a periodic axis indices wrap; at walls the normal component on
+# the face below the first cell is zero, and a tangential component beyond
+# the last cell is the no-slip mirror (the negative of the last cell's).
+
+def _shift_normal_below(a, arr_axis: int, periodic: bool):
+    """Normal component on the face below (index - 1 along its own axis)."""
+    return _face_below(a, arr_axis, periodic)
+
+
+def _shift_tangential_above(a, arr_axis: int, periodic: bool):
+    """Tangential component at index + 1 across an axis: wraps, or beyond a
+    wall the no-slip mirror -a of the last cell."""
+    if periodic:
+        return np.roll(a, -1, arr_axis)
+    out = np.empty_like(a)
+    dst = [slice(None)] * 3; src = [slice(None)] * 3
+    dst[arr_axis] = slice(0, -1); src[arr_axis] = slice(1, None)
+    out[tuple(dst)] = a[tuple(src)]
+    dst[arr_axis] = slice(-1, None); src[arr_axis] = slice(-1, None)
+    out[tuple(dst)] = -a[tuple(src)]
+    return out
+
+
+def dt_rates(u, v, w, bc, dx: float, dy: float, dzf):
+    """Advective rates (rx, ry, rz) at the +x, +y and +z face of every cell,
+    arrays (nz, ny, nx), as defined above."""
+    u, v, w, dzf = _f64(u), _f64(v), _f64(w), _f64(dzf)
+    px, py, pz = (_axis_periodic(bc, a) for a in range(3))
+    # array axes: 2 = x, 1 = y, 0 = z
+    v_s = _shift_normal_below(v, 1, py)
+    w_b = _shift_normal_below(w, 0, pz)
+    u_w = _shift_normal_below(u, 2, px)
+    # x face (i+1/2, j, k): v at (i|i+1, j-1|j), w at (i|i+1, k-1|k)
+    vx = 0.25 * np.abs(v + v_s + _shift_tangential_above(v, 2, px) + _shift_tangential_above(v_s, 2, px))
+    wx = 0.25 * np.abs(w + w_b + _shift_tangential_above(w, 2, px) + _shift_tangential_above(w_b, 2, px))
+    idzf = (1.0 / dzf)[:, None, None]
+    rx = np.abs(u) / dx + vx / dy + wx * idzf
+    # y face (i, j+1/2, k): u at (i-1|i, j|j+1), w at (j|j+1, k-1|k)
+    uy = 0.25 * np.abs(u + u_w + _shift_tangential_above(u, 1, py) + _shift_tangential_above(u_w, 1, py))
+    wy = 0.25 * np.abs(w + w_b + _shift_tangential_above(w, 1, py) + _shift_tangential_above(w_b, 1, py))
+    ry = uy / dx + np.abs(v) / dy + wy * idzf
+    # z face (i, j, k+1/2): u at (i-1|i, k|k+1), v at (j-1|j, k|k+1)
+    uz = 0.25 * np.abs(u + u_w + _shift_tangential_above(u, 0, pz) + _shift_tangential_above(u_w, 0, pz))
+    vz = 0.25 * np.abs(v + v_s + _shift_tangential_above(v, 0, pz) + _shift_tangential_above(v_s, 0, pz))
+    nz = dzf.shape[0]
+    dzc = np.empty(nz)
+    dzc[:-1] = 0.5 * (dzf[:-1] + dzf[1:])
+    dzc[-1] = 0.5 * (dzf[-1] + dzf[0]) if pz else dzf[-1]   # wall face: mirror ghost cell
+    rz = uz / dx + vz / dy + np.abs(w) / dzc[:, None, None]
+    return rx, ry, rz
+
+
+def max_dt(u, v, w, bc, dx: float, dy: float, dzf, nu: float = 0.0) -> float:
+    """The bound of eq. (dt): min(sqrt(3) / max rate, 1.65 dl^2 / nu) with dl
+    = min(dx, dy, min dzf); nu = 0 omits the viscous bound (implicit
+    diffusion).  A field at rest with nu = 0 gives +inf."""
+    rx, ry, rz = dt_rates(u, v, w, bc, dx, dy, dzf)
+    rate = max(float(rx.max()), float(ry.max()), float(rz.max()))
+    dt = np.sqrt(3.0) / rate if rate > 0 else np.inf
+    if nu > 0:
+        dl = min(dx, dy, float(np.min(_f64(dzf))))
+        dt = min(dt, 1.65 * dl * dl / nu)
+    return float(dt)

@@ -648,3 +648,158 @@ def test_projection_keeps_a_divergence_free_field():
     np.testing.assert_allclose(u1, u, rtol=0, atol=1e-11 * np.abs(u).max())
     np.testing.assert_allclose(v1, v, rtol=0, atol=1e-11 * np.abs(v).max())
     assert np.abs(w1).max() < 1e-11
+
+
+@pytest.mark.parametrize("bc", PROJ_BCS)
+def test_projection_implicit_pressure_update(bc):
+    """Implicit diffusion (the pressure update after eq. (poi_ns_id)):
+    p += Phi - alpha L_h Phi.  Since L_h Phi equals the (compatible)
+    divergence source D u / gdt, the update must equal Phi - alpha D u / gdt,
+    with D taken from the independently written divergence."""
+    nx, ny, nz = 12, 10, 9
+    dx, dy, dzf = 0.4, 0.3, _proj_grid(bc, nz)
+    rng = np.random.default_rng(sum(bc) + 70)
+    u, v, w = _walls_zero(*(rng.standard_normal((nz, ny, nx)) for _ in range(3)), bc)
+    p = rng.standard_normal((nz, ny, nx))
+    gdt, alpha = 0.02, 3.5e-3
+    f = O.divergence(u, v, w, bc, dx, dy, dzf) / gdt
+    assert abs(O.weighted_mean(f, dzf)) < 1e-12 * np.abs(f).max()
+    u1, v1, w1, p1, phi = O.project(u, v, w, p, bc, dx, dy, dzf, gdt, alpha=alpha)
+    np.testing.assert_allclose(p1 - p, phi - alpha * f, rtol=0, atol=1e-11 * np.abs(alpha * f).max())
+    # the velocity update does not depend on alpha
+    u0, v0, w0, p0, _ = O.project(u, v, w, p, bc, dx, dy, dzf, gdt)
+    assert np.array_equal(u0, u1) and np.array_equal(v0, v1) and np.array_equal(w0, w1)
+    assert np.abs((p1 - p0) + alpha * f).max() < 1e-11 * np.abs(alpha * f).max()
+
+
+# --------------------------------------------------------------------------- #
+# time-step criterion, eq. (dt) with the Listing's face rates
+
+def test_dt_uniform_flow_and_viscous_bound():
+    """A uniform stream U along x on a periodic box: every face rate is
+    U/dx, so dt = sqrt(3) dx / U; at rest only the viscous bound 1.65 dl^2/nu
+    remains, dl the smallest spacing (here a z cell)."""
+    nx, ny, nz = 8, 6, 5
+    bc = (P, P, P, P, P, P)
+    dx, dy, dzf = 0.3, 0.2, np.full(nz, 0.25)
+    U = 1.7
+    u = np.full((nz, ny, nx), U); v = np.zeros_like(u); w = np.zeros_like(u)
+    for r in O.dt_rates(u, v, w, bc, dx, dy, dzf):
+        np.testing.assert_allclose(r, U / dx, rtol=1e-15)
+    assert O.max_dt(u, v, w, bc, dx, dy, dzf) == pytest.approx(np.sqrt(3) * dx / U, rel=1e-15)
+    z = np.zeros_like(u)
+    assert O.max_dt(z, z, z, bc, dx, dy, dzf) == np.inf
+    assert O.max_dt(z, z, z, bc, dx, dy, dzf, nu=1e-3) == pytest.approx(1.65 * 0.2 ** 2 / 1e-3, rel=1e-15)
+    dzs = inputs.tanh_dzf(nz, 1.5, 2.0)
+    assert O.max_dt(z, z, z, (P, P, P, P, N, N), dx, dy, dzs, nu=2e-3) == pytest.approx(
+        1.65 * min(dy, dzs.min()) ** 2 / 2e-3, rel=1e-15)
+    dzs = inputs.tanh_dzf(16, 1.5, 2.0)
+    assert dzs.min() < dy
+    z16 = np.zeros((16, ny, nx))
+    assert O.max_dt(z16, z16, z16, (P, P, P, P, N, N), dx, dy, dzs, nu=2e-3) == pytest.approx(
+        1.65 * dzs.min() ** 2 / 2e-3, rel=1e-15)
+    # with both bounds the smaller wins
+    assert O.max_dt(u, v, w, bc, dx, dy, dzf, nu=10.0) == pytest.approx(1.65 * 0.2 ** 2 / 10.0, rel=1e-15)
+
+
+def _single(shape, at, val=1.0):
+    a = np.zeros(shape)
+    a[at] = val
+    return a
+
+
+def test_dt_rate_stencil_single_entries():
+    """One non-zero velocity entry, periodic box: it must show up at exactly
+    the faces whose four-point means contain it (value 1/4 of it over its
+    spacing) and at its own face (full value), nowhere else."""
+    nx, ny, nz = 7, 6, 5
+    bc = (P, P, P, P, P, P)
+    dx, dy = 0.5, 0.25
+    dzf = np.array([0.1, 0.2, 0.3, 0.15, 0.25])
+    dzc = 0.5 * (dzf + np.roll(dzf, -1))
+    k0, j0, i0 = 2, 3, 4
+    sh = (nz, ny, nx)
+    z = np.zeros(sh)
+
+    def expect(entries):
+        e = np.zeros(sh)
+        for (k, j, i), val in entries:
+            e[k % nz, j % ny, i % nx] = val
+        return e
+
+    # v at (i0, j0, k0): x faces (i0|i0-1, j0|j0+1), y face (i0, j0), z faces (j0|j0+1, k0|k0-1)
+    rx, ry, rz = O.dt_rates(z, _single(sh, (k0, j0, i0)), z, bc, dx, dy, dzf)
+    q = 0.25 / dy
+    np.testing.assert_allclose(rx, expect([((k0, j0, i0), q), ((k0, j0, i0 - 1), q), ((k0, j0 + 1, i0), q),
+                                           ((k0, j0 + 1, i0 - 1), q)]), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(ry, expect([((k0, j0, i0), 1 / dy)]), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(rz, expect([((k0, j0, i0), q), ((k0, j0 + 1, i0), q), ((k0 - 1, j0, i0), q),
+                                           ((k0 - 1, j0 + 1, i0), q)]), rtol=1e-15, atol=0)
+    # w at (i0, j0, k0): x faces over dzf_k, y faces over dzf_k, own z face over dzc_k0
+    rx, ry, rz = O.dt_rates(z, z, _single(sh, (k0, j0, i0)), bc, dx, dy, dzf)
+    np.testing.assert_allclose(rx, expect([((k0, j0, i0), 0.25 / dzf[k0]), ((k0, j0, i0 - 1), 0.25 / dzf[k0]),
+                                           ((k0 + 1, j0, i0), 0.25 / dzf[k0 + 1]),
+                                           ((k0 + 1, j0, i0 - 1), 0.25 / dzf[k0 + 1])]), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(ry, expect([((k0, j0, i0), 0.25 / dzf[k0]), ((k0, j0 - 1, i0), 0.25 / dzf[k0]),
+                                           ((k0 + 1, j0, i0), 0.25 / dzf[k0 + 1]),
+                                           ((k0 + 1, j0 - 1, i0), 0.25 / dzf[k0 + 1])]), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(rz, expect([((k0, j0, i0), 1 / dzc[k0])]), rtol=1e-15, atol=0)
+    # u at (i0, j0, k0): own x face; y faces (i0|i0+1, j0|j0-1); z faces (i0|i0+1, k0|k0-1)
+    rx, ry, rz = O.dt_rates(_single(sh, (k0, j0, i0)), z, z, bc, dx, dy, dzf)
+    q = 0.25 / dx
+    np.testing.assert_allclose(rx, expect([((k0, j0, i0), 1 / dx)]), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(ry, expect([((k0, j0, i0), q), ((k0, j0, i0 + 1), q), ((k0, j0 - 1, i0), q),
+                                           ((k0, j0 - 1, i0 + 1), q)]), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(rz, expect([((k0, j0, i0), q), ((k0, j0, i0 + 1), q), ((k0 - 1, j0, i0), q),
+                                           ((k0 - 1, j0, i0 + 1), q)]), rtol=1e-15, atol=0)
+
+
+def test_dt_walls_no_slip_and_no_penetration():
+    """Walls: a tangential value in the last cell cancels with its no-slip
+    mirror on the wall face's four-point mean, and the normal component below
+    the first cell is zero (it never appears wrapped from the far side)."""
+    nx, ny, nz = 6, 5, 4
+    bc = (N, N, P, P, N, N)
+    dx, dy, dzf = 0.5, 0.25, np.array([0.2, 0.3, 0.35, 0.25])
+    sh = (nz, ny, nx)
+    z = np.zeros(sh)
+    # v in the last x cell: at the last x face it meets its mirror -> 0
+    rx, _, _ = O.dt_rates(z, _single(sh, (1, 2, nx - 1)), z, bc, dx, dy, dzf)
+    assert rx[1, 2, nx - 1] == 0 and rx[1, 3, nx - 1] == 0
+    assert rx[1, 2, nx - 2] == pytest.approx(0.25 / dy, rel=1e-15)
+    # u in the top z cell: at the top (wall) z face it meets its mirror -> 0
+    _, _, rz = O.dt_rates(_single(sh, (nz - 1, 2, 3)), z, z, bc, dx, dy, dzf)
+    assert rz[nz - 1, 2, 3] == 0 and rz[nz - 1, 2, 4] == 0
+    assert rz[nz - 2, 2, 3] == pytest.approx(0.25 / dx, rel=1e-15)
+    # w on the first z face: the face below the first cell is a wall (zero),
+    # so the top cell's x faces see nothing of it
+    rx, _, _ = O.dt_rates(z, z, _single(sh, (0, 1, 2)), bc, dx, dy, dzf)
+    assert np.count_nonzero(rx) == 4 and rx[nz - 1].max() == 0
+    # a (non-zero) value given on the top wall face is divided by the mirror
+    # ghost cell's centre distance, the top cell's width
+    _, _, rz = O.dt_rates(z, z, _single(sh, (nz - 1, 1, 2)), bc, dx, dy, dzf)
+    assert rz[nz - 1, 1, 2] == pytest.approx(1 / dzf[nz - 1], rel=1e-15)
+    _, _, rz = O.dt_rates(z, z, _single(sh, (1, 1, 2)), bc, dx, dy, dzf)
+    assert rz[1, 1, 2] == pytest.approx(2 / (dzf[1] + dzf[2]), rel=1e-15)
+    # u on the first x face: no wrap to the last cell's y faces
+    _, ry, _ = O.dt_rates(_single(sh, (1, 1, 0)), z, z, bc, dx, dy, dzf)
+    assert ry[1, :, nx - 1].max() == 0 and ry[1, 1, 0] == pytest.approx(0.25 / dx, rel=1e-15)
+
+
+def test_dt_scaling_and_bounds():
+    """dt(c u) = dt(u)/c without viscosity; the largest rate lies between
+    max|u|/dx (the x faces) and the sum of the three component maxima over
+    their smallest spacings."""
+    nx, ny, nz = 10, 8, 7
+    bc = (P, P, P, P, N, N)
+    dx, dy = 0.3, 0.4
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    rng = np.random.default_rng(71)
+    u, v, w = _walls_zero(*(rng.standard_normal((nz, ny, nx)) for _ in range(3)), bc)
+    d1 = O.max_dt(u, v, w, bc, dx, dy, dzf)
+    d2 = O.max_dt(3 * u, 3 * v, 3 * w, bc, dx, dy, dzf)
+    assert d2 == pytest.approx(d1 / 3, rel=1e-14)
+    rate = np.sqrt(3) / d1
+    dzc = 0.5 * (dzf[1:] + dzf[:-1])
+    hi = np.abs(u).max() / dx + np.abs(v).max() / dy + np.abs(w).max() / min(dzf.min(), dzc.min())
+    assert np.abs(u).max() / dx <= rate * (1 + 1e-15) and rate <= hi
