@@ -191,9 +191,24 @@ def bench_project(torch, capi, pr, args):
     e.record()
     torch.cuda.synchronize()
     ms = s.elapsed_time(e) / args.steps
+    # the same step with the implicit-diffusion pressure update (alpha =
+    # gamma nu dt / 2, nu = 2e-4) and the time-step bound of eq. (dt) on the
+    # corrected velocity (one more pass reading u, v, w: 24 B per point)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    alpha = 0.5 * 1.6e-3 * 2e-4
+    for _ in range(args.warmup):
+        plan.project_ex(*fields, 1.6e-3, alpha=alpha, nu=2e-4, dt_max=dt)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(args.steps):
+        plan.project_ex(*fields, 1.6e-3, alpha=alpha, nu=2e-4, dt_max=dt)
+    e.record()
+    torch.cuda.synchronize()
+    ms_ex = s.elapsed_time(e) / args.steps
     plan.close()
     return {"projection_ms_per_step": ms, "grid_pts_per_s": pr.npts / (ms * 1e-3),
             "algorithmic_GBps": 168 * pr.npts / (ms * 1e-3) / 1e9, "bytes_per_point": 168,
+            "implicit_update_and_dt_ms_per_step": ms_ex, "dt_max": float(dt.item()),
             "grid": [pr.nx, pr.ny, pr.nz], "steps": args.steps}
 
 

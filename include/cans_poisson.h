@@ -196,6 +196,37 @@ int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream
 int cans_poisson_project(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
                          hipStream_t stream);
 
+/*
+ * cans_poisson_project with the two other pieces of a Runge-Kutta substep
+ * that sit on the same fields (Section 2, "Numerical method"):
+ *   alpha  = gamma_k nu dt / 2 >= 0: the pressure update of implicit
+ *            diffusion, p += Phi - alpha L_h Phi (the last equation after
+ *            eq. (poi_ns_id)); alpha = 0 gives the explicit-diffusion update
+ *            p += Phi of cans_poisson_project.  L_h is the operator of
+ *            eq. (poi) with the pressure's ghost rules.
+ *   dt_max = NULL, or a device pointer to one double that receives the
+ *            time-step bound of eq. (dt) on the corrected velocity:
+ *            sqrt(3) / (largest advective rate), and with nu > 0 at most
+ *            1.65 dl^2 / nu, dl = min(dx, dy, min dzf).  The advective rate is
+ *            taken as the Listing of Section 3 takes it: at the +x, +y and +z
+ *            face of every cell, the face-normal component plus the
+ *            magnitudes of the four-point means of the other two, each over
+ *            its spacing (dx, dy, dzf_k; the centre distance dzc_k at z faces,
+ *            the wall cell's width on a wall face).  Beyond the last cell of a
+ *            walled axis the tangential components are the no-slip mirror
+ *            (negated); the normal component below the first cell is zero.  A
+ *            velocity at rest with nu = 0 gives +inf.
+ *   nu     >= 0: the viscosity of the viscous bound (0 omits it, as with
+ *            implicit diffusion).
+ * Layout, boundary rules, ownership, the one-call-in-flight rule and errors
+ * are those of cans_poisson_project; a negative or non-finite alpha or nu is
+ * CANS_ERR_INVALID_ARG and dt_max equal to one of the fields CANS_ERR_ALIAS.
+ * The first projection call of a plan (either form) allocates Phi and a
+ * table of 2048 block maxima.
+ */
+int cans_poisson_project_ex(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
+                            double alpha, double nu, double *dt_max, hipStream_t stream);
+
 /* Copy the last solve's cans_info to *out.  Synchronises with the device, so
  * it is meant to be called after the solve's stream has been synchronised. */
 int cans_poisson_get_info(cans_plan_t plan, cans_info *out);

@@ -36,7 +36,8 @@ def z_widths(nz: int, bc) -> int:
 EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "cans_poisson_solve",
            "cans_poisson_get_info", "cans_poisson_destroy", "cans_status_string",
            "cans_poisson_workspace_bytes", "cans_poisson_debug_stage", "cans_poisson_plan_batched",
-           "cans_poisson_solve_batched", "cans_poisson_get_info_batched", "cans_poisson_project"]
+           "cans_poisson_solve_batched", "cans_poisson_get_info_batched", "cans_poisson_project",
+           "cans_poisson_project_ex"]
 
 
 class CansOpts(ctypes.Structure):
@@ -83,6 +84,7 @@ def load() -> ctypes.CDLL:
         "cans_poisson_plan_ex": ([pp, i, i, i, ip, d, d, dp, ctypes.POINTER(CansOpts)], i),
         "cans_poisson_solve": ([vp, vp, vp, vp], i),
         "cans_poisson_project": ([vp, vp, vp, vp, vp, d, vp], i),
+        "cans_poisson_project_ex": ([vp, vp, vp, vp, vp, d, d, d, vp, vp], i),
         "cans_poisson_get_info": ([vp, ctypes.POINTER(CansInfo)], i),
         "cans_poisson_destroy": ([vp], None),
         "cans_status_string": ([i], ctypes.c_char_p),
@@ -194,6 +196,19 @@ class Plan:
         boundaries."""
         _check(self._lib.cans_poisson_project(self._h, self._a(u), self._a(v), self._a(w), self._a(p), float(gdt),
                                               _stream(stream)), "cans_poisson_project")
+
+    def project_ex(self, u, v, w, p, gdt: float, alpha: float = 0.0, nu: float = 0.0, dt_max=None,
+                   stream=None) -> None:
+        """``cans_poisson_project_ex``: the projection step with the pressure
+        update p += Phi - alpha L_h Phi (implicit diffusion) and, when
+        `dt_max` (a one-element float64 CUDA tensor) is given, the bound of
+        eq. (dt) on the corrected velocity written into it."""
+        dt_addr = None
+        if dt_max is not None:
+            dt_addr = _addr(dt_max, 1, self.device)
+        _check(self._lib.cans_poisson_project_ex(self._h, self._a(u), self._a(v), self._a(w), self._a(p),
+                                                 float(gdt), float(alpha), float(nu), dt_addr, _stream(stream)),
+               "cans_poisson_project_ex")
 
     def debug_stage(self, stage: int, inp, out, stream=None) -> None:
         _check(self._lib.cans_poisson_debug_stage(self._h, stage, self._a(inp), self._a(out), _stream(stream)),

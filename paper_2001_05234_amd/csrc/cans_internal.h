@@ -43,6 +43,18 @@ struct Axis {
     unsigned short *d_wf_hi = nullptr, *d_wf_lo = nullptr, *d_wi_hi = nullptr, *d_wi_lo = nullptr;
 };
 
+// Per-solve mutable device memory of one problem: the plan's own (allocated
+// when the plan is built), or carved from the library's static scratch array
+// by the entry point that allocates nothing.
+struct Work {
+    float *a32 = nullptr;          // FP32 spectral field (refine mode)
+    double *partials = nullptr;    // block partial sums of the reductions
+    double *sums = nullptr;        // first-level sums of the partials (256 records)
+    double *info = nullptr;        // info record, I_SIZE doubles
+    int *flag = nullptr;           // [0] refinement finished
+    double *wc = nullptr, *wd = nullptr, *wz = nullptr;  // plain elimination (deep or periodic z)
+};
+
 struct Problem {
     int nx = 0, ny = 0, nz = 0;
     int bc[6] = {0, 0, 0, 0, 0, 0};
@@ -54,17 +66,12 @@ struct Problem {
     double scale = 1;
     double *d_za = nullptr, *d_zb = nullptr, *d_zc = nullptr;
     double *d_zaf = nullptr, *d_zcf = nullptr, *d_dzf = nullptr;
-    // workspace
-    double *wc = nullptr, *wd = nullptr, *wz = nullptr;
-    float *a32 = nullptr;          // FP32 spectral field (refine mode)
-    double *partials = nullptr;    // residual block sums
-    double *sums = nullptr;        // first-level sums of the partials (256 triples)
-    int nres_blocks = 0;
-    double *d_info = nullptr;
-    int *d_flag = nullptr;         // [0] refinement finished
+    Work ws;                       // the plan's own workspace
     // projection step (allocated at its first use)
     double *phi = nullptr;         // the potential Phi (FP64 field)
     double *d_zgc = nullptr;       // 1/dzc_k across the +z face of level k, 0 on a wall face
+    double *d_dzc = nullptr;       // dzc_k across the +z face of level k (the mirror cell's at a wall)
+    double *dt_part = nullptr;     // block maxima of the time-step rates
     size_t npts() const { return (size_t)nx * ny * nz; }
 };
 
@@ -73,29 +80,35 @@ struct Problem {
 // Tin/Tout: double or float; epi 0 store, 1 update p += v - info[I_MEANP].
 int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s);
 int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hipStream_t s);
-// (also leaves FP64 block sums of dzf*in in pb.partials for launch_mean_rhs)
-int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *done, hipStream_t s);
+// (also leaves FP64 block sums of dzf*in in w.partials for launch_mean_rhs)
+int launch_x_fwd_32(const Problem &pb, const Work &w, const double *in, float *out, const int *done, hipStream_t s);
 int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipStream_t s);
-int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, const int *done,
+int launch_x_inv_32(const Problem &pb, const Work &w, const float *in, double *p, bool update, const int *done,
                     hipStream_t s);
-int launch_zsolve_f64(const Problem &pb, double *data, double *removed, hipStream_t s);
-int launch_zsolve_32(const Problem &pb, float *data, double *removed, const int *done, hipStream_t s);
+int launch_zsolve_f64(const Problem &pb, const Work &w, double *data, double *removed, hipStream_t s);
+int launch_zsolve_32(const Problem &pb, const Work &w, float *data, double *removed, const int *done, hipStream_t s);
 // refinement: residual fused with the forward x transform (FP32 out), and the
 // residual norm alone; then the reduction that decides convergence.
-int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float *out, const int *done,
+int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out,
+                      const int *done, hipStream_t s);
+int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done,
                       hipStream_t s);
-int launch_resid_norm(const Problem &pb, const double *f, const double *p, const int *done, hipStream_t s);
-int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipStream_t s);
-int launch_reset(const Problem &pb, hipStream_t s);
-int launch_mean_rhs(const Problem &pb, hipStream_t s);
+int launch_finalize(const Problem &pb, const Work &w, int check, int max_iter, double tol, hipStream_t s);
+int launch_reset(const Problem &pb, const Work &w, hipStream_t s);
+int launch_mean_rhs(const Problem &pb, const Work &w, hipStream_t s);
 
 int resid_blocks(const Problem &pb);
 
 // projection step: D u / gdt fused into the forward x transform (FP64, into
-// out), and the correction u -= gdt G phi, p += phi
+// out), and the correction u -= gdt G phi, p += phi - alpha L_h phi
 int launch_div_xfwd(const Problem &pb, const double *u, const double *v, const double *w, double gdt, double *out,
                     hipStream_t s);
 int launch_project_correct(const Problem &pb, double *u, double *v, double *w, double *p, const double *phi,
-                           double gdt, hipStream_t s);
+                           double gdt, double alpha, hipStream_t s);
+// time-step bound of eq. (dt) on a staggered velocity into dt (device, one
+// double); pb.dt_part holds dt_blocks(pb) block maxima
+int dt_blocks(const Problem &pb);
+int launch_max_dt(const Problem &pb, const double *u, const double *v, const double *w, double nu, double *dt,
+                  hipStream_t s);
 
 }  // namespace cans

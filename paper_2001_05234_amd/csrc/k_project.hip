@@ -56,9 +56,13 @@ struct CorrArgs {
     int nx, ny, nz;
     int px, py, pz;
     double gdx, gdy, gdt;       // gdt/dx, gdt/dy, gdt
+    double alpha;               // implicit diffusion: p += Phi - alpha L_h Phi
+    LapArgs la;                 // L_h of Phi (the pressure's ghost rules)
 };
 
-// u -= gdt G Phi on the +faces and p += Phi; one block per x line.
+// u -= gdt G Phi on the +faces and p += Phi (LAP: p += Phi - alpha L_h Phi,
+// the pressure update of implicit diffusion); one block per x line.
+template <bool LAP>
 __global__ __launch_bounds__(256) void k_project_correct(CorrArgs c)
 {
     const int line = (int)blockIdx.x;
@@ -74,7 +78,105 @@ __global__ __launch_bounds__(256) void k_project_correct(CorrArgs c)
         c.u[e] -= c.gdx * (fe - f0);
         c.v[e] -= c.gdy * (fn - f0);
         c.w[e] -= gz * (ft - f0);
-        c.p[e] += f0;
+        if constexpr (LAP) c.p[e] += f0 - c.alpha * lap_point(c.phi, i, j, k, c.la);
+        else c.p[e] += f0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Time-step bound of eq. (dt) on the staggered velocity, its advective part
+// as the Listing of Section 3 evaluates it: at the +x, +y, +z face of each
+// cell, the face-normal component plus the magnitudes of the four-point
+// means of the two others, each over its spacing (dx, dy, dzf_k; the centre
+// distance dzc_k at z faces).  Out-of-range neighbours: a component one face
+// below the first cell along its own axis wraps or is zero at a wall; one
+// cell beyond the last along another axis wraps or is the no-slip mirror
+// (negated last value).
+struct RateArgs {
+    const double *u, *v, *w;
+    const double *dzf;          // cell widths
+    const double *dzc;          // centre distance across the +z face of each level (mirror cell at a wall)
+    int nx, ny, nz;
+    int per[3];                 // periodic x, y, z
+    double idx, idy;
+};
+
+// component `comp` (0 u, 1 v, 2 w) at cell (i, j, k), indices one past
+// either end allowed as described above
+static __device__ inline double vel_at(const RateArgs &r, int comp, int i, int j, int k)
+{
+    const double *f = comp == 0 ? r.u : (comp == 1 ? r.v : r.w);
+    int idx[3] = {i, j, k};
+    const int n[3] = {r.nx, r.ny, r.nz};
+    double sgn = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (idx[a] < 0) {           // below the first cell: only along the component's own axis
+            if (!r.per[a]) return 0.0;
+            idx[a] = n[a] - 1;
+        } else if (idx[a] >= n[a]) {  // beyond the last cell: only across
+            if (r.per[a]) {
+                idx[a] = 0;
+            } else {
+                idx[a] = n[a] - 1;
+                sgn = -sgn;
+            }
+        }
+    }
+    return sgn * f[(size_t)idx[0] + (size_t)r.nx * ((size_t)idx[1] + (size_t)r.ny * idx[2])];
+}
+
+static __device__ inline double cell_rate(const RateArgs &r, int i, int j, int k)
+{
+    const double idz = 1.0 / r.dzf[k];
+    const double ux = fabs(vel_at(r, 0, i, j, k));
+    const double vx = 0.25 * fabs(vel_at(r, 1, i, j, k) + vel_at(r, 1, i, j - 1, k) + vel_at(r, 1, i + 1, j, k) +
+                                  vel_at(r, 1, i + 1, j - 1, k));
+    const double wx = 0.25 * fabs(vel_at(r, 2, i, j, k) + vel_at(r, 2, i, j, k - 1) + vel_at(r, 2, i + 1, j, k) +
+                                  vel_at(r, 2, i + 1, j, k - 1));
+    const double rx = ux * r.idx + vx * r.idy + wx * idz;
+    const double uy = 0.25 * fabs(vel_at(r, 0, i, j, k) + vel_at(r, 0, i - 1, j, k) + vel_at(r, 0, i, j + 1, k) +
+                                  vel_at(r, 0, i - 1, j + 1, k));
+    const double vy = fabs(vel_at(r, 1, i, j, k));
+    const double wy = 0.25 * fabs(vel_at(r, 2, i, j, k) + vel_at(r, 2, i, j, k - 1) + vel_at(r, 2, i, j + 1, k) +
+                                  vel_at(r, 2, i, j + 1, k - 1));
+    const double ry = uy * r.idx + vy * r.idy + wy * idz;
+    const double uz = 0.25 * fabs(vel_at(r, 0, i, j, k) + vel_at(r, 0, i - 1, j, k) + vel_at(r, 0, i, j, k + 1) +
+                                  vel_at(r, 0, i - 1, j, k + 1));
+    const double vz = 0.25 * fabs(vel_at(r, 1, i, j, k) + vel_at(r, 1, i, j - 1, k) + vel_at(r, 1, i, j, k + 1) +
+                                  vel_at(r, 1, i, j - 1, k + 1));
+    const double wz = fabs(vel_at(r, 2, i, j, k));
+    const double rz = uz * r.idx + vz * r.idy + wz / r.dzc[k];
+    return fmax(rx, fmax(ry, rz));
+}
+
+constexpr int kRateBlocks = 2048;
+
+// block maxima of the face rates over lines b, b + grid, ... (x lines j + ny k)
+__global__ __launch_bounds__(256) void k_dt_rates(RateArgs r, double *__restrict__ part)
+{
+    const int nlines = r.ny * r.nz;
+    double m = 0.0;
+    for (int line = blockIdx.x; line < nlines; line += gridDim.x) {
+        const int k = line / r.ny, j = line - k * r.ny;
+        for (int i = threadIdx.x; i < r.nx; i += 256) m = fmax(m, cell_rate(r, i, j, k));
+    }
+    double z = 0.0;
+    block_max2(m, z);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// dt = min(sqrt(3) / max rate, 1.65 dl^2 / nu): the largest block maximum
+// (a maximum is exact in any order); +inf for a field at rest without nu
+__global__ __launch_bounds__(256) void k_dt_final(const double *__restrict__ part, int nblk, double visc_bound,
+                                                  double *__restrict__ dt)
+{
+    double m = 0.0, z = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, part[b]);
+    block_max2(m, z);
+    if (threadIdx.x == 0) {
+        const double adv = m > 0.0 ? sqrt(3.0) / m : __builtin_inf();
+        dt[0] = fmin(adv, visc_bound);
     }
 }
 
@@ -94,12 +196,36 @@ int launch_div_xfwd(const Problem &pb, const double *u, const double *v, const d
 }
 
 int launch_project_correct(const Problem &pb, double *u, double *v, double *w, double *p, const double *phi,
-                           double gdt, hipStream_t s)
+                           double gdt, double alpha, hipStream_t s)
 {
     CorrArgs c{u, v, w, p, phi, pb.d_zgc, pb.nx, pb.ny, pb.nz,
                pb.bc[0] == CANS_BC_PERIODIC, pb.bc[2] == CANS_BC_PERIODIC, pb.bc[4] == CANS_BC_PERIODIC,
-               gdt / pb.ax.h, gdt / pb.ay.h, gdt};
-    hipLaunchKernelGGL(k_project_correct, dim3((unsigned)(pb.ny * pb.nz)), dim3(256), 0, s, c);
+               gdt / pb.ax.h, gdt / pb.ay.h, gdt, alpha, lapargs(pb)};
+    if (alpha != 0.0)
+        hipLaunchKernelGGL(k_project_correct<true>, dim3((unsigned)(pb.ny * pb.nz)), dim3(256), 0, s, c);
+    else
+        hipLaunchKernelGGL(k_project_correct<false>, dim3((unsigned)(pb.ny * pb.nz)), dim3(256), 0, s, c);
+    return check_launch();
+}
+
+int dt_blocks(const Problem &pb)
+{
+    const long nlines = (long)pb.ny * pb.nz;
+    return (int)(nlines < kRateBlocks ? nlines : kRateBlocks);
+}
+
+int launch_max_dt(const Problem &pb, const double *u, const double *v, const double *w, double nu, double *dt,
+                  hipStream_t s)
+{
+    RateArgs r{u, v, w, pb.d_dzf, pb.d_dzc, pb.nx, pb.ny, pb.nz,
+               {pb.bc[0] == CANS_BC_PERIODIC, pb.bc[2] == CANS_BC_PERIODIC, pb.bc[4] == CANS_BC_PERIODIC},
+               1.0 / pb.ax.h, 1.0 / pb.ay.h};
+    double dl = pb.ax.h < pb.ay.h ? pb.ax.h : pb.ay.h;
+    for (double d : pb.dzf) dl = d < dl ? d : dl;
+    const double visc = nu > 0.0 ? 1.65 * dl * dl / nu : __builtin_inf();
+    const int nb = dt_blocks(pb);
+    hipLaunchKernelGGL(k_dt_rates, dim3((unsigned)nb), dim3(256), 0, s, r, pb.dt_part);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, pb.dt_part, nb, visc, dt);
     return check_launch();
 }
 }  // namespace cans

@@ -222,18 +222,6 @@ __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ 
 }
 
 
-static LapArgs lapargs(const Problem &pb)
-{
-    LapArgs la;
-    la.nx = pb.nx; la.ny = pb.ny; la.nz = pb.nz;
-    for (int i = 0; i < 6; ++i) la.bc[i] = pb.bc[i];
-    la.idx2 = 1.0 / (pb.ax.h * pb.ax.h);
-    la.idy2 = 1.0 / (pb.ay.h * pb.ay.h);
-    la.zaf = pb.d_zaf; la.zcf = pb.d_zcf;
-    la.shift = pb.shift;
-    return la;
-}
-
 int resid_blocks(const Problem &pb)
 {
     const long nlines = (long)pb.ny * pb.nz;
@@ -241,13 +229,13 @@ int resid_blocks(const Problem &pb)
     return (int)((nlines + L - 1) / L);
 }
 
-int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float *out, const int *done,
-                      hipStream_t s)
+int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out,
+                      const int *done, hipStream_t s)
 {
     if (pb.ax.dense) {
         hipLaunchKernelGGL(k_dense_resid, dense_grid(pb), dim3(256), dense_lds(pb.nx), s, f, p, out,
                            (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wf_hi, pb.ax.d_wf_lo, lapargs(pb),
-                           pb.d_dzf, pb.d_info, pb.partials, done);
+                           pb.d_dzf, w.info, w.partials, done);
         return check_launch();
     }
     const XGeom &g = pb.ax.gx32[1];
@@ -256,15 +244,16 @@ int launch_resid_xfwd(const Problem &pb, const double *f, const double *p, float
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         hipLaunchKernelGGL(k_resid_xfwd<KD>, grid, dim3(kThreads), sh, s, f, p, out, nlines, g,
-                           pb.ax.d_tw32, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done));
+                           pb.ax.d_tw32, lapargs(pb), pb.d_dzf, w.info, w.partials, done));
     return check_launch();
 }
 
-int launch_resid_norm(const Problem &pb, const double *f, const double *p, const int *done, hipStream_t s)
+int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done,
+                      hipStream_t s)
 {
     const long nlines = (long)pb.ny * pb.nz;
     hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)resid_blocks(pb)), dim3(kThreads), 0, s, f, p, nlines,
-                       pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L, lapargs(pb), pb.d_dzf, pb.d_info, pb.partials, done);
+                       pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
     return check_launch();
 }
 
@@ -272,40 +261,40 @@ int launch_resid_norm(const Problem &pb, const double *f, const double *p, const
 // (one launch per check instead of two; small problems are launch-bound).
 constexpr int kDirectReduce = 4096;
 
-int launch_finalize(const Problem &pb, int check, int max_iter, double tol, hipStream_t s)
+int launch_finalize(const Problem &pb, const Work &w, int check, int max_iter, double tol, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
     const int nblk = resid_blocks(pb);
     if (nblk <= kDirectReduce) {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.partials, nblk, check, max_iter, tol,
-                           inv_wvol, pb.singular, pb.d_info, pb.d_flag);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, w.partials, nblk, check, max_iter, tol,
+                           inv_wvol, pb.singular, w.info, w.flag);
         return check_launch();
     }
-    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, nblk, pb.sums,
-                       pb.d_flag);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, check, max_iter, tol,
-                       inv_wvol, pb.singular, pb.d_info, pb.d_flag);
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, w.partials, nblk, w.sums,
+                       w.flag);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, w.sums, kReduceBlocks, check, max_iter, tol,
+                       inv_wvol, pb.singular, w.info, w.flag);
     return check_launch();
 }
 
-int launch_mean_rhs(const Problem &pb, hipStream_t s)
+int launch_mean_rhs(const Problem &pb, const Work &w, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
     const int nblk = xfwd_blocks(pb);
     if (nblk <= kDirectReduce) {
-        hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.partials, nblk, inv_wvol, pb.singular,
-                           pb.d_info);
+        hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, w.partials, nblk, inv_wvol, pb.singular,
+                           w.info);
         return check_launch();
     }
-    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, pb.partials, nblk, pb.sums, nullptr);
-    hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, pb.sums, kReduceBlocks, inv_wvol, pb.singular,
-                       pb.d_info);
+    hipLaunchKernelGGL(k_reduce1, dim3(kReduceBlocks), dim3(kThreads), 0, s, w.partials, nblk, w.sums, nullptr);
+    hipLaunchKernelGGL(k_mean_rhs, dim3(1), dim3(kThreads), 0, s, w.sums, kReduceBlocks, inv_wvol, pb.singular,
+                       w.info);
     return check_launch();
 }
 
-int launch_reset(const Problem &pb, hipStream_t s)
+int launch_reset(const Problem &pb, const Work &w, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, pb.d_info, pb.d_flag);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.info, w.flag);
     return check_launch();
 }
 }  // namespace cans

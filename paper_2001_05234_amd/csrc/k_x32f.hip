@@ -4,12 +4,12 @@
 
 namespace cans {
 
-int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *done, hipStream_t s)
+int launch_x_fwd_32(const Problem &pb, const Work &w, const double *in, float *out, const int *done, hipStream_t s)
 {
     if (pb.ax.dense) {
         hipLaunchKernelGGL((k_dense_x<true, double, float, 0>), dense_grid(pb), dim3(256), dense_lds(pb.nx), s, in, out,
                            (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wf_hi, pb.ax.d_wf_lo, nullptr, done,
-                           pb.d_dzf, pb.ny, pb.partials);
+                           pb.d_dzf, pb.ny, w.partials);
         return check_launch();
     }
     const XGeom &g = pb.ax.gx32[1];
@@ -18,7 +18,7 @@ int launch_x_fwd_32(const Problem &pb, const double *in, float *out, const int *
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         hipLaunchKernelGGL((k_xform_x<KD, true, float, double, float, 0>), grid, dim3(kThreads), sh, s,
-                           in, out, nlines, g, pb.ax.d_tw32, nullptr, done, pb.d_dzf, pb.ny, pb.partials));
+                           in, out, nlines, g, pb.ax.d_tw32, nullptr, done, pb.d_dzf, pb.ny, w.partials));
     return check_launch();
 }
 

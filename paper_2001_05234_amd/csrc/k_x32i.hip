@@ -4,18 +4,18 @@
 
 namespace cans {
 
-int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, const int *done,
+int launch_x_inv_32(const Problem &pb, const Work &w, const float *in, double *p, bool update, const int *done,
                     hipStream_t s)
 {
     if (pb.ax.dense) {
         if (update)
             hipLaunchKernelGGL((k_dense_x<false, float, double, 1>), dense_grid(pb), dim3(256), dense_lds(pb.nx), s,
                                in, p, (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wi_hi, pb.ax.d_wi_lo,
-                               pb.d_info, done, nullptr, pb.ny, nullptr);
+                               w.info, done, nullptr, pb.ny, nullptr);
         else
             hipLaunchKernelGGL((k_dense_x<false, float, double, 0>), dense_grid(pb), dim3(256), dense_lds(pb.nx), s,
                                in, p, (long)pb.ny * pb.nz, pb.nx, mag_of(pb.nx), pb.ax.d_wi_hi, pb.ax.d_wi_lo,
-                               pb.d_info, done, nullptr, pb.ny, nullptr);
+                               w.info, done, nullptr, pb.ny, nullptr);
         return check_launch();
     }
     const XGeom &g = pb.ax.gx32[0];
@@ -24,9 +24,9 @@ int launch_x_inv_32(const Problem &pb, const float *in, double *p, bool update, 
     const size_t sh = tile_lds(AX_X, g, sizeof(float));
     CANS_KIND_SWITCH(pb.ax.kind,
         if (update) hipLaunchKernelGGL((k_xform_x<KD, false, float, float, double, 1>), grid, dim3(kThreads), sh, s,
-                                       in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, pb.ny, nullptr);
+                                       in, p, nlines, g, pb.ax.d_tw32, w.info, done, nullptr, pb.ny, nullptr);
         else hipLaunchKernelGGL((k_xform_x<KD, false, float, float, double, 0>), grid, dim3(kThreads), sh, s,
-                                in, p, nlines, g, pb.ax.d_tw32, pb.d_info, done, nullptr, pb.ny, nullptr));
+                                in, p, nlines, g, pb.ax.d_tw32, w.info, done, nullptr, pb.ny, nullptr));
     return check_launch();
 }
 

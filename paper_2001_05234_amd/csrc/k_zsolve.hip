@@ -13,7 +13,7 @@ __global__ __launch_bounds__(256) void k_zsolve(T *data, ZArgs a, const int *__r
     zsolve_column(col, data, a);
 }
 
-static ZArgs zargs(const Problem &pb, double *removed);
+static ZArgs zargs(const Problem &pb, const Work &w, double *removed);
 
 // Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
 // into S segments of at most MMAX levels held in registers; a wave holds
@@ -85,11 +85,11 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
 }
 
 template <typename T>
-static int launch_zsolve(const Problem &pb, T *data, double *removed, const int *done, hipStream_t s)
+static int launch_zsolve(const Problem &pb, const Work &w, T *data, double *removed, const int *done, hipStream_t s)
 {
     const size_t plane = (size_t)pb.nx * pb.ny;
     const ZPart zp = zpart_shape(pb.nz, pb.cyclic != 0);
-    ZArgs za = zargs(pb, removed);
+    ZArgs za = zargs(pb, w, removed);
     if (zp.mmax == 0) {
         hipLaunchKernelGGL(k_zsolve<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, s, data, za, done);
         return check_launch();
@@ -125,7 +125,7 @@ static int launch_zsolve(const Problem &pb, T *data, double *removed, const int 
     return check_launch();
 }
 
-static ZArgs zargs(const Problem &pb, double *removed)
+static ZArgs zargs(const Problem &pb, const Work &w, double *removed)
 {
     ZArgs a;
     a.nx = pb.nx; a.ny = pb.ny; a.nz = pb.nz;
@@ -133,18 +133,18 @@ static ZArgs zargs(const Problem &pb, double *removed)
     a.lamx = pb.ax.d_lam; a.lamy = pb.ay.d_lam;
     a.dzf = pb.d_dzf; a.wsum = pb.wsum; a.scale = pb.scale;
     a.cyclic = pb.cyclic; a.singular = pb.singular;
-    a.wc = pb.wc; a.wd = pb.wd; a.wz = pb.wz;
+    a.wc = w.wc; a.wd = w.wd; a.wz = w.wz;
     a.removed = removed;
     return a;
 }
 
-int launch_zsolve_f64(const Problem &pb, double *data, double *removed, hipStream_t s)
+int launch_zsolve_f64(const Problem &pb, const Work &w, double *data, double *removed, hipStream_t s)
 {
-    return launch_zsolve<double>(pb, data, removed, nullptr, s);
+    return launch_zsolve<double>(pb, w, data, removed, nullptr, s);
 }
 
-int launch_zsolve_32(const Problem &pb, float *data, double *removed, const int *done, hipStream_t s)
+int launch_zsolve_32(const Problem &pb, const Work &w, float *data, double *removed, const int *done, hipStream_t s)
 {
-    return launch_zsolve<float>(pb, data, removed, done, s);
+    return launch_zsolve<float>(pb, w, data, removed, done, s);
 }
 }  // namespace cans

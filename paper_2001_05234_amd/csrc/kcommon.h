@@ -97,11 +97,7 @@ static __device__ inline int line_level(long line, long line0, int k0, int j0, i
     return (j0 + d < ny) ? k0 : (int)(line / ny);
 }
 
-// x transform: a block holds L consecutive x lines (rows j + ny*k).
-// EPI 0: out = v;  EPI 1: out = out + v - info[I_MEANP] (refinement update).
-// `wsum_part` (optional, forward only): block partial sums of dzf_k * in in
-// FP64, so the exact weighted mean of the rhs is known in refinement mode.
-// At least 4 waves per SIMD: the staged FP64 inverses would otherwise take
+// blocks of the dense (matrix-core) x kernels
 static inline dim3 dense_grid(const Problem &pb)
 {
     const long nlines = (long)pb.ny * pb.nz;
@@ -110,6 +106,20 @@ static inline dim3 dense_grid(const Problem &pb)
 
 // ---------------------------------------------------------------------------
 // launchers
+// FP64 operator L_h of eq. (poi) (plus the plan's shift) for the residual
+// and pressure-update kernels
+static inline LapArgs lapargs(const Problem &pb)
+{
+    LapArgs la;
+    la.nx = pb.nx; la.ny = pb.ny; la.nz = pb.nz;
+    for (int i = 0; i < 6; ++i) la.bc[i] = pb.bc[i];
+    la.idx2 = 1.0 / (pb.ax.h * pb.ax.h);
+    la.idy2 = 1.0 / (pb.ay.h * pb.ay.h);
+    la.zaf = pb.d_zaf; la.zcf = pb.d_zcf;
+    la.shift = pb.shift;
+    return la;
+}
+
 static inline size_t tile_lds(int axis, const XGeom &g, size_t elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
 
 // blocks of the first forward x transform, which also leaves the partial

@@ -153,7 +153,7 @@ int autotune(cans_plan_s *pl, Problem &pb)
     if (hipMemset(s64, 0, N * sizeof(double)) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = CANS_ERR_HIP;
-    if (rc == CANS_OK && pb.a32 && hipMemset(pb.a32, 0, N * sizeof(float)) != hipSuccess) rc = CANS_ERR_HIP;
+    if (rc == CANS_OK && pb.ws.a32 && hipMemset(pb.ws.a32, 0, N * sizeof(float)) != hipSuccess) rc = CANS_ERR_HIP;
     auto timeit = [&](auto launch) -> float {
         if (launch() != CANS_OK || launch() != CANS_OK) return 1e30f;
         (void)hipEventRecord(e0, st);
@@ -190,12 +190,12 @@ int autotune(cans_plan_s *pl, Problem &pb)
             tune(pb.ay.gy64[0], AX_Y, pb.ny, 8, [&] { return launch_y_f64(pb, false, s64, s64, st); });
         } else {
             if (!pb.ax.dense) {
-                tune(pb.ax.gx32[1], AX_X, pb.nx, 4, [&] { return launch_x_fwd_32(pb, s64, pb.a32, nullptr, st); });
+                tune(pb.ax.gx32[1], AX_X, pb.nx, 4, [&] { return launch_x_fwd_32(pb, pb.ws, s64, pb.ws.a32, nullptr, st); });
                 tune(pb.ax.gx32[0], AX_X, pb.nx, 4,
-                     [&] { return launch_x_inv_32(pb, pb.a32, s64, false, nullptr, st); });
+                     [&] { return launch_x_inv_32(pb, pb.ws, pb.ws.a32, s64, false, nullptr, st); });
             }
-            tune(pb.ay.gy32[1], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, true, pb.a32, nullptr, st); });
-            tune(pb.ay.gy32[0], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, false, pb.a32, nullptr, st); });
+            tune(pb.ay.gy32[1], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, true, pb.ws.a32, nullptr, st); });
+            tune(pb.ay.gy32[0], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, false, pb.ws.a32, nullptr, st); });
         }
         if (hipStreamSynchronize(st) != hipSuccess) rc = CANS_ERR_HIP;
     }
@@ -236,21 +236,21 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     // partitioned solve): multipliers and modified rhs
     const size_t N = pb.npts();
     if (zpart_shape(nz, pb.cyclic != 0).mmax == 0) {
-        CANS_TRY(alloc(pl, &pb.wc, N));
-        CANS_TRY(alloc(pl, &pb.wd, N));
-        if (pb.cyclic) CANS_TRY(alloc(pl, &pb.wz, N));
+        CANS_TRY(alloc(pl, &pb.ws.wc, N));
+        CANS_TRY(alloc(pl, &pb.ws.wd, N));
+        if (pb.cyclic) CANS_TRY(alloc(pl, &pb.ws.wz, N));
     }
     if (pl->opts.precision == CANS_PREC_FP32_REFINE) {
-        CANS_TRY(alloc(pl, &pb.a32, N));
+        CANS_TRY(alloc(pl, &pb.ws.a32, N));
         // block partial sums: enough for any tile shape (one line per block)
-        CANS_TRY(alloc(pl, &pb.partials, kNP * (size_t)pb.ny * pb.nz));
-        CANS_TRY(alloc(pl, &pb.sums, kNP * 256));
+        CANS_TRY(alloc(pl, &pb.ws.partials, kNP * (size_t)pb.ny * pb.nz));
+        CANS_TRY(alloc(pl, &pb.ws.sums, kNP * 256));
     }
     if (pl->opts.autotune) CANS_TRY(autotune(pl, pb));
     std::vector<double> info(I_SIZE, 0.0);
-    CANS_TRY(upload(pl, &pb.d_info, info.data(), I_SIZE));
+    CANS_TRY(upload(pl, &pb.ws.info, info.data(), I_SIZE));
     int zero = 0;
-    CANS_TRY(upload(pl, &pb.d_flag, &zero, 1));
+    CANS_TRY(upload(pl, &pb.ws.flag, &zero, 1));
     return CANS_OK;
 }
 
@@ -312,11 +312,11 @@ std::vector<int> assign_branches(const std::vector<Problem> &probs)
     return br;
 }
 
-int solve_fp64(const Problem &pb, const double *rhs, double *p, hipStream_t s)
+int solve_fp64(const Problem &pb, const Work &w, const double *rhs, double *p, hipStream_t s)
 {
     CANS_TRY(launch_x_f64(pb, true, rhs, p, s));
     CANS_TRY(launch_y_f64(pb, true, p, p, s));
-    CANS_TRY(launch_zsolve_f64(pb, p, pb.d_info + I_REMOVED, s));
+    CANS_TRY(launch_zsolve_f64(pb, w, p, w.info + I_REMOVED, s));
     CANS_TRY(launch_y_f64(pb, false, p, p, s));
     CANS_TRY(launch_x_f64(pb, false, p, p, s));
     return CANS_OK;
@@ -327,29 +327,29 @@ int solve_fp64(const Problem &pb, const double *rhs, double *p, hipStream_t s)
 // e = A^{-1} r with r = Pi f - L p in FP64, p <- p + e - mean(p).  Each step
 // starts with a residual check; a finished flag on the device makes the
 // remaining kernels return at once, so no host synchronisation is needed.
-int solve_refine(const Problem &pb, const cans_opts &o, const double *rhs, double *p, hipStream_t s)
+int solve_refine(const Problem &pb, const Work &w, const cans_opts &o, const double *rhs, double *p, hipStream_t s)
 {
-    const int *done = pb.d_flag;
-    CANS_TRY(launch_reset(pb, s));
-    CANS_TRY(launch_x_fwd_32(pb, rhs, pb.a32, nullptr, s));
-    CANS_TRY(launch_mean_rhs(pb, s));
-    CANS_TRY(launch_y_32(pb, true, pb.a32, nullptr, s));
-    CANS_TRY(launch_zsolve_32(pb, pb.a32, nullptr, nullptr, s));
-    CANS_TRY(launch_y_32(pb, false, pb.a32, nullptr, s));
-    CANS_TRY(launch_x_inv_32(pb, pb.a32, p, false, nullptr, s));
+    const int *done = w.flag;
+    CANS_TRY(launch_reset(pb, w, s));
+    CANS_TRY(launch_x_fwd_32(pb, w, rhs, w.a32, nullptr, s));
+    CANS_TRY(launch_mean_rhs(pb, w, s));
+    CANS_TRY(launch_y_32(pb, true, w.a32, nullptr, s));
+    CANS_TRY(launch_zsolve_32(pb, w, w.a32, nullptr, nullptr, s));
+    CANS_TRY(launch_y_32(pb, false, w.a32, nullptr, s));
+    CANS_TRY(launch_x_inv_32(pb, w, w.a32, p, false, nullptr, s));
     // check 0, fused with the forward x transform the first correction needs
-    CANS_TRY(launch_resid_xfwd(pb, rhs, p, pb.a32, done, s));
-    CANS_TRY(launch_finalize(pb, 0, o.max_iter, o.tol, s));
+    CANS_TRY(launch_resid_xfwd(pb, w, rhs, p, w.a32, done, s));
+    CANS_TRY(launch_finalize(pb, w, 0, o.max_iter, o.tol, s));
     for (int it = 1; it <= o.max_iter; ++it) {
-        CANS_TRY(launch_y_32(pb, true, pb.a32, done, s));
-        CANS_TRY(launch_zsolve_32(pb, pb.a32, nullptr, done, s));
-        CANS_TRY(launch_y_32(pb, false, pb.a32, done, s));
-        CANS_TRY(launch_x_inv_32(pb, pb.a32, p, true, done, s));
+        CANS_TRY(launch_y_32(pb, true, w.a32, done, s));
+        CANS_TRY(launch_zsolve_32(pb, w, w.a32, nullptr, done, s));
+        CANS_TRY(launch_y_32(pb, false, w.a32, done, s));
+        CANS_TRY(launch_x_inv_32(pb, w, w.a32, p, true, done, s));
         // check `it` without a transform; only if it fails is the residual
         // formed again with its forward x transform for the next correction
-        CANS_TRY(launch_resid_norm(pb, rhs, p, done, s));
-        CANS_TRY(launch_finalize(pb, it, o.max_iter, o.tol, s));
-        if (it < o.max_iter) CANS_TRY(launch_resid_xfwd(pb, rhs, p, pb.a32, done, s));
+        CANS_TRY(launch_resid_norm(pb, w, rhs, p, done, s));
+        CANS_TRY(launch_finalize(pb, w, it, o.max_iter, o.tol, s));
+        if (it < o.max_iter) CANS_TRY(launch_resid_xfwd(pb, w, rhs, p, w.a32, done, s));
     }
     return CANS_OK;
 }
@@ -357,7 +357,7 @@ int solve_refine(const Problem &pb, const cans_opts &o, const double *rhs, doubl
 int fill_info(const Problem &pb, int precision, cans_info *out)
 {
     double h[I_SIZE];
-    if (hipMemcpy(h, pb.d_info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return CANS_ERR_HIP;
+    if (hipMemcpy(h, pb.ws.info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return CANS_ERR_HIP;
     std::memset(out, 0, sizeof(*out));
     out->removed_mean = h[I_REMOVED];
     for (int i = 0; i < CANS_HISTORY; ++i) out->history[i] = -1;
@@ -455,41 +455,58 @@ int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream
     if (!plan || !rhs || !p || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
     if (plan->opts.graph) return cans_poisson_solve_batched(plan, &rhs, &p, stream);
     const Problem &pb = plan->probs[0];
-    if (plan->opts.precision == CANS_PREC_FP64) return solve_fp64(pb, rhs, p, stream);
+    if (plan->opts.precision == CANS_PREC_FP64) return solve_fp64(pb, pb.ws, rhs, p, stream);
     if ((const void *)rhs == (const void *)p) return CANS_ERR_ALIAS;
-    return solve_refine(pb, plan->opts, rhs, p, stream);
+    return solve_refine(pb, pb.ws, plan->opts, rhs, p, stream);
 }
 
-int cans_poisson_project(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
-                         hipStream_t stream)
+int cans_poisson_project_ex(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt, double alpha,
+                            double nu, double *dt_max, hipStream_t stream)
 {
     if (!plan || !u || !v || !w || !p || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
     if (!(gdt > 0) || !std::isfinite(gdt)) return CANS_ERR_INVALID_ARG;
+    if (!(alpha >= 0) || !std::isfinite(alpha) || !(nu >= 0) || !std::isfinite(nu)) return CANS_ERR_INVALID_ARG;
     if (plan->opts.precision != CANS_PREC_FP64 || plan->opts.shift != 0.0) return CANS_ERR_UNSUPPORTED;
     Problem &pb = plan->probs[0];
     for (int a = 0; a < 3; ++a)
         if (pb.bc[2 * a] != pb.bc[2 * a + 1] ||
             (pb.bc[2 * a] != CANS_BC_PERIODIC && pb.bc[2 * a] != CANS_BC_NEUMANN))
             return CANS_ERR_UNSUPPORTED;
-    const void *f[4] = {u, v, w, p};
-    for (int a = 0; a < 4; ++a)
-        for (int b = a + 1; b < 4; ++b)
-            if (f[a] == f[b]) return CANS_ERR_ALIAS;
+    const void *f[5] = {u, v, w, p, dt_max};
+    for (int a = 0; a < 5; ++a)
+        for (int b = a + 1; b < 5; ++b)
+            if (f[a] && f[a] == f[b]) return CANS_ERR_ALIAS;
     if (!pb.phi) {
-        // first use: the potential field and 1/dzc across each +z face
+        // first use: the potential field, the z centre distances across each
+        // +z face (and their inverses, 0 on a wall face) and the block maxima
+        // of the time-step rates
         const int nz = pb.nz;
-        std::vector<double> zgc(nz, 0.0);
-        for (int k = 0; k + 1 < nz; ++k) zgc[k] = 2.0 / (pb.dzf[k] + pb.dzf[k + 1]);
+        std::vector<double> zgc(nz, 0.0), dzc(nz, 0.0);
+        for (int k = 0; k + 1 < nz; ++k) {
+            dzc[k] = 0.5 * (pb.dzf[k] + pb.dzf[k + 1]);
+            zgc[k] = 2.0 / (pb.dzf[k] + pb.dzf[k + 1]);
+        }
+        dzc[nz - 1] = pb.cyclic ? 0.5 * (pb.dzf[nz - 1] + pb.dzf[0]) : pb.dzf[nz - 1];
         if (pb.cyclic) zgc[nz - 1] = 2.0 / (pb.dzf[nz - 1] + pb.dzf[0]);
         CANS_TRY(upload(plan, &pb.d_zgc, zgc.data(), nz));
+        CANS_TRY(upload(plan, &pb.d_dzc, dzc.data(), nz));
+        CANS_TRY(alloc(plan, &pb.dt_part, (size_t)dt_blocks(pb)));
         CANS_TRY(alloc(plan, &pb.phi, pb.npts()));
     }
     CANS_TRY(launch_div_xfwd(pb, u, v, w, gdt, pb.phi, stream));
     CANS_TRY(launch_y_f64(pb, true, pb.phi, pb.phi, stream));
-    CANS_TRY(launch_zsolve_f64(pb, pb.phi, pb.d_info + I_REMOVED, stream));
+    CANS_TRY(launch_zsolve_f64(pb, pb.ws, pb.phi, pb.ws.info + I_REMOVED, stream));
     CANS_TRY(launch_y_f64(pb, false, pb.phi, pb.phi, stream));
     CANS_TRY(launch_x_f64(pb, false, pb.phi, pb.phi, stream));
-    return launch_project_correct(pb, u, v, w, p, pb.phi, gdt, stream);
+    CANS_TRY(launch_project_correct(pb, u, v, w, p, pb.phi, gdt, alpha, stream));
+    if (dt_max) CANS_TRY(launch_max_dt(pb, u, v, w, nu, dt_max, stream));
+    return CANS_OK;
+}
+
+int cans_poisson_project(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt,
+                         hipStream_t stream)
+{
+    return cans_poisson_project_ex(plan, u, v, w, p, gdt, 0.0, 0.0, nullptr, stream);
 }
 
 int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, double *const *p, hipStream_t stream)
@@ -529,8 +546,8 @@ int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, doubl
         for (size_t i = 0; i < n && rc == CANS_OK; ++i) {
             const Problem &pb = plan->probs[i];
             hipStream_t s = g.side[g.branch[i]];
-            rc = plan->opts.precision == CANS_PREC_FP64 ? solve_fp64(pb, rhs[i], p[i], s)
-                                                        : solve_refine(pb, plan->opts, rhs[i], p[i], s);
+            rc = plan->opts.precision == CANS_PREC_FP64 ? solve_fp64(pb, pb.ws, rhs[i], p[i], s)
+                                                        : solve_refine(pb, pb.ws, plan->opts, rhs[i], p[i], s);
         }
         for (int b = 0; b < kBranches && rc == CANS_OK; ++b)
             if (hipEventRecord(g.join[b], g.side[b]) != hipSuccess || hipStreamWaitEvent(g.cap, g.join[b], 0) != hipSuccess)
@@ -573,19 +590,19 @@ int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, doub
     if (plan->opts.precision == CANS_PREC_FP32_REFINE) {
         // single kernels of the refinement path on the plan's FP32 field
         switch (stage) {
-        case 1: return in ? launch_x_fwd_32(pb, in, pb.a32, nullptr, stream) : CANS_ERR_INVALID_ARG;
-        case 2: return launch_y_32(pb, true, pb.a32, nullptr, stream);
-        case 3: return launch_zsolve_32(pb, pb.a32, nullptr, nullptr, stream);
-        case 4: return launch_y_32(pb, false, pb.a32, nullptr, stream);
-        case 5: return out ? launch_x_inv_32(pb, pb.a32, out, false, nullptr, stream) : CANS_ERR_INVALID_ARG;
-        case 0: return launch_reset(pb, stream);
+        case 1: return in ? launch_x_fwd_32(pb, pb.ws, in, pb.ws.a32, nullptr, stream) : CANS_ERR_INVALID_ARG;
+        case 2: return launch_y_32(pb, true, pb.ws.a32, nullptr, stream);
+        case 3: return launch_zsolve_32(pb, pb.ws, pb.ws.a32, nullptr, nullptr, stream);
+        case 4: return launch_y_32(pb, false, pb.ws.a32, nullptr, stream);
+        case 5: return out ? launch_x_inv_32(pb, pb.ws, pb.ws.a32, out, false, nullptr, stream) : CANS_ERR_INVALID_ARG;
+        case 0: return launch_reset(pb, pb.ws, stream);
         case 6:
             if (!in || !out) return CANS_ERR_INVALID_ARG;
-            return launch_resid_xfwd(pb, in, out, pb.a32, pb.d_flag, stream);
-        case 7: return out ? launch_x_inv_32(pb, pb.a32, out, true, nullptr, stream) : CANS_ERR_INVALID_ARG;
+            return launch_resid_xfwd(pb, pb.ws, in, out, pb.ws.a32, pb.ws.flag, stream);
+        case 7: return out ? launch_x_inv_32(pb, pb.ws, pb.ws.a32, out, true, nullptr, stream) : CANS_ERR_INVALID_ARG;
         case 8:
             if (!in || !out) return CANS_ERR_INVALID_ARG;
-            return launch_resid_norm(pb, in, out, pb.d_flag, stream);
+            return launch_resid_norm(pb, pb.ws, in, out, pb.ws.flag, stream);
         default: return CANS_ERR_INVALID_ARG;
         }
     }
@@ -597,7 +614,7 @@ int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, doub
         if (in != out && hipMemcpyAsync(out, in, pb.npts() * sizeof(double), hipMemcpyDeviceToDevice, stream) !=
                              hipSuccess)
             return CANS_ERR_HIP;
-        return launch_zsolve_f64(pb, out, pb.d_info + I_REMOVED, stream);
+        return launch_zsolve_f64(pb, pb.ws, out, pb.ws.info + I_REMOVED, stream);
     case 4: return launch_y_f64(pb, false, in, out, stream);
     case 5: return launch_x_f64(pb, false, in, out, stream);
     default: return CANS_ERR_INVALID_ARG;

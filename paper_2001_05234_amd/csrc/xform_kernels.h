@@ -8,7 +8,11 @@
 
 namespace cans {
 
-
+// x transform: a block holds L consecutive x lines (rows j + ny*k).
+// EPI 0: out = v;  EPI 1: out = out + v - info[I_MEANP] (refinement update).
+// `wsum_part` (optional, forward only): block partial sums of dzf_k * in in
+// FP64, so the exact weighted mean of the rhs is known in refinement mode.
+// At least 4 waves per SIMD: the staged FP64 inverses would otherwise take
 // 145 VGPRs and run 3 (the cap costs them a small spill and is faster).
 template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
@@ -103,9 +107,6 @@ __global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, i
                                                      BlockSync());
     }
 }
-
-// Residual of the current p fused with the forward x transform of it:
-//   r = (f - removed mean) - L_h p   (FP64), out = T_x r (FP32);
 
 // ---------------------------------------------------------------------------
 // Dense (matrix-core) x transforms of the refinement path: the same prologues

@@ -488,6 +488,80 @@ def test_projection_step(shape, bc):
     plan.close()
 
 
+@pytest.mark.parametrize("shape,bc", [((32, 24, 20), (P, P, P, P, N, N)), ((24, 16, 18), (N, N, P, P, N, N)),
+                                      ((16, 20, 12), (P, P, N, N, P, P)), ((18, 12, 10), (N, N, N, N, N, N)),
+                                      ((66, 40, 50), (P, P, P, P, N, N))])
+def test_projection_implicit_update_and_dt(shape, bc):
+    """cans_poisson_project_ex against the oracle: the implicit-diffusion
+    pressure update p += Phi - alpha L_h Phi (1e-12 on the change of p) and
+    the time-step bound of eq. (dt) on the corrected velocity (1e-14; with and
+    without the viscous bound), for periodic and walled axes and a ragged
+    grid; velocities equal those of the explicit form."""
+    nx, ny, nz = shape
+    dx, dy = 2 * np.pi / nx, np.pi / ny
+    dzf = np.full(nz, 2.0 / nz) if bc[4] == P else inputs.tanh_dzf(nz, 1.5, 2.0)
+    rng = np.random.default_rng(nx * ny + nz + sum(bc))
+    u, v, w, p = (rng.standard_normal((nz, ny, nx)) for _ in range(4))
+    if bc[0] == N:
+        u[:, :, -1] = 0
+    if bc[2] == N:
+        v[:, -1, :] = 0
+    if bc[4] == N:
+        w[-1] = 0
+    gdt, alpha = 1.6e-3, 0.8 * 2e-4 * 1.6e-3 / 2
+    say("projection ex", shape, bc)
+    plan = capi.Plan(nx, ny, nz, bc, dx, dy, dzf, precision="fp64")
+    uo, vo, wo, po, phi = O.project(u, v, w, p, bc, dx, dy, dzf, gdt, alpha=alpha)
+    for nu in (0.0, 5e-2):
+        dev = [torch.from_numpy(a.copy()).cuda() for a in (u, v, w, p)]
+        dt = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+        plan.project_ex(*dev, gdt, alpha=alpha, nu=nu, dt_max=dt)
+        torch.cuda.synchronize()
+        ug, vg, wg, pg = (a.cpu().numpy() for a in dev)
+        assert rel(pg - p, po - p) < TOL64, rel(pg - p, po - p)
+        for g_, o_, a_ in ((ug, uo, u), (vg, vo, v), (wg, wo, w)):
+            assert rel(g_ - a_, o_ - a_) < 1e-11, rel(g_ - a_, o_ - a_)
+        # the bound on the velocity the GPU returned (rates are local sums)
+        dto = O.max_dt(ug, vg, wg, bc, dx, dy, dzf, nu=nu)
+        say("  dt", float(dt.item()), dto)
+        assert abs(dt.item() - dto) <= 1e-14 * dto
+        # explicit form: same velocity, p += Phi only
+        dev2 = [torch.from_numpy(a.copy()).cuda() for a in (u, v, w, p)]
+        plan.project(*dev2, gdt)
+        torch.cuda.synchronize()
+        for a_, b_ in zip(dev[:3], dev2[:3]):
+            assert torch.equal(a_, b_)
+        pe = dev2[3].cpu().numpy()
+        # the implicit term -alpha L_h Phi alone
+        assert rel(pg - pe, po - p - phi) < 1e-10, rel(pg - pe, po - p - phi)
+    # without dt_max nothing is written
+    dt = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    dev = [torch.from_numpy(a.copy()).cuda() for a in (u, v, w, p)]
+    plan.project_ex(*dev, gdt, alpha=alpha)
+    torch.cuda.synchronize()
+    assert dt.item() == -1.0
+    plan.close()
+
+
+def test_projection_ex_rejections_and_rest():
+    nx, ny, nz = 16, 12, 8
+    a = [torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+    plan = capi.Plan(nx, ny, nz, (P, P, P, P, N, N), 0.1, 0.1, np.full(nz, 0.1), precision="fp64")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for kw in ({"alpha": -1.0}, {"nu": -1.0}, {"alpha": float("nan")}, {"nu": float("inf")}):
+        with pytest.raises(capi.CansError) as e:
+            plan.project_ex(*a, 0.1, dt_max=dt, **kw)
+        assert e.value.code == -1
+    # a field at rest: +inf without viscosity, the viscous bound with it
+    plan.project_ex(*a, 0.1, dt_max=dt)
+    torch.cuda.synchronize()
+    assert dt.item() == float("inf")
+    plan.project_ex(*a, 0.1, nu=1e-3, dt_max=dt)
+    torch.cuda.synchronize()
+    assert dt.item() == pytest.approx(1.65 * 0.1 ** 2 / 1e-3, rel=1e-15)
+    plan.close()
+
+
 def test_projection_rejections():
     nx, ny, nz = 16, 12, 8
     a = [torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda") for _ in range(4)]

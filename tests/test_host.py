@@ -101,6 +101,7 @@ def test_options_validation():
 def test_project_rejects_null_plan():
     lib = capi.load()
     assert lib.cans_poisson_project(None, None, None, None, None, 1.0, None) == -1
+    assert lib.cans_poisson_project_ex(None, None, None, None, None, 1.0, 0.0, 0.0, None, None) == -1
 
 
 def test_null_arguments():
