@@ -490,7 +490,7 @@ def test_projection_step(shape, bc):
 
 @pytest.mark.parametrize("shape,bc", [((32, 24, 20), (P, P, P, P, N, N)), ((24, 16, 18), (N, N, P, P, N, N)),
                                       ((16, 20, 12), (P, P, N, N, P, P)), ((18, 12, 10), (N, N, N, N, N, N)),
-                                      ((66, 40, 50), (P, P, P, P, N, N))])
+                                      ((90, 40, 50), (P, P, P, P, N, N))])
 def test_projection_implicit_update_and_dt(shape, bc):
     """cans_poisson_project_ex against the oracle: the implicit-diffusion
     pressure update p += Phi - alpha L_h Phi (1e-12 on the change of p) and
