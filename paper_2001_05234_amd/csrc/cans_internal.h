@@ -53,6 +53,18 @@ struct Work {
     double *info = nullptr;        // info record, I_SIZE doubles
     int *flag = nullptr;           // [0] refinement finished
     double *wc = nullptr, *wd = nullptr, *wz = nullptr;  // plain elimination (deep or periodic z)
+    unsigned *zctr = nullptr;      // pipelined z solve: tiles claimed, blocks finished (zero between launches)
+};
+
+// Launch shape of the persistent, pipelined z solve (k_zsolve_pipe), chosen
+// when the plan is built; off when the problem does not fit it.
+constexpr int kPipeCols = 32;      // columns per tile
+constexpr int kPipeThreads = 768;  // largest block (24 segments of 16 levels)
+struct PipePlan {
+    bool on = false;
+    bool db = false;   // two tile buffers in LDS
+    int threads = 0, grid = 0, ntiles = 0;
+    size_t lds = 0;
 };
 
 struct Problem {
@@ -67,6 +79,7 @@ struct Problem {
     double *d_za = nullptr, *d_zb = nullptr, *d_zc = nullptr;
     double *d_zaf = nullptr, *d_zcf = nullptr, *d_dzf = nullptr;
     Work ws;                       // the plan's own workspace
+    PipePlan zpipe32, zpipe64;     // pipelined z solve for FP32 / FP64 data
     // projection step (allocated at its first use)
     double *phi = nullptr;         // the potential Phi (FP64 field)
     double *d_zgc = nullptr;       // 1/dzc_k across the +z face of level k, 0 on a wall face
@@ -86,6 +99,8 @@ int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipSt
 int launch_x_inv_32(const Problem &pb, const Work &w, const float *in, double *p, bool update, const int *done,
                     hipStream_t s);
 int launch_zsolve_f64(const Problem &pb, const Work &w, double *data, double *removed, hipStream_t s);
+// choose the pipelined z-solve shapes of a problem (plan time)
+int plan_zpipe(Problem &pb);
 int launch_zsolve_32(const Problem &pb, const Work &w, float *data, double *removed, const int *done, hipStream_t s);
 // refinement: residual fused with the forward x transform (FP32 out), and the
 // residual norm alone; then the reduction that decides convergence.

@@ -2,6 +2,9 @@
 // its launchers.
 #include "kcommon.h"
 
+#include <algorithm>
+#include <cstdint>
+
 namespace cans {
 
 template <typename T>
@@ -84,9 +87,286 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent, software-pipelined form of the partitioned solve (non-periodic
+// z).  A block stays resident and walks tiles of kPipeCols adjacent columns x
+// all levels.  The tile is brought into LDS by direct global->LDS loads
+// (global_load_lds_dwordx4: the data goes to LDS without passing through
+// registers), so the next tile's fetch is in flight while the current one is
+// solved.  Per tile: each lane (one column, one segment of MMAX levels) runs
+// the single-sweep reduction (zp_sweep_reduce), wave 0 solves the interface
+// system of every column from both ends (zp_ends_*), each lane finishes its
+// segment and stores it.
+// DB (two tile buffers): the next fetch starts at the top of an iteration and
+// the rhs is read from LDS in the reduction and again in the finish.  !DB (one
+// buffer): the rhs is copied to registers first and the next fetch starts
+// after that.  lambda of the next tile is loaded after the stores, so the only
+// wait for global memory is the one at the top of an iteration.
+// Levels beyond nz (the segments cover S * MMAX >= nz) are the decoupled
+// padding rows of zpad_row; their loads are clamped to a real level and
+// replaced by zero, their stores skipped.
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename T>
+struct PipeGeom {
+    static constexpr int ROW_B = kPipeCols * (int)sizeof(T);  // bytes of one level of a tile
+    static constexpr int RPI = 1024 / ROW_B;                    // levels per wave-wide 16-byte load
+    static constexpr int GRP_B = 1024 + 64;                     // LDS bytes per load group (padded)
+};
+
+template <typename T, int MMAX, bool DB>
+__global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag, int ntiles, unsigned *ctr,
+                                                              const int *__restrict__ done)
+{
+    if (done && *done) return;
+    using G = PipeGeom<T>;
+    static_assert(MMAX % G::RPI == 0, "segments start on a load group");
+    extern __shared__ __align__(16) unsigned char sm[];
+    constexpr int SPW = 64 / kPipeCols;              // segments per wave
+    const int nw = (int)(blockDim.x >> 6);
+    const int S = nw * SPW;                          // segments per column
+    const int nzp = S * MMAX;                        // levels incl. padding
+    const int nz = ag.nz;
+    const int ngrp = nzp / G::RPI;
+    const size_t tb = (size_t)ngrp * G::GRP_B;
+    unsigned char *buf0 = sm, *buf1 = sm + (DB ? tb : 0);
+    double *coef = reinterpret_cast<double *>(sm + (DB ? 2 : 1) * tb);
+    double *zabc = coef + 6 * S * kPipeCols;
+    // tile numbers from thread 0: [2] the first, [it & 1] the next one in
+    // iteration it (two slots, so a slot is rewritten only after a barrier
+    // that every thread passes after reading it)
+    int *tslot = reinterpret_cast<int *>(zabc + 3 * nzp);
+    for (int i = threadIdx.x; i < nzp; i += blockDim.x) zpad_row(ag, i, zabc[i], zabc[nzp + i], zabc[2 * nzp + i]);
+    // levels beyond nz are never fetched: their LDS rows stay zero, the
+    // padding rows' zero right-hand side
+    for (int b = 0; b < (DB ? 2 : 1); ++b)
+        for (int e = threadIdx.x; e < (nzp - nz) * kPipeCols; e += blockDim.x) {
+            const int k = nz + e / kPipeCols;
+            *reinterpret_cast<T *>((b ? buf1 : buf0) + (k / G::RPI) * G::GRP_B + (k % G::RPI) * G::ROW_B +
+                                   (e % kPipeCols) * (int)sizeof(T)) = T(0);
+        }
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = lane % kPipeCols, seg = w * SPW + lane / kPipeCols;
+    const int k0 = seg * MMAX;
+    const double *za = zabc + k0, *zb = zabc + nzp + k0, *zc = zabc + 2 * nzp + k0;
+    const size_t plane = (size_t)ag.nx * ag.ny;
+    // the six coefficients of a segment sit kPipeCols doubles apart, so one
+    // base address per segment and column serves all of them
+    auto C = [&](int q, int s, int cc) -> double & { return coef[(s * 6 + q) * kPipeCols + cc]; };
+    // global->LDS: lane = (level in the group, 16-byte chunk of the level)
+    constexpr int CHUNK = 16 / (int)sizeof(T);
+    const int lrow = lane / (64 / G::RPI);
+    const int lcol = (lane % (64 / G::RPI)) * CHUNK;
+    auto fetch = [&](int t, unsigned char *buf) {
+        size_t c0 = (size_t)t * kPipeCols + lcol;
+        if (c0 >= plane) c0 = plane - CHUNK;  // beyond the last column: any real chunk (not used)
+        for (int gi = w; gi < ngrp; gi += nw) {
+            const int row = gi * G::RPI + lrow;
+            if (row < nz)
+                __builtin_amdgcn_global_load_lds((const void *)(data + c0 + plane * row),
+                                                 (lds_void *)(buf + gi * G::GRP_B), 16, 0, 0);
+        }
+    };
+    const int boff = (k0 / G::RPI) * G::GRP_B + c * (int)sizeof(T);
+    auto raw = [&](const unsigned char *buf, int q) -> T {
+        return *reinterpret_cast<const T *>(buf + boff + (q / G::RPI) * G::GRP_B + (q % G::RPI) * G::ROW_B);
+    };
+    const double scale = ag.scale;
+    // the singular column (column 0 of a singular problem) is solved apart
+    const size_t skip = ag.singular ? 0 : ~(size_t)0;
+    const unsigned nxu = (unsigned)ag.nx;
+    double lxn = 0, lyn = 0;
+    // columns not solved here (beyond the plane, the singular one) get the
+    // regular lambda -1
+    auto lamload = [&](int t) {
+        const size_t col = (size_t)t * kPipeCols + c;
+        const bool own = col < plane && col != skip;
+        const unsigned cu = own ? (unsigned)col : 0u;
+        lxn = own ? ag.lamx[cu % nxu] : -1.0;
+        lyn = own ? ag.lamy[cu / nxu] : 0.0;
+    };
+    // Tiles are claimed from a counter (ctr[0]) by thread 0, two ahead of the
+    // one being solved, so a block that starts late (block 0 with the singular
+    // column) simply solves fewer.  The last block to finish (ctr[1]) resets
+    // both counters for the next launch.
+    if (threadIdx.x == 0) tslot[2] = (int)atomicAdd(&ctr[0], 1u);
+    __syncthreads();
+    int t = tslot[2], it = 0;
+    if (t < ntiles) {
+        fetch(t, buf0);
+        lamload(t);
+    }
+    int claim = 0;  // thread 0: the tile after the next
+    if (threadIdx.x == 0) claim = (int)atomicAdd(&ctr[0], 1u);
+    if (ag.singular && blockIdx.x == 0) {
+        // the singular column: projected rhs, pinned last row, zero weighted
+        // mean, by one thread on a copy staged in the coefficient area
+        T *colv = reinterpret_cast<T *>(coef);
+        double *wdz = coef + nz, *wc = coef + 2 * nz, *wd = coef + 3 * nz;
+        for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+            colv[k] = data[plane * k];
+            wdz[k] = ag.dzf[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ZArgs a = ag;
+            a.nx = 1;
+            a.ny = 1;
+            a.za = zabc;
+            a.zb = zabc + nzp;
+            a.zc = zabc + 2 * nzp;
+            a.dzf = wdz;
+            zsolve_singular_ws<T>(0, colv, a, wc, wd, 1);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nz; k += blockDim.x) data[plane * k] = colv[k];
+    }
+    while (t < ntiles) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (threadIdx.x == 0) tslot[it & 1] = claim;
+        __syncthreads();
+        const int tn = tslot[it & 1];
+        const unsigned char *cur = (DB && (it & 1)) ? buf1 : buf0;
+        const double lam = lxn + lyn;
+        T f[DB ? 1 : MMAX];  // !DB: the tile's rhs, as stored
+        if constexpr (DB) {
+            if (tn < ntiles) fetch(tn, (it & 1) ? buf0 : buf1);
+        } else {
+#pragma unroll
+            for (int q = 0; q < MMAX; ++q) f[q] = raw(cur, q);
+            __syncthreads();
+            if (tn < ntiles) fetch(tn, buf0);
+        }
+        if (threadIdx.x == 0 && tn < ntiles) claim = (int)atomicAdd(&ctr[0], 1u);
+        auto fv = [&](int q) -> double {
+            if constexpr (DB) return scale * (double)raw(cur, q);
+            else return scale * (double)f[q];
+        };
+        double r[MMAX], out[6];
+        zp_sweep_reduce<MMAX>(fv, za, zb, zc, lam, r, out);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) C(q, seg, c) = out[q];
+        __syncthreads();
+        if (w == 0) {
+            // lanes [0, 32): top role, [32, 64): bottom role of column lane & 31
+            const bool bot = lane >= 32;
+            const int cc = lane & 31;
+            auto Cc = [&](int q, int s) -> double & { return C(q, s, cc); };
+            double y2, g2;
+            zp_ends_forward<4>(S, bot, Cc, y2, g2);
+            const double y2o = __shfl_xor(y2, 32, 64), g2o = __shfl_xor(g2, 32, 64);
+            zp_ends_backward<4>(S, bot, Cc, zp_ends_meet(y2, g2, y2o, g2o));
+        }
+        __syncthreads();
+        const double xL = seg > 0 ? C(5, seg - 1, c) : 0.0;
+        const double xR = seg < S - 1 ? C(4, seg + 1, c) : 0.0;
+        double x[MMAX];
+        zp_sweep_finish<MMAX>(fv, za, zc, r, xL, xR, x);
+        const size_t col = (size_t)t * kPipeCols + c;
+        if (col < plane && col != skip) {
+            // levels of this segment below nz; opaque to the compiler so the
+            // comparisons are not hoisted out of the tile loop
+            int lim = nz - k0;
+            asm volatile("" : "+v"(lim));
+            T *ptr = data + col + plane * k0;
+#pragma unroll
+            for (int q = 0; q < MMAX; ++q) {
+                if (q < lim) ptr[0] = (T)x[q];
+                ptr += plane;
+            }
+        }
+        if (tn < ntiles) lamload(tn);
+        t = tn;
+        ++it;
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&ctr[1], 1u) == gridDim.x - 1) {
+            ctr[0] = 0;
+            ctr[1] = 0;
+        }
+    }
+}
+
+// LDS bytes of k_zsolve_pipe for S segments of MMAX levels
+template <typename T>
+static size_t pipe_lds(int S, int mmax, bool db)
+{
+    using G = PipeGeom<T>;
+    const int nzp = S * mmax;
+    return (db ? 2 : 1) * (size_t)(nzp / G::RPI) * G::GRP_B + (size_t)6 * S * kPipeCols * 8 + (size_t)3 * nzp * 8 +
+           16;
+}
+
+template <typename T>
+static const void *pipe_kernel(bool db)
+{
+    return db ? (const void *)k_zsolve_pipe<T, 16, true> : (const void *)k_zsolve_pipe<T, 16, false>;
+}
+
+// Shape of the pipelined solve for this problem (or none): non-periodic z
+// with 128 < nz <= 384, 16-level segments, two per wave (S even, <= 24, so
+// at most 768 threads and 168 registers a lane).  Two tile buffers when they
+// fit the 160 KiB of LDS, else one; 16-byte aligned data.  The grid is one
+// resident block per available slot.
+template <typename T>
+static PipePlan pipe_plan_of(const Problem &pb)
+{
+    PipePlan pp;
+    if (pb.cyclic || pb.nz <= 128 || pb.nz > 384) return pp;
+    int S = (pb.nz + 15) / 16;
+    S += S & 1;
+    const size_t kLds = 160 * 1024;
+    const bool db = pipe_lds<T>(S, 16, true) <= kLds;
+    const size_t lds = pipe_lds<T>(S, 16, db);
+    if (lds > kLds) return pp;
+    const void *k = pipe_kernel<T>(db);
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return pp;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return pp;
+    const int threads = 32 * S;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, lds) != hipSuccess || per < 1) return pp;
+    const size_t plane = (size_t)pb.nx * pb.ny;
+    const long ntiles = (long)((plane + kPipeCols - 1) / kPipeCols);
+    pp.on = true;
+    pp.db = db;
+    pp.threads = threads;
+    pp.lds = lds;
+    pp.ntiles = (int)ntiles;
+    pp.grid = (int)std::min<long>(ntiles, (long)ncu * per);
+    return pp;
+}
+
+int plan_zpipe(Problem &pb)
+{
+    pb.zpipe32 = pipe_plan_of<float>(pb);
+    pb.zpipe64 = pipe_plan_of<double>(pb);
+    return CANS_OK;
+}
+
+template <typename T>
+static int launch_zpipe(const Problem &pb, const PipePlan &pp, unsigned *ctr, T *data, double *removed,
+                        const int *done, hipStream_t s)
+{
+    ZArgs za = zargs(pb, Work{}, removed);
+    if (pp.db)
+        hipLaunchKernelGGL((k_zsolve_pipe<T, 16, true>), dim3(pp.grid), dim3(pp.threads), pp.lds, s, data, za,
+                           pp.ntiles, ctr, done);
+    else
+        hipLaunchKernelGGL((k_zsolve_pipe<T, 16, false>), dim3(pp.grid), dim3(pp.threads), pp.lds, s, data, za,
+                           pp.ntiles, ctr, done);
+    return check_launch();
+}
+
 template <typename T>
 static int launch_zsolve(const Problem &pb, const Work &w, T *data, double *removed, const int *done, hipStream_t s)
 {
+    const PipePlan &pp = sizeof(T) == 4 ? pb.zpipe32 : pb.zpipe64;
+    if (pp.on && w.zctr && ((uintptr_t)data & 15) == 0) return launch_zpipe<T>(pb, pp, w.zctr, data, removed, done, s);
     const size_t plane = (size_t)pb.nx * pb.ny;
     const ZPart zp = zpart_shape(pb.nz, pb.cyclic != 0);
     ZArgs za = zargs(pb, w, removed);

@@ -232,6 +232,7 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     CANS_TRY(upload(pl, &pb.d_zaf, af.data(), nz));
     CANS_TRY(upload(pl, &pb.d_zcf, cf.data(), nz));
     CANS_TRY(upload(pl, &pb.d_dzf, pb.dzf.data(), nz));
+    CANS_TRY(plan_zpipe(pb));
     // workspace of the plain elimination (nz beyond the register-resident
     // partitioned solve): multipliers and modified rhs
     const size_t N = pb.npts();
@@ -251,6 +252,8 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     CANS_TRY(upload(pl, &pb.ws.info, info.data(), I_SIZE));
     int zero = 0;
     CANS_TRY(upload(pl, &pb.ws.flag, &zero, 1));
+    const unsigned zc2[2] = {0u, 0u};
+    CANS_TRY(upload(pl, &pb.ws.zctr, zc2, 2));
     return CANS_OK;
 }
 

@@ -513,6 +513,165 @@ CANS_HD void zp_store(const ZLane<MMAX, CYC> &L, T *data, const ZArgs &a, size_t
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-sweep form of the segment reduction (non-periodic z).  The top-down
+// elimination of a segment with its outside neighbours xL, xR kept symbolic,
+//   x_t = d_t - g_t xL - cp_t x_{t+1},
+// also gives the first row by back-substituting symbolically:
+//   x_0 = sum_t P_t (d_t - g_t xL) + P_m xR,   P_t = prod_{j<t} (-cp_j),
+// so one sweep yields all six coefficients of the interface relations
+//   x_{k0} + A xL + B xR = D,   x_{k1-1} + C xL + E xR = F
+// with A = sum P_t g_t, B = -P_m, D = sum P_t d_t, C = g_{m-1}, E = cp_{m-1},
+// F = d_{m-1}.  Only the reciprocal pivots r_t are kept for the finish.  For
+// the operators here b + lam < 0 < a, c, so every P_t and every g_t has one
+// sign: the sums for A and B do not cancel.
+// fv(t): scaled rhs of level t; za/zb/zc: the segment's first level.
+template <int MMAX, typename FV>
+CANS_HD void zp_sweep_reduce(const FV &fv, const double *za, const double *zb, const double *zc, double lam,
+                             double (&r)[MMAX], double (&out)[6])
+{
+    double cp = 0, d = 0, g = 0, P = 1, Ds = 0, As = 0;
+    // the next level's coefficients are read one level ahead
+    double an = za[0], bn = zb[0], cn = zc[0];
+    for (int t = 0; t < MMAX; ++t) {
+        const double ak = an, bk = bn + lam, ck = cn;
+        if (t + 1 < MMAX) {
+            an = za[t + 1];
+            bn = zb[t + 1];
+            cn = zc[t + 1];
+        }
+        const double rr = rcp64(t == 0 ? bk : bk - ak * cp);
+        r[t] = rr;
+        d = (t == 0 ? fv(t) : fv(t) - ak * d) * rr;
+        g = (t == 0 ? ak : -ak * g) * rr;
+        zp_pin(g);
+        Ds = fma(P, d, Ds);
+        As = fma(P, g, As);
+        cp = ck * rr;
+        P = -P * cp;
+        zp_pin(P);
+    }
+    out[0] = As;
+    out[1] = -P;
+    out[2] = g;
+    out[3] = Ds;
+    out[4] = cp;
+    out[5] = d;
+}
+
+// x of the segment from its outside neighbours: the top-down sweep again with
+// xL known (stored reciprocal pivots), then back-substitution from xR.
+template <int MMAX, typename FV>
+CANS_HD void zp_sweep_finish(const FV &fv, const double *za, const double *zc, const double (&r)[MMAX], double xL,
+                             double xR, double (&x)[MMAX])
+{
+    double d = xL;
+    double an = za[0];
+    for (int t = 0; t < MMAX; ++t) {
+        const double ak = an;
+        if (t + 1 < MMAX) an = za[t + 1];
+        d = (fv(t) - ak * d) * r[t];
+        x[t] = d;
+    }
+    double xx = xR;
+    double cn = zc[MMAX - 1];
+    for (int t = MMAX - 1; t >= 0; --t) {
+        const double ck = cn;
+        if (t > 0) cn = zc[t - 1];
+        xx = x[t] - ck * r[t] * xx;
+        x[t] = xx;
+    }
+}
+
+// The interface system of one column solved from both ends at once.  The top
+// role eliminates over segments 0 .. S/2-1 exactly as zp_interface does
+// (v_s = y2 - g2 u_{s+1}, u_s = y1 - g1 u_{s+1}); the bottom role eliminates
+// upwards over S-1 .. S/2 (u_s = p1 - h1 v_{s-1}, v_s = p2 - h2 v_{s-1}).  The
+// bottom recurrence is the top one with the coefficients (A,B,C,D,E,F) read as
+// (E,C,B,F,A,D) and the results (y1,y2,g1,g2) standing for (p2,p1,h2,h1), so
+// one code path serves both.  The two chains meet between segments S/2-1 and
+// S/2 (v_{S/2-1} = y2 - g2 u_{S/2}, u_{S/2} = p1 - h1 v_{S/2-1}), then each role
+// substitutes back over its half.  Coefficients are read NB steps at a time.
+// C(q, s): coefficient q of segment s of this column; results u_s -> C(4, s),
+// v_s -> C(5, s).
+CANS_HD int zp_ends_steps(int S, bool bot) { return bot ? S - S / 2 : S / 2; }
+
+template <int NB, typename Cf>
+CANS_HD void zp_ends_forward(int S, bool bot, Cf C, double &y2p, double &g2p)
+{
+    const int n = zp_ends_steps(S, bot), nmax = S - S / 2;
+    const int qA = bot ? 4 : 0, qB = bot ? 2 : 1, qC = bot ? 1 : 2, qD = bot ? 5 : 3, qE = bot ? 0 : 4, qF = bot ? 3 : 5;
+    y2p = 0;
+    g2p = 0;
+#pragma unroll 1
+    for (int b0 = 0; b0 < nmax; b0 += NB) {
+        double A[NB], B[NB], Cc[NB], D[NB], E[NB], F[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = b0 + j < n ? b0 + j : n - 1;
+            const int s = bot ? S - 1 - i : i;
+            A[j] = C(qA, s); B[j] = C(qB, s); Cc[j] = C(qC, s);
+            D[j] = C(qD, s); E[j] = C(qE, s); F[j] = C(qF, s);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = b0 + j;
+            if (i < n) {
+                const int s = bot ? S - 1 - i : i;
+                const double inv = rcp64(1.0 - A[j] * g2p);
+                const double y1 = (D[j] - A[j] * y2p) * inv;
+                const double cg = Cc[j] * g2p;
+                const double y2 = (F[j] - Cc[j] * y2p) + cg * y1;
+                const double g1 = B[j] * inv;
+                const double g2 = E[j] + cg * g1;
+                C(0, s) = y1;
+                C(1, s) = y2;
+                C(2, s) = g1;
+                C(3, s) = g2;
+                g2p = g2;
+                y2p = y2;
+            }
+        }
+    }
+}
+
+// the unknown next to the meeting point on this role's side of the other
+// role's last relation: top gets u_{S/2}, bottom gets v_{S/2-1}
+CANS_HD double zp_ends_meet(double y2, double g2, double y2o, double g2o)
+{
+    return (y2o - g2o * y2) * rcp64(1.0 - g2 * g2o);
+}
+
+template <int NB, typename Cf>
+CANS_HD void zp_ends_backward(int S, bool bot, Cf C, double prev)
+{
+    const int n = zp_ends_steps(S, bot), nmax = S - S / 2;
+    const int q1 = bot ? 5 : 4, q2 = bot ? 4 : 5;
+#pragma unroll 1
+    for (int b0 = 0; b0 < nmax; b0 += NB) {
+        double Y1[NB], Y2[NB], G1[NB], G2[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i0 = n - 1 - (b0 + j);
+            const int i = i0 >= 0 ? i0 : 0;
+            const int s = bot ? S - 1 - i : i;
+            Y1[j] = C(0, s); Y2[j] = C(1, s); G1[j] = C(2, s); G2[j] = C(3, s);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i0 = n - 1 - (b0 + j);
+            if (i0 >= 0) {
+                const int s = bot ? S - 1 - i0 : i0;
+                const double o1 = Y1[j] - G1[j] * prev;
+                const double o2 = Y2[j] - G2[j] * prev;
+                C(q1, s) = o1;
+                C(q2, s) = o2;
+                prev = o1;
+            }
+        }
+    }
+}
+
 // Shape of the partitioned solve for nz: register depth per lane, columns
 // per block and threads per block (segments = threads/64 * 64/cpb).
 //   nz <= 128: 64 columns, segments of <= 8 levels;

@@ -221,10 +221,85 @@ void zsolve_part_mm(Setup &s, T *data, double *removed, int cpb, int S)
     }
 }
 
+// the persistent pipelined z kernel (non-periodic z, 128 < nz <= 384), phase
+// by phase over the tiles of 32 columns: single-sweep reduction per segment,
+// the interface of every column from both ends, the finish; padding levels
+// have a zero right-hand side and are not stored
+template <typename T>
+void zsolve_pipe_mm(Setup &s, T *data, double *removed)
+{
+    constexpr int MMAX = 16, CPB = 32;
+    int S = (s.nz + 15) / 16;
+    S += S & 1;
+    const int nzp = S * MMAX, nz = s.nz;
+    std::vector<double> pa(nzp), pb(nzp), pc(nzp);
+    for (int k = 0; k < nzp; ++k) zpad_row(s.z, k, pa[k], pb[k], pc[k]);
+    const size_t plane = (size_t)s.nx * s.ny;
+    // the singular column first (the kernel's block 0 does it before its
+    // tiles), sequentially as zsolve_singular_ws
+    if (s.z.singular) {
+        std::vector<double> wc(nz), wd(nz);
+        ZArgs as = s.z;
+        as.removed = removed;
+        as.za = pa.data(); as.zb = pb.data(); as.zc = pc.data();
+        zsolve_singular_ws<T>(0, data, as, wc.data(), wd.data(), 1);
+    }
+    const size_t skip = s.z.singular ? 0 : ~(size_t)0;
+    std::vector<double> coef((size_t)6 * S * CPB), r((size_t)S * CPB * MMAX), xs((size_t)S * CPB * MMAX);
+    auto C = [&](int q, int sg, int c) -> double & { return coef[((size_t)sg * 6 + q) * CPB + c]; };
+    for (size_t col0 = 0; col0 < plane; col0 += CPB) {
+        auto own = [&](size_t col) { return col < plane && col != skip; };
+        auto lam_of = [&](size_t col) { return own(col) ? s.lamx[col % s.nx] + s.lamy[col / s.nx] : -1.0; };
+        auto fv_of = [&](size_t col, int k0, int q) -> double {
+            const int k = k0 + q;
+            return (col < plane && k < nz) ? s.z.scale * (double)data[col + plane * k] : 0.0;
+        };
+        for (int sg = 0; sg < S; ++sg)
+            for (int c = 0; c < CPB; ++c) {
+                const size_t col = col0 + c;
+                auto fv = [&](int q) -> double { return fv_of(col, sg * MMAX, q); };
+                double rr[MMAX], out[6];
+                zp_sweep_reduce<MMAX>(fv, &pa[sg * MMAX], &pb[sg * MMAX], &pc[sg * MMAX], lam_of(col), rr, out);
+                for (int q = 0; q < MMAX; ++q) r[((size_t)sg * CPB + c) * MMAX + q] = rr[q];
+                for (int q = 0; q < 6; ++q) C(q, sg, c) = out[q];
+            }
+        for (int c = 0; c < CPB; ++c) {
+            auto Cc = [&](int q, int sg) -> double & { return C(q, sg, c); };
+            double y2t, g2t, y2b, g2b;
+            zp_ends_forward<4>(S, false, Cc, y2t, g2t);
+            zp_ends_forward<4>(S, true, Cc, y2b, g2b);
+            const double pt = zp_ends_meet(y2t, g2t, y2b, g2b), pbm = zp_ends_meet(y2b, g2b, y2t, g2t);
+            zp_ends_backward<4>(S, false, Cc, pt);
+            zp_ends_backward<4>(S, true, Cc, pbm);
+        }
+        for (int sg = 0; sg < S; ++sg)
+            for (int c = 0; c < CPB; ++c) {
+                const size_t col = col0 + c;
+                auto fv = [&](int q) -> double { return fv_of(col, sg * MMAX, q); };
+                double rr[MMAX], x[MMAX];
+                for (int q = 0; q < MMAX; ++q) rr[q] = r[((size_t)sg * CPB + c) * MMAX + q];
+                const double xL = sg > 0 ? C(5, sg - 1, c) : 0.0, xR = sg < S - 1 ? C(4, sg + 1, c) : 0.0;
+                zp_sweep_finish<MMAX>(fv, &pa[sg * MMAX], &pc[sg * MMAX], rr, xL, xR, x);
+                for (int q = 0; q < MMAX; ++q) xs[((size_t)sg * CPB + c) * MMAX + q] = x[q];
+            }
+        for (int sg = 0; sg < S; ++sg)
+            for (int c = 0; c < CPB; ++c) {
+                const size_t col = col0 + c;
+                if (!own(col)) continue;
+                for (int q = 0; q < MMAX && sg * MMAX + q < nz; ++q)
+                    data[col + plane * (sg * MMAX + q)] = (T)xs[((size_t)sg * CPB + c) * MMAX + q];
+            }
+    }
+}
+
 // the kernel shape the GPU launches for this nz; false when it does not apply
 template <typename T>
 bool zsolve_part_any(Setup &s, T *data, double *removed)
 {
+    if (!s.z.cyclic && s.nz > 128 && s.nz <= 384) {
+        zsolve_pipe_mm(s, data, removed);
+        return true;
+    }
     const ZPart zp = zpart_shape(s.nz, s.z.cyclic != 0);
     if (zp.mmax == 0) return false;
     const int S = (zp.threads / 64) * (64 / zp.cpb);

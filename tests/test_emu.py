@@ -123,7 +123,9 @@ def test_zsolve_stage():
 def test_zsolve_partitioned(nz):
     """Register-resident partitioned z solve (segments per wave, reduced
     interface system) against the oracle's column solves, including the
-    singular column and ragged column blocks."""
+    singular column and ragged column blocks.  For 128 < nz <= 384 on a
+    non-periodic z this is the persistent pipelined kernel's arithmetic
+    (single-sweep reduction, interface from both ends, padded levels)."""
     rng = np.random.default_rng(nz)
     for bc in [(P, P, N, N, N, N), (D, N, P, P, D, D), (N, N, N, N, N, D), (P, P, P, P, D, N)]:
         ny, nx = 6, 22
