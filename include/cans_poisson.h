@@ -61,7 +61,9 @@ enum cans_status {
                                    do not allow, shift > 0) */
     CANS_ERR_ALLOC = -3,        /* device or host allocation failed */
     CANS_ERR_HIP = -4,          /* HIP runtime or launch error */
-    CANS_ERR_ALIAS = -5         /* rhs == p where the mode forbids it */
+    CANS_ERR_ALIAS = -5,        /* rhs == p where the mode forbids it */
+    CANS_ERR_TOO_LARGE = -6     /* the problem's workspace exceeds the fixed
+                                   scratch of cans_poisson_solve_noalloc */
 };
 
 /* arithmetic of the transforms (the z elimination is always FP64) */
@@ -170,6 +172,30 @@ int cans_poisson_plan_ex(cans_plan_t *out, int nx, int ny, int nz, const int bc[
  * cans_poisson_get_info.
  */
 int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as cans_poisson_solve, with the same arguments, results and rules,
+ * but every per-solve device buffer it writes (the FP32 spectral field of
+ * FP32_REFINE plans, block partial sums, the info record, the convergence
+ * flag, the z-solve tile counters, and the plain elimination's multipliers
+ * where nz needs them) carved from one fixed array compiled into the library,
+ * CANS_NOALLOC_SCRATCH_BYTES bytes per device, held until the process ends.
+ * The call allocates nothing: no hipMalloc, no graph (opts.graph is ignored,
+ * kernels are launched directly).  Plans with more than one problem give
+ * CANS_ERR_INVALID_ARG, a problem whose buffers exceed the array gives
+ * CANS_ERR_TOO_LARGE (FP32_REFINE: about 4 bytes per grid point, so up to
+ * roughly 20 million points; FP64 plans need a few hundred bytes unless nz >
+ * 512 or z is periodic with nz > 128, which need 16-24 bytes per point), and a
+ * current device other than the plan's gives CANS_ERR_INVALID_ARG.  The info
+ * record is copied into the plan's at the end, so cans_poisson_get_info
+ * reports this solve after a stream sync.  Every call on one device shares
+ * that device's array: calls that overlap on one device (other streams or
+ * threads, before the previous one completed) race and give wrong results.
+ */
+#define CANS_NOALLOC_SCRATCH_BYTES (80u << 20)
+int cans_poisson_solve_noalloc(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream);
 
 /*
  * Enqueue one projection (pressure-correction) step, the equations that

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libcans_poisson.so")
 
 CANS_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported problem", -3: "allocation failed",
-          -4: "HIP runtime error", -5: "rhs and p alias"}
+          -4: "HIP runtime error", -5: "rhs and p alias",
+          -6: "problem exceeds the fixed scratch of the no-allocation solve"}
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 XFORM_AUTO, XFORM_FFT, XFORM_DENSE = 0, 1, 2
 BC_PERIODIC, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET_FACE = 0, 1, 2, 3
@@ -37,7 +38,7 @@ EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "ca
            "cans_poisson_get_info", "cans_poisson_destroy", "cans_status_string",
            "cans_poisson_workspace_bytes", "cans_poisson_debug_stage", "cans_poisson_plan_batched",
            "cans_poisson_solve_batched", "cans_poisson_get_info_batched", "cans_poisson_project",
-           "cans_poisson_project_ex"]
+           "cans_poisson_project_ex", "cans_poisson_solve_noalloc"]
 
 
 class CansOpts(ctypes.Structure):
@@ -83,6 +84,7 @@ def load() -> ctypes.CDLL:
         "cans_poisson_plan": ([pp, i, i, i, ip, d, d, dp], i),
         "cans_poisson_plan_ex": ([pp, i, i, i, ip, d, d, dp, ctypes.POINTER(CansOpts)], i),
         "cans_poisson_solve": ([vp, vp, vp, vp], i),
+        "cans_poisson_solve_noalloc": ([vp, vp, vp, vp], i),
         "cans_poisson_project": ([vp, vp, vp, vp, vp, d, vp], i),
         "cans_poisson_project_ex": ([vp, vp, vp, vp, vp, d, d, d, vp, vp], i),
         "cans_poisson_get_info": ([vp, ctypes.POINTER(CansInfo)], i),
@@ -189,6 +191,12 @@ class Plan:
 
     def solve(self, rhs, p, stream=None) -> None:
         _check(self._lib.cans_poisson_solve(self._h, self._a(rhs), self._a(p), _stream(stream)), "cans_poisson_solve")
+
+    def solve_noalloc(self, rhs, p, stream=None) -> None:
+        """cans_poisson_solve_noalloc: the same solve on the library's fixed
+        scratch (no device allocation)."""
+        _check(self._lib.cans_poisson_solve_noalloc(self._h, self._a(rhs), self._a(p), _stream(stream)),
+               "cans_poisson_solve_noalloc")
 
     def project(self, u, v, w, p, gdt: float, stream=None) -> None:
         """One projection step (``cans_poisson_project``): u, v, w -= gdt G Phi,

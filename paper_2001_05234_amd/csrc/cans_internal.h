@@ -110,6 +110,10 @@ int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const d
                       hipStream_t s);
 int launch_finalize(const Problem &pb, const Work &w, int check, int max_iter, double tol, hipStream_t s);
 int launch_reset(const Problem &pb, const Work &w, hipStream_t s);
+// zero a workspace's info record, flag and z-solve counters (a kernel, so the
+// sequence stays capturable); copy an info record to another
+int launch_clear_work(const Work &w, hipStream_t s);
+int launch_copy_info(const double *src, double *dst, hipStream_t s);
 int launch_mean_rhs(const Problem &pb, const Work &w, hipStream_t s);
 
 int resid_blocks(const Problem &pb);

@@ -292,6 +292,32 @@ int launch_mean_rhs(const Problem &pb, const Work &w, hipStream_t s)
     return check_launch();
 }
 
+__global__ void k_clear_work(double *__restrict__ info, int *__restrict__ flag, unsigned *__restrict__ zctr)
+{
+    const int t = threadIdx.x;
+    if (t < I_SIZE) info[t] = 0.0;
+    if (t == 0) flag[0] = 0;
+    if (zctr && t < 2) zctr[t] = 0u;
+}
+
+__global__ void k_copy_info(const double *__restrict__ src, double *__restrict__ dst)
+{
+    const int t = threadIdx.x;
+    if (t < I_SIZE) dst[t] = src[t];
+}
+
+int launch_clear_work(const Work &w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(64), 0, s, w.info, w.flag, w.zctr);
+    return check_launch();
+}
+
+int launch_copy_info(const double *src, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_info, dim3(1), dim3(64), 0, s, src, dst);
+    return check_launch();
+}
+
 int launch_reset(const Problem &pb, const Work &w, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.info, w.flag);

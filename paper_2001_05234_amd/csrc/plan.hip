@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -379,6 +380,59 @@ int fill_info(const Problem &pb, int precision, cans_info *out)
     return CANS_OK;
 }
 
+// ---- the solve that allocates nothing ------------------------------------
+// The per-solve buffers of cans_poisson_solve_noalloc live in this array.  In
+// host code `scratch` names a host-side stand-in, not device memory: its
+// device address on each GPU comes from hipGetSymbolAddress (scratch_on) and
+// only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CANS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+// device address of the array on device `dev` (current), looked up once
+int scratch_on(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return CANS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CANS_ERR_HIP;
+        g_scratch[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return CANS_OK;
+}
+
+// the workspace of one solve carved from `base` (256-byte aligned pieces),
+// the same pieces build_problem allocates for the plan's own workspace
+int carve_work(const Problem &pb, int precision, unsigned char *base, Work &w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> unsigned char * {
+        unsigned char *p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const size_t N = pb.npts();
+    w = Work{};
+    if (zpart_shape(pb.nz, pb.cyclic != 0).mmax == 0) {
+        w.wc = reinterpret_cast<double *>(take(N * sizeof(double)));
+        w.wd = reinterpret_cast<double *>(take(N * sizeof(double)));
+        if (pb.cyclic) w.wz = reinterpret_cast<double *>(take(N * sizeof(double)));
+    }
+    if (precision == CANS_PREC_FP32_REFINE) {
+        w.a32 = reinterpret_cast<float *>(take(N * sizeof(float)));
+        w.partials = reinterpret_cast<double *>(take(kNP * (size_t)pb.ny * pb.nz * sizeof(double)));
+        w.sums = reinterpret_cast<double *>(take(kNP * 256 * sizeof(double)));
+    }
+    w.info = reinterpret_cast<double *>(take(I_SIZE * sizeof(double)));
+    w.flag = reinterpret_cast<int *>(take(sizeof(int)));
+    w.zctr = reinterpret_cast<unsigned *>(take(2 * sizeof(unsigned)));
+    return off <= (size_t)CANS_NOALLOC_SCRATCH_BYTES ? CANS_OK : CANS_ERR_TOO_LARGE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -405,6 +459,7 @@ const char *cans_status_string(int code)
     case CANS_ERR_ALLOC: return "allocation failed";
     case CANS_ERR_HIP: return "HIP runtime error";
     case CANS_ERR_ALIAS: return "rhs and p alias";
+    case CANS_ERR_TOO_LARGE: return "problem exceeds the fixed scratch of the no-allocation solve";
     default: return "unknown status";
     }
 }
@@ -461,6 +516,25 @@ int cans_poisson_solve(cans_plan_t plan, const double *rhs, double *p, hipStream
     if (plan->opts.precision == CANS_PREC_FP64) return solve_fp64(pb, pb.ws, rhs, p, stream);
     if ((const void *)rhs == (const void *)p) return CANS_ERR_ALIAS;
     return solve_refine(pb, pb.ws, plan->opts, rhs, p, stream);
+}
+
+int cans_poisson_solve_noalloc(cans_plan_t plan, const double *rhs, double *p, hipStream_t stream)
+{
+    if (!plan || !rhs || !p || plan->probs.size() != 1) return CANS_ERR_INVALID_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return CANS_ERR_HIP;
+    if (dev != plan->device) return CANS_ERR_INVALID_ARG;
+    const Problem &pb = plan->probs[0];
+    const int prec = plan->opts.precision;
+    if (prec != CANS_PREC_FP64 && (const void *)rhs == (const void *)p) return CANS_ERR_ALIAS;
+    unsigned char *base = nullptr;
+    CANS_TRY(scratch_on(dev, &base));
+    Work w;
+    CANS_TRY(carve_work(pb, prec, base, w));
+    // the array keeps the previous call's contents: clear what must start at zero
+    CANS_TRY(launch_clear_work(w, stream));
+    CANS_TRY(prec == CANS_PREC_FP64 ? solve_fp64(pb, w, rhs, p, stream) : solve_refine(pb, w, plan->opts, rhs, p, stream));
+    return launch_copy_info(w.info, pb.ws.info, stream);
 }
 
 int cans_poisson_project_ex(cans_plan_t plan, double *u, double *v, double *w, double *p, double gdt, double alpha,
