@@ -108,7 +108,8 @@ int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const d
                       const int *done, hipStream_t s);
 int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done,
                       hipStream_t s);
-int launch_finalize(const Problem &pb, const Work &w, int check, int max_iter, double tol, hipStream_t s);
+// nblk: the block partials the preceding residual kernel wrote
+int launch_finalize(const Problem &pb, const Work &w, int nblk, int check, int max_iter, double tol, hipStream_t s);
 int launch_reset(const Problem &pb, const Work &w, hipStream_t s);
 // zero a workspace's info record, flag and z-solve counters (a kernel, so the
 // sequence stays capturable); copy an info record to another
@@ -116,7 +117,15 @@ int launch_clear_work(const Work &w, hipStream_t s);
 int launch_copy_info(const double *src, double *dst, hipStream_t s);
 int launch_mean_rhs(const Problem &pb, const Work &w, hipStream_t s);
 
-int resid_blocks(const Problem &pb);
+// block partials written by launch_resid_xfwd / launch_resid_norm (at most
+// kNP (ny + 8) nz doubles); plan_resid: their LDS limits (plan time)
+int resid_blocks_xfwd(const Problem &pb);
+int resid_blocks_norm(const Problem &pb);
+int plan_resid(const Problem &pb);
+// LDS bytes the residual+transform kernel needs with x tile g; the largest
+// the plan allows it (tile candidates beyond it are not used)
+size_t resid_xfwd_lds(const Problem &pb, const XGeom &g);
+constexpr size_t kResidLdsMax = 156 * 1024;
 
 // projection step: D u / gdt fused into the forward x transform (FP64, into
 // out), and the correction u -= gdt G phi, p += phi - alpha L_h phi

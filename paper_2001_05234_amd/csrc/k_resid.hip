@@ -4,12 +4,174 @@
 
 namespace cans {
 
+// ---------------------------------------------------------------------------
+// Residual kernels.  A block takes L consecutive rows (x lines) of one plane.
+// Block b belongs to XCD b % 8 (blocks are dispatched round-robin over the
+// eight XCDs); XCD x owns the rows [x H, (x+1) H) of every plane and walks
+// them plane by plane, so the rows above and below a block's rows (y
+// neighbours) and the same rows one plane up and down (z neighbours) are read
+// by the same XCD close in time and come from its L2: each p value reaches
+// HBM about once.  H is ceil(ny/8) rounded up to a multiple of L.
+struct RSlice {
+    int L, H, bpp;   // rows per block, slice height, blocks per plane and slice
+};
+
+static inline RSlice rslice(const Problem &pb, int L)
+{
+    const int h8 = (pb.ny + 7) / 8;
+    const int H = (h8 + L - 1) / L * L;
+    return RSlice{L, H, H / L};
+}
+
+static inline int rslice_blocks(const Problem &pb, const RSlice &rs) { return 8 * pb.nz * rs.bpp; }
+
+// rows of the norm-only kernel (x lines per block)
+static inline int norm_rows(const Problem &pb)
+{
+    (void)pb;
+    return 2;
+}
+
+// The residual r = (f - mf) - L_h p (eq. (poi), plus the plan's shift) of the
+// rows j0 .. j0 + nr - 1 (nr <= 2) of plane k, block-wide, in chunks of
+// kResidChunk points of a row.  Each thread first loads all it needs of the
+// chunk into registers: its kResidU points of the two rows and of the rows
+// just below and above them (by the y ghost rule of the face at a domain
+// boundary: periodic wraps, Neumann mirrors, Dirichlet mirrors with the sign
+// flipped), so every global load is in flight at once.  The rows themselves
+// go to LDS (`rows`, 2 (kResidChunk + 2) doubles) for the x neighbours; the
+// planes above and below and f are loaded after the barrier, again all at
+// once.  The arithmetic per point is lap_point's.  put(l, e, r) receives every
+// residual; acc accumulates the block's partial sums.
+constexpr int kResidU = 4;                       // points of a row per thread and chunk
+constexpr int kResidChunk = kResidU * kThreads;  // 1024
+
+struct RAcc {
+    double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
+};
+
+template <typename Put>
+__device__ void resid_pair(const double *__restrict__ f, const double *__restrict__ p, int k, int j0, int nr,
+                           const LapArgs &la, double mf, double wk, double *rows, Put put, RAcc &acc)
+{
+    const int n = la.nx, ny = la.ny, nz = la.nz;
+    const size_t sy = (size_t)n, sz = (size_t)n * ny;
+    const double *pk = p + sz * k;
+    const int t = (int)threadIdx.x, rs = kResidChunk + 2;
+    // the staged rows: 0 = j0 - 1, 1 = j0, 2 = j0 + 1 (if nr == 2), nr + 1 = above
+    const double *rp[4];
+    double sg[4];
+    for (int l = 0; l < 4; ++l) {
+        int j = j0 + l - 1;
+        if (l == nr + 1) j = j0 + nr;
+        if (l > nr + 1) j = j0 + nr - 1;  // not used
+        sg[l] = 1.0;
+        if (j < 0) {
+            sg[l] = la.bc[2] == CANS_BC_PERIODIC || la.bc[2] == CANS_BC_NEUMANN ? 1.0 : -1.0;
+            j = la.bc[2] == CANS_BC_PERIODIC ? ny - 1 : 0;
+        } else if (j >= ny) {
+            sg[l] = la.bc[3] == CANS_BC_PERIODIC || la.bc[3] == CANS_BC_NEUMANN ? 1.0 : -1.0;
+            j = la.bc[3] == CANS_BC_PERIODIC ? 0 : ny - 1;
+        }
+        rp[l] = pk + sy * j;
+    }
+    const double *zm_pl = k > 0 ? pk - sz : p + sz * (nz - 1);  // wrap plane at a boundary
+    const double *zp_pl = k < nz - 1 ? pk + sz : p;
+    const bool zm_in = k > 0, zp_in = k < nz - 1;
+    const double zaf = la.zaf[k], zcf = la.zcf[k];
+    const double *fk = f + sz * k;
+    for (int e0 = 0; e0 < n; e0 += kResidChunk) {
+        // unconditional loads (indices clamped into the row) so that they
+        // are all issued before the first wait
+        double c[4][kResidU];
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+            for (int u = 0; u < kResidU; ++u) {
+                const int e = e0 + t + u * kThreads;
+                c[l][u] = sg[l] * rp[l][e < n ? e : n - 1];
+            }
+        __syncthreads();  // the previous chunk's reads of `rows` are done
+        // the rows' chunk in LDS, with the x neighbours just outside it
+#pragma unroll
+        for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int u = 0; u < kResidU; ++u) {
+                const int e = e0 + t + u * kThreads;
+                if (e < n) rows[l * rs + 1 + t + u * kThreads] = c[l + 1][u];
+            }
+        if (t < 2 * 2) {
+            // x neighbours just outside the chunk: the next chunk's first
+            // point, or the ghost after the row's last point
+            const int l = t >> 1;
+            if (l < nr) {
+                const double *row = rp[l + 1];
+                if ((t & 1) == 0)
+                    rows[l * rs] = e0 > 0 ? row[e0 - 1] : ghost(la.bc[0], row[0], row[n - 1]);
+                else if (e0 + kResidChunk < n)
+                    rows[l * rs + kResidChunk + 1] = row[e0 + kResidChunk];
+                else
+                    rows[l * rs + 1 + (n - e0)] = ghost(la.bc[1], row[n - 1], row[0]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            if (l >= nr) break;
+            // the planes above and below and f of the row's points, all in flight at once
+            double zmv[kResidU], zpv[kResidU], fvv[kResidU];
+            const size_t ro = sy * (j0 + l);
+#pragma unroll
+            for (int u = 0; u < kResidU; ++u) {
+                const int e = e0 + t + u * kThreads;
+                const size_t o = ro + (e < n ? e : 0);
+                zmv[u] = zm_pl[o];
+                zpv[u] = zp_pl[o];
+                fvv[u] = fk[o];
+            }
+#pragma unroll
+            for (int u = 0; u < kResidU; ++u) {
+                const int e = e0 + t + u * kThreads;
+                const int q = 1 + t + u * kThreads;
+                if (e < n) {
+                    const double cc = c[l + 1][u];
+                    const double xm = rows[l * rs + q - 1], xp = rows[l * rs + q + 1];
+                    const double ym = c[l][u], yp = c[l + 2][u];
+                    const double zm = zm_in ? zmv[u] : ghost(la.bc[4], cc, zmv[u]);
+                    const double zp = zp_in ? zpv[u] : ghost(la.bc[5], cc, zpv[u]);
+                    const double fv = fvv[u] - mf;
+                    const double lap = (xm - 2.0 * cc + xp) * la.idx2 + (ym - 2.0 * cc + yp) * la.idy2 +
+                                       zcf * (zp - cc) - zaf * (cc - zm) + la.shift * cc;
+                    const double r = fv - lap;
+                    put(l, e, r);
+                    acc.srr += r * r;
+                    acc.sff += fv * fv;
+                    acc.rmax = fmax(acc.rmax, fabs(r));
+                    acc.fmx = fmax(acc.fmx, fabs(fv));
+                    acc.spw += wk * cc;
+                }
+            }
+        }
+    }
+    __syncthreads();  // `rows` free for the caller
+}
+
+// block -> (plane, first row, rows in the plane); lv = 0 for a block beyond the grid
+static __device__ inline void rslice_of(unsigned b, int H, int bpp, int L, int ny, int nz, int &k, int &j0, int &lv)
+{
+    const int x = (int)(b % 8), i = (int)(b / 8);
+    k = i / bpp;
+    j0 = x * H + (i % bpp) * L;
+    lv = (k < nz && j0 < ny) ? min(L, ny - j0) : 0;
+}
+
+// The residual fused with the forward x transform of its rows (FP32 out);
 // block partials: sums of |r|^2, |f - mean|^2, dzf p; maxima of |r|, |f - mean|.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restrict__ f,
-                                                         const double *__restrict__ p, float *out,
-                                                         long nlines, XGeom g,
-                                                         const cx<float> *__restrict__ tw, LapArgs la,
+                                                         const double *__restrict__ p, float *out, int H, int bpp,
+                                                         XGeom g, int rows_off, const cx<float> *__restrict__ tw,
+                                                         LapArgs la,
                                                          const double *__restrict__ dzf,
                                                          const double *__restrict__ info,
                                                          double *__restrict__ partials,
@@ -18,89 +180,48 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
     if (*done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile<AX_X, float> tile{reinterpret_cast<cx<float> *>(smem), g.L, g.RS, g.psh};
-    const int n = g.n, ny = la.ny;
-    const long line0 = (long)blockIdx.x * g.L;
-    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
-    const double mf = info[I_REMOVED];
-    double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
-    // residual of the tile's lines into LDS (coalesced, each point once)
-    auto one = [&](int e, int l, long line, int j, int k) {
-        const size_t gi = (size_t)line * n + e;
-        const double fv = f[gi] - mf;
-        const double r = fv - lap_point(p, e, j, k, la);
-        srr += r * r;
-        sff += fv * fv;
-        rmax = fmax(rmax, fabs(r));
-        fmx = fmax(fmx, fabs(fv));
-        spw += dzf[k] * p[gi];
-        tile_real(tile, e, l) = (float)r;
-    };
-    if (n % kThreads == 0) {
-        // whole lines per thread group: line, j and k are uniform per pass
-        for (int l = 0; l < g.L; ++l) {
-            const long line = line0 + l;
-            if (line < nlines) {
-                const int k = line_level(line, line0, k0, j0, ny), j = (int)(line - (long)k * ny);
-                for (int e = threadIdx.x; e < n; e += kThreads) one(e, l, line, j, k);
-            } else {
-                for (int e = threadIdx.x; e < n; e += kThreads) tile_real(tile, e, l) = 0.f;
-            }
-        }
-    } else {
-        for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
-            const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
-            const long line = line0 + l;
-            if (line < nlines) {
-                const int k = line_level(line, line0, k0, j0, ny), j = (int)(line - (long)k * ny);
-                one(e, l, line, j, k);
-            } else {
-                tile_real(tile, e, l) = 0.f;
-            }
-        }
+    double *rows = reinterpret_cast<double *>(smem + rows_off);  // after the transform tile
+    const int n = g.n, L = g.L;
+    int k, j0, lv;
+    rslice_of(blockIdx.x, H, bpp, L, la.ny, la.nz, k, j0, lv);
+    RAcc acc;
+    if (lv > 0) {
+        const double mf = info[I_REMOVED];
+        for (int l0 = 0; l0 < lv; l0 += 2)
+            resid_pair(f, p, k, j0 + l0, min(2, lv - l0), la, mf, dzf[k], rows,
+                       [&](int l, int e, double r) { tile_real(tile, e, l0 + l) = (float)r; }, acc);
+        for (int idx = threadIdx.x; idx < (L - lv) * n; idx += kThreads)
+            tile_real(tile, idx % n, lv + idx / n) = 0.f;
+        __syncthreads();
+        const long line0 = (long)k * la.ny + j0;
+        auto src = [&](int e, int l) -> float { return tile_real(tile, e, l); };
+        auto put = [&](int q, int l, float v) {
+            if (l < lv) out[(size_t)(line0 + l) * n + q] = v;
+        };
+        tile_transform<KIND, true, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
     }
-    __syncthreads();
-    auto src = [&](int e, int l) -> float { return tile_real(tile, e, l); };
-    auto put = [&](int q, int l, float v) {
-        const long line = line0 + l;
-        if (line < nlines) out[(size_t)line * n + q] = v;
-    };
-    tile_transform<KIND, true, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
-    put_partial(partials, blockIdx.x, srr, sff, spw, rmax, fmx);
+    put_partial(partials, blockIdx.x, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
 }
 
 // Residual norms only (the check after a correction): the same block
-// partials as k_resid_xfwd over lines_per_block lines.
+// partials over norm_rows() rows a block.
 __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restrict__ f,
-                                                         const double *__restrict__ p, long nlines,
-                                                         int lines_per_block, LapArgs la,
-                                                         const double *__restrict__ dzf,
+                                                         const double *__restrict__ p, int H, int bpp, int L,
+                                                         LapArgs la, const double *__restrict__ dzf,
                                                          const double *__restrict__ info,
                                                          double *__restrict__ partials,
                                                          const int *__restrict__ done)
 {
     if (*done) return;
-    const int n = la.nx, ny = la.ny;
-    const long line0 = (long)blockIdx.x * lines_per_block;
-    const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
-    const double mf = info[I_REMOVED];
-    double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
-    for (int l = 0; l < lines_per_block; ++l) {
-        const long line = line0 + l;
-        if (line >= nlines) break;
-        const int k = line_level(line, line0, k0, j0, ny), j = (int)(line - (long)k * ny);
-        const double wk = dzf[k];
-        for (int e = threadIdx.x; e < n; e += kThreads) {
-            const size_t gi = (size_t)line * n + e;
-            const double fv = f[gi] - mf;
-            const double r = fv - lap_point(p, e, j, k, la);
-            srr += r * r;
-            sff += fv * fv;
-            rmax = fmax(rmax, fabs(r));
-            fmx = fmax(fmx, fabs(fv));
-            spw += wk * p[gi];
-        }
-    }
-    put_partial(partials, blockIdx.x, srr, sff, spw, rmax, fmx);
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *rows = reinterpret_cast<double *>(smem);
+    int k, j0, lv;
+    rslice_of(blockIdx.x, H, bpp, L, la.ny, la.nz, k, j0, lv);
+    RAcc acc;
+    for (int l0 = 0; l0 < lv; l0 += 2)
+        resid_pair(f, p, k, j0 + l0, min(2, lv - l0), la, info[I_REMOVED], dzf[k], rows, [](int, int, double) {},
+                   acc);
+    put_partial(partials, blockIdx.x, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
 }
 
 // First level of the block-partial reductions: block b reduces its contiguous
@@ -222,12 +343,13 @@ __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ 
 }
 
 
-int resid_blocks(const Problem &pb)
+int resid_blocks_xfwd(const Problem &pb)
 {
-    const long nlines = (long)pb.ny * pb.nz;
-    const int L = pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L;
-    return (int)((nlines + L - 1) / L);
+    if (pb.ax.dense) return (int)dense_grid(pb).x;
+    return rslice_blocks(pb, rslice(pb, pb.ax.gx32[1].L));
 }
+
+int resid_blocks_norm(const Problem &pb) { return rslice_blocks(pb, rslice(pb, norm_rows(pb))); }
 
 int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out,
                       const int *done, hipStream_t s)
@@ -239,11 +361,13 @@ int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const d
         return check_launch();
     }
     const XGeom &g = pb.ax.gx32[1];
-    const long nlines = (long)pb.ny * pb.nz;
-    const dim3 grid((unsigned)resid_blocks(pb));
-    const size_t sh = tile_lds(AX_X, g, sizeof(float));
+    const RSlice rs = rslice(pb, g.L);
+    const size_t off = (tile_lds(AX_X, g, sizeof(float)) + 15) / 16 * 16;
+    const size_t sh = resid_xfwd_lds(pb, g);
+    if (sh > kResidLdsMax) return CANS_ERR_UNSUPPORTED;
+    const dim3 grid((unsigned)rslice_blocks(pb, rs));
     CANS_KIND_SWITCH(pb.ax.kind,
-        hipLaunchKernelGGL(k_resid_xfwd<KD>, grid, dim3(kThreads), sh, s, f, p, out, nlines, g,
+        hipLaunchKernelGGL(k_resid_xfwd<KD>, grid, dim3(kThreads), sh, s, f, p, out, rs.H, rs.bpp, g, (int)off,
                            pb.ax.d_tw32, lapargs(pb), pb.d_dzf, w.info, w.partials, done));
     return check_launch();
 }
@@ -251,20 +375,44 @@ int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const d
 int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done,
                       hipStream_t s)
 {
-    const long nlines = (long)pb.ny * pb.nz;
-    hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)resid_blocks(pb)), dim3(kThreads), 0, s, f, p, nlines,
-                       pb.ax.dense ? kDenseLines : pb.ax.gx32[1].L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
+    const RSlice rs = rslice(pb, norm_rows(pb));
+    const size_t sh = (size_t)2 * (kResidChunk + 2) * sizeof(double);
+    hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)rslice_blocks(pb, rs)), dim3(kThreads), sh, s, f, p, rs.H,
+                       rs.bpp, rs.L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
     return check_launch();
+}
+
+// LDS of the residual+transform kernel for x tile geometry g: the FP32
+// transform tile, then the FP64 rows
+size_t resid_xfwd_lds(const Problem &pb, const XGeom &g)
+{
+    return (tile_lds(AX_X, g, sizeof(float)) + 15) / 16 * 16 + (size_t)2 * (kResidChunk + 2) * sizeof(double);
+}
+
+// dynamic LDS beyond the default 64 KiB for the residual kernels: up to the
+// 160 KiB of a CU less each kernel's static LDS (its reductions)
+int plan_resid(const Problem &pb)
+{
+    const void *ks[] = {(const void *)k_resid_xfwd<K_P>, (const void *)k_resid_xfwd<K_NN>,
+                        (const void *)k_resid_xfwd<K_DD>, (const void *)k_resid_xfwd<K_ND>,
+                        (const void *)k_resid_xfwd<K_DN>, (const void *)k_resid_norm};
+    (void)pb;
+    for (const void *k : ks) {
+        hipFuncAttributes fa;
+        if (hipFuncGetAttributes(&fa, k) != hipSuccess) return CANS_ERR_HIP;
+        const int dyn = (int)(kResidLdsMax - fa.sharedSizeBytes);
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) return CANS_ERR_HIP;
+    }
+    return CANS_OK;
 }
 
 // Up to this many block partials the last-level kernel reads them directly
 // (one launch per check instead of two; small problems are launch-bound).
 constexpr int kDirectReduce = 4096;
 
-int launch_finalize(const Problem &pb, const Work &w, int check, int max_iter, double tol, hipStream_t s)
+int launch_finalize(const Problem &pb, const Work &w, int nblk, int check, int max_iter, double tol, hipStream_t s)
 {
     const double inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
-    const int nblk = resid_blocks(pb);
     if (nblk <= kDirectReduce) {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, w.partials, nblk, check, max_iter, tol,
                            inv_wvol, pb.singular, w.info, w.flag);

@@ -191,7 +191,12 @@ int autotune(cans_plan_s *pl, Problem &pb)
             tune(pb.ay.gy64[0], AX_Y, pb.ny, 8, [&] { return launch_y_f64(pb, false, s64, s64, st); });
         } else {
             if (!pb.ax.dense) {
-                tune(pb.ax.gx32[1], AX_X, pb.nx, 4, [&] { return launch_x_fwd_32(pb, pb.ws, s64, pb.ws.a32, nullptr, st); });
+                // the forward tile is also the residual kernel's: only candidates
+                // whose residual LDS fits
+                tune(pb.ax.gx32[1], AX_X, pb.nx, 4, [&] {
+                    if (resid_xfwd_lds(pb, pb.ax.gx32[1]) > kResidLdsMax) return (int)CANS_ERR_UNSUPPORTED;
+                    return launch_x_fwd_32(pb, pb.ws, s64, pb.ws.a32, nullptr, st);
+                });
                 tune(pb.ax.gx32[0], AX_X, pb.nx, 4,
                      [&] { return launch_x_inv_32(pb, pb.ws, pb.ws.a32, s64, false, nullptr, st); });
             }
@@ -234,6 +239,7 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     CANS_TRY(upload(pl, &pb.d_zcf, cf.data(), nz));
     CANS_TRY(upload(pl, &pb.d_dzf, pb.dzf.data(), nz));
     CANS_TRY(plan_zpipe(pb));
+    CANS_TRY(plan_resid(pb));
     // workspace of the plain elimination (nz beyond the register-resident
     // partitioned solve): multipliers and modified rhs
     const size_t N = pb.npts();
@@ -244,8 +250,9 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
     }
     if (pl->opts.precision == CANS_PREC_FP32_REFINE) {
         CANS_TRY(alloc(pl, &pb.ws.a32, N));
-        // block partial sums: enough for any tile shape (one line per block)
-        CANS_TRY(alloc(pl, &pb.ws.partials, kNP * (size_t)pb.ny * pb.nz));
+        // block partial sums: enough for any tile shape (one row per block,
+        // rows in eight slices of every plane)
+        CANS_TRY(alloc(pl, &pb.ws.partials, kNP * (size_t)(pb.ny + 8) * pb.nz));
         CANS_TRY(alloc(pl, &pb.ws.sums, kNP * 256));
     }
     if (pl->opts.autotune) CANS_TRY(autotune(pl, pb));
@@ -343,7 +350,7 @@ int solve_refine(const Problem &pb, const Work &w, const cans_opts &o, const dou
     CANS_TRY(launch_x_inv_32(pb, w, w.a32, p, false, nullptr, s));
     // check 0, fused with the forward x transform the first correction needs
     CANS_TRY(launch_resid_xfwd(pb, w, rhs, p, w.a32, done, s));
-    CANS_TRY(launch_finalize(pb, w, 0, o.max_iter, o.tol, s));
+    CANS_TRY(launch_finalize(pb, w, resid_blocks_xfwd(pb), 0, o.max_iter, o.tol, s));
     for (int it = 1; it <= o.max_iter; ++it) {
         CANS_TRY(launch_y_32(pb, true, w.a32, done, s));
         CANS_TRY(launch_zsolve_32(pb, w, w.a32, nullptr, done, s));
@@ -352,7 +359,7 @@ int solve_refine(const Problem &pb, const Work &w, const cans_opts &o, const dou
         // check `it` without a transform; only if it fails is the residual
         // formed again with its forward x transform for the next correction
         CANS_TRY(launch_resid_norm(pb, w, rhs, p, done, s));
-        CANS_TRY(launch_finalize(pb, w, it, o.max_iter, o.tol, s));
+        CANS_TRY(launch_finalize(pb, w, resid_blocks_norm(pb), it, o.max_iter, o.tol, s));
         if (it < o.max_iter) CANS_TRY(launch_resid_xfwd(pb, w, rhs, p, w.a32, done, s));
     }
     return CANS_OK;
@@ -424,7 +431,7 @@ int carve_work(const Problem &pb, int precision, unsigned char *base, Work &w)
     }
     if (precision == CANS_PREC_FP32_REFINE) {
         w.a32 = reinterpret_cast<float *>(take(N * sizeof(float)));
-        w.partials = reinterpret_cast<double *>(take(kNP * (size_t)pb.ny * pb.nz * sizeof(double)));
+        w.partials = reinterpret_cast<double *>(take(kNP * (size_t)(pb.ny + 8) * pb.nz * sizeof(double)));
         w.sums = reinterpret_cast<double *>(take(kNP * 256 * sizeof(double)));
     }
     w.info = reinterpret_cast<double *>(take(I_SIZE * sizeof(double)));
