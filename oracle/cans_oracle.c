@@ -36,12 +36,20 @@
  *
  * Layout: every 3-D field is x fastest, a[i + nx*(j + ny*k)].
  * Boundary codes per face: 0 = periodic, 1 = Neumann, 2 = Dirichlet;
- * bc[6] = {x-, x+, y-, y+, z-, z+}.  Code 3 (z only, on both z faces) is
- * Dirichlet for a field located on the z faces rather than the cell centres,
- * as the wall-normal velocity of a channel is in the implicit diffusion
- * steps of eq. (up_id_2): the unknowns are the nz interior faces of a grid
- * of nz+1 cells, dzf then holds those nz+1 cell widths, and the field is
- * zero on the two wall faces.
+ * bc[6] = {x-, x+, y-, y+, z-, z+}.  Codes 3 and 4 describe a field that
+ * lives on the cell faces of an axis instead of the cell centres (a velocity
+ * component along its own direction, as in the implicit diffusion steps of
+ * eq. (up_id_2)); both ends of such an axis carry 3 or 4:
+ *   3  Dirichlet on the boundary face: the field is zero there and the face
+ *      is not an unknown;
+ *   4  Neumann on the boundary face: the face is an unknown, and the zero
+ *      derivative across it mirrors the field about it (w_{-1} = w_1).
+ * Along x or y with C cells of width h the unknowns are therefore the C-1
+ * interior faces (3,3), all C+1 faces (4,4), or the C faces other than the
+ * Dirichlet one ((3,4), (4,3)); the operator is (w_{i-1} - 2 w_i +
+ * w_{i+1})/h^2.  Along z only (3,3) is allowed: the unknowns are the nz
+ * interior faces of a grid of nz+1 cells, dzf then holds those nz+1 cell
+ * widths (stretched), and the operator is the flux form of zcoef_real.
  */
 #include <math.h>
 #include <omp.h>
@@ -62,21 +70,28 @@ typedef double REAL;
 #define SYM(name) name
 #endif
 
-enum { BC_P = 0, BC_N = 1, BC_D = 2, BC_DF = 3 };
+enum { BC_P = 0, BC_N = 1, BC_D = 2, BC_DF = 3, BC_NF = 4 };
 
 /* Threads of the OpenMP loops below (for timing the oracle on n cores), and
  * the number a parallel loop will use. */
 void SYM(oracle_set_threads)(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int SYM(oracle_threads)(void) { return omp_get_max_threads(); }
-/* transform kinds of one axis, named by the (lower, upper) boundary pair */
-enum { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4, K_FD = 5 };
+/* transform kinds of one axis, named by the (lower, upper) boundary pair;
+ * K_FD .. K_FND are the face-located pairs (3,3), (4,4), (3,4), (4,3) */
+enum { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4, K_FD = 5, K_FN = 6, K_FDN = 7, K_FND = 8 };
+
+static int is_face(int code) { return code == BC_DF || code == BC_NF; }
 
 /* Axis kind from its two face conditions; -1 when the pair is invalid
- * (periodic must be paired with periodic, a face-located field has code 3 at
- * both ends).  K_FD (face-located Dirichlet) is a z kind only. */
+ * (periodic must be paired with periodic, a face-located field has code 3
+ * or 4 at both ends). */
 int SYM(oracle_axis_kind)(int lo, int hi)
 {
-    if (lo == BC_DF || hi == BC_DF) return (lo == BC_DF && hi == BC_DF) ? K_FD : -1;
+    if (is_face(lo) || is_face(hi)) {
+        if (!is_face(lo) || !is_face(hi)) return -1;
+        if (lo == BC_DF) return hi == BC_DF ? K_FD : K_FDN;
+        return hi == BC_NF ? K_FN : K_FND;
+    }
     if (lo == BC_P || hi == BC_P) return (lo == BC_P && hi == BC_P) ? K_P : -1;
     if (lo == BC_N && hi == BC_N) return K_NN;
     if (lo == BC_D && hi == BC_D) return K_DD;
@@ -86,9 +101,14 @@ int SYM(oracle_axis_kind)(int lo, int hi)
 }
 
 /*
- * Eigenvector rows T[q][i] (row-major, T[q*n+i]) and eigenvalues mu[q] of the
- * 1-D operator (p_{i-1} - 2 p_i + p_{i+1}) with the ghost rules above
- * (unit spacing).  These are the discrete transforms F of Section 2:
+ * Eigenvector rows and eigenvalues mu[q] of the 1-D operator (p_{i-1} - 2 p_i
+ * + p_{i+1}) with the ghost rules above (unit spacing).  These are the
+ * discrete transforms F of Section 2.  R[q][i] (row-major, R[q*n+i]) is the
+ * q-th eigenvector of the operator (A R_q = mu_q R_q), T[q][i] = w_i R[q][i]
+ * the q-th row of the forward transform (T A = diag(mu) T), with w_i = 1/2
+ * on an unknown that sits on a Neumann boundary face (codes 4) and 1
+ * elsewhere, so that T is the left eigenvector matrix (w A is symmetric).
+ * Cell-centred kinds (w = 1, T = R):
  *   P : real DFT, stored in the order
  *       q=0: 1,  q=1: (-1)^i,  q=2l: cos(2 pi l i/n),  q=2l+1: -sin(2 pi l i/n)
  *       (l = 1..n/2-1; for odd n the (-1)^i row does not exist and the pairs
@@ -97,8 +117,22 @@ int SYM(oracle_axis_kind)(int lo, int hi)
  *   DD: sin(pi (q+1)(i+1/2)/n)         DST-II,  mu = -4 sin^2(pi (q+1)/(2n));
  *   ND: cos(pi (2q+1)(2i+1)/(4n))      DCT-IV,  mu = -4 sin^2(pi (2q+1)/(4n));
  *   DN: sin(pi (2q+1)(2i+1)/(4n))      DST-IV,  mu as ND.
+ * Face-located kinds (unknown i on a face; R, and the weighted T):
+ *   FD : sin(pi (q+1)(i+1)/(n+1))      DST-I,   mu = -4 sin^2(pi (q+1)/(2(n+1)));
+ *   FN : cos(pi q i/(n-1))             DCT-I,   mu = -4 sin^2(pi q/(2(n-1))),
+ *        w_0 = w_{n-1} = 1/2 (n >= 2);
+ *   FDN: sin(pi (2q+1)(i+1)/(2n))      DST-III-type, mu = -4 sin^2(pi (2q+1)/(4n)),
+ *        w_{n-1} = 1/2;
+ *   FND: cos(pi (2q+1) i/(2n))         DCT-III-type, mu as FDN, w_0 = 1/2.
  */
-static void eigen_real(int kind, int n, REAL *T, REAL *mu)
+static REAL face_weight(int kind, int n, int i)
+{
+    if ((kind == K_FN && (i == 0 || i == n - 1)) || (kind == K_FDN && i == n - 1) || (kind == K_FND && i == 0))
+        return (REAL)0.5;
+    return 1;
+}
+
+static void eigen_real(int kind, int n, REAL *T, REAL *R, REAL *mu)
 {
     for (int q = 0; q < n; ++q) {
         REAL wav = 0; /* the angle whose sin^2 gives mu */
@@ -121,8 +155,25 @@ static void eigen_real(int kind, int n, REAL *T, REAL *mu)
             case K_DD: v = RSIN(RPI * (REAL)(q + 1) * x / (REAL)n); wav = RPI * (REAL)(q + 1) / (2 * (REAL)n); break;
             case K_ND: v = RCOS(RPI * (REAL)(2 * q + 1) * (2 * x) / (4 * (REAL)n)); wav = RPI * (REAL)(2 * q + 1) / (4 * (REAL)n); break;
             case K_DN: v = RSIN(RPI * (REAL)(2 * q + 1) * (2 * x) / (4 * (REAL)n)); wav = RPI * (REAL)(2 * q + 1) / (4 * (REAL)n); break;
+            case K_FD:
+                v = RSIN(RPI * (REAL)(q + 1) * (REAL)(i + 1) / (REAL)(n + 1));
+                wav = RPI * (REAL)(q + 1) / (2 * (REAL)(n + 1));
+                break;
+            case K_FN:
+                v = RCOS(RPI * (REAL)q * (REAL)i / (REAL)(n - 1));
+                wav = RPI * (REAL)q / (2 * (REAL)(n - 1));
+                break;
+            case K_FDN:
+                v = RSIN(RPI * (REAL)(2 * q + 1) * (REAL)(i + 1) / (2 * (REAL)n));
+                wav = RPI * (REAL)(2 * q + 1) / (4 * (REAL)n);
+                break;
+            case K_FND:
+                v = RCOS(RPI * (REAL)(2 * q + 1) * (REAL)i / (2 * (REAL)n));
+                wav = RPI * (REAL)(2 * q + 1) / (4 * (REAL)n);
+                break;
             }
-            T[(size_t)q * n + i] = v;
+            if (R) R[(size_t)q * n + i] = v;
+            T[(size_t)q * n + i] = face_weight(kind, n, i) * v;
         }
         REAL s = RSIN(wav);
         mu[q] = -4 * s * s;
@@ -132,15 +183,24 @@ static void eigen_real(int kind, int n, REAL *T, REAL *mu)
 void SYM(oracle_eigen)(int kind, int n, double *T, double *mu)
 {
     REAL *Tr = malloc(sizeof(REAL) * (size_t)n * n), *mr = malloc(sizeof(REAL) * n);
-    eigen_real(kind, n, Tr, mr);
+    eigen_real(kind, n, Tr, NULL, mr);
     for (size_t e = 0; e < (size_t)n * n; ++e) T[e] = (double)Tr[e];
     for (int q = 0; q < n; ++q) mu[q] = (double)mr[q];
     free(Tr); free(mr);
 }
 
 /* Index of the constant (zero-eigenvalue) row of an axis, or -1 if none.
- * Only P and NN have one, and it is row 0 in both orders above. */
-static int zero_row(int kind) { return (kind == K_P || kind == K_NN) ? 0 : -1; }
+ * P, NN and FN have one, and it is row 0 in every order above. */
+static int zero_row(int kind) { return (kind == K_P || kind == K_NN || kind == K_FN) ? 0 : -1; }
+
+/* An x or y axis of n unknowns: a valid kind, and at least two unknowns when
+ * one of its ends is a Neumann face (the mirror needs the second face). */
+static int axis_ok(int kind, int n)
+{
+    if (kind < 0) return 0;
+    if (kind == K_FN || kind == K_FDN || kind == K_FND) return n >= 2;
+    return 1;
+}
 
 /*
  * Tridiagonal coefficients of the z operator, conservative form
@@ -162,7 +222,8 @@ static int zero_row(int kind) { return (kind == K_P || kind == K_NN) ? 0 : -1; }
  */
 static int zcoef_real(int nz, int lo, int hi, const double *dzf, REAL *a, REAL *b, REAL *c)
 {
-    if (SYM(oracle_axis_kind)(lo, hi) < 0) return -1;
+    int kz = SYM(oracle_axis_kind)(lo, hi);
+    if (kz < 0 || kz > K_FD) return -1;  /* of the face-located pairs z takes (3,3) only */
     if (lo == BC_DF) {
         for (int k = 0; k < nz; ++k) {
             REAL below = dzf[k], above = dzf[k + 1], cv = (below + above) / 2;
@@ -289,16 +350,22 @@ static void apply_along(int axis, int nx, int ny, int nz, const REAL *M, const R
     }
 }
 
-/* Forward matrix T and its inverse T^{-1} = T^T diag(1/|row_q|^2); the row
- * norms come from diag(T T^T), computed by a plain sum. */
+/* Forward matrix T and its inverse T^{-1}[i][q] = R[q][i] / (T_q . R_q):
+ * the left and right eigenvectors of one operator are biorthogonal
+ * (T_q . R_p = 0 for mu_q != mu_p; the repeated eigenvalues of P come in
+ * sin/cos pairs, orthogonal too), so T R^T is diagonal and its diagonal,
+ * computed by a plain sum, normalises the inverse.  With w = 1 (the
+ * cell-centred kinds) this is T^T diag(1/|row_q|^2). */
 static void forward_inverse(int kind, int n, REAL *T, REAL *Ti, REAL *mu)
 {
-    eigen_real(kind, n, T, mu);
+    REAL *R = malloc(sizeof(REAL) * (size_t)n * n);
+    eigen_real(kind, n, T, R, mu);
     for (int q = 0; q < n; ++q) {
         REAL nn = 0;
-        for (int i = 0; i < n; ++i) nn += T[(size_t)q * n + i] * T[(size_t)q * n + i];
-        for (int i = 0; i < n; ++i) Ti[(size_t)i * n + q] = T[(size_t)q * n + i] / nn;
+        for (int i = 0; i < n; ++i) nn += T[(size_t)q * n + i] * R[(size_t)q * n + i];
+        for (int i = 0; i < n; ++i) Ti[(size_t)i * n + q] = R[(size_t)q * n + i] / nn;
     }
+    free(R);
 }
 
 static REAL *to_real(const double *v, size_t n)
@@ -343,11 +410,16 @@ static int spectral_solve_real(int nx, int ny, int nz, const int bc[6], double d
 {
     int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
     int kz = SYM(oracle_axis_kind)(bc[4], bc[5]);
-    if (kx < 0 || ky < 0 || kz < 0 || kx == K_FD || ky == K_FD) return -1;
+    if (!axis_ok(kx, nx) || !axis_ok(ky, ny) || kz < 0 || kz > K_FD) return -1;
+    /* a face-located Neumann pair (DCT-I) has a constant mode too; a problem
+     * it would make singular is not defined here */
+    if ((kz == K_P || kz == K_NN) && shift == 0.0 && zero_row(kx) >= 0 && zero_row(ky) >= 0 &&
+        (kx == K_FN || ky == K_FN))
+        return -1;
     REAL *T = malloc(sizeof(REAL) * ((size_t)nx * nx + (size_t)ny * ny));
     REAL *mux = malloc(sizeof(REAL) * (nx + ny)), *muy = mux + nx;
-    eigen_real(kx, nx, T, mux);
-    eigen_real(ky, ny, T + (size_t)nx * nx, muy);
+    eigen_real(kx, nx, T, NULL, mux);
+    eigen_real(ky, ny, T + (size_t)nx * nx, NULL, muy);
     REAL *za = malloc(sizeof(REAL) * 3 * nz), *zb = za + nz, *zc = za + 2 * nz;
     zcoef_real(nz, bc[4], bc[5], dzf, za, zb, zc);
     int zx = zero_row(kx), zy = zero_row(ky);
@@ -435,7 +507,11 @@ int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double
                       const double *dzf, double shift, const double *f, double *p, double *info)
 {
     int kx = SYM(oracle_axis_kind)(bc[0], bc[1]), ky = SYM(oracle_axis_kind)(bc[2], bc[3]);
-    if (kx < 0 || ky < 0 || kx == K_FD || ky == K_FD || SYM(oracle_axis_kind)(bc[4], bc[5]) < 0) return -1;
+    int kz = SYM(oracle_axis_kind)(bc[4], bc[5]);
+    if (!axis_ok(kx, nx) || !axis_ok(ky, ny) || kz < 0 || kz > K_FD) return -1;
+    if ((kz == K_P || kz == K_NN) && shift == 0.0 && zero_row(kx) >= 0 && zero_row(ky) >= 0 &&
+        (kx == K_FN || ky == K_FN))
+        return -1;
     size_t N = (size_t)nx * ny * nz;
     REAL *Tx = malloc(sizeof(REAL) * (size_t)nx * nx), *Tix = malloc(sizeof(REAL) * (size_t)nx * nx);
     REAL *Ty = malloc(sizeof(REAL) * (size_t)ny * ny), *Tiy = malloc(sizeof(REAL) * (size_t)ny * ny);
@@ -457,7 +533,9 @@ int SYM(oracle_solve)(int nx, int ny, int nz, const int bc[6], double dx, double
 /*
  * out = L_h p + shift p, the 7-point operator of eq. (poi) with the z part
  * in the conservative form above and the ghost rules of each face (a
- * face-located z field: the form of zcoef_real, zero on the wall faces).
+ * face-located z field: the form of zcoef_real, zero on the wall faces; a
+ * face-located x or y field: the rules of codes 3 and 4 in the header).
+ * Boundary codes are taken as given (x and y need nx, ny >= 2 for code 4).
  */
 void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, double dy,
                          const double *dzf, double shift, const double *p, double *out)
@@ -485,10 +563,16 @@ void SYM(oracle_apply_L)(int nx, int ny, int nz, const int bc[6], double dx, dou
             REAL c0 = P3(i, j, k);
             /* neighbour value through the ghost rule of a face */
             REAL xm, xp, ym, yp, zm, zp;
-            xm = i > 0 ? P3(i - 1, j, k) : bc[0] == BC_P ? P3(nx - 1, j, k) : bc[0] == BC_N ? c0 : -c0;
-            xp = i < nx - 1 ? P3(i + 1, j, k) : bc[1] == BC_P ? P3(0, j, k) : bc[1] == BC_N ? c0 : -c0;
-            ym = j > 0 ? P3(i, j - 1, k) : bc[2] == BC_P ? P3(i, ny - 1, k) : bc[2] == BC_N ? c0 : -c0;
-            yp = j < ny - 1 ? P3(i, j + 1, k) : bc[3] == BC_P ? P3(i, 0, k) : bc[3] == BC_N ? c0 : -c0;
+            /* x and y: a face-located field is zero beyond a Dirichlet face
+             * (code 3) and mirrored about a Neumann face it sits on (code 4) */
+            xm = i > 0 ? P3(i - 1, j, k) : bc[0] == BC_P ? P3(nx - 1, j, k) : bc[0] == BC_N ? c0
+                 : bc[0] == BC_DF ? 0 : bc[0] == BC_NF ? P3(1, j, k) : -c0;
+            xp = i < nx - 1 ? P3(i + 1, j, k) : bc[1] == BC_P ? P3(0, j, k) : bc[1] == BC_N ? c0
+                 : bc[1] == BC_DF ? 0 : bc[1] == BC_NF ? P3(nx - 2, j, k) : -c0;
+            ym = j > 0 ? P3(i, j - 1, k) : bc[2] == BC_P ? P3(i, ny - 1, k) : bc[2] == BC_N ? c0
+                 : bc[2] == BC_DF ? 0 : bc[2] == BC_NF ? P3(i, 1, k) : -c0;
+            yp = j < ny - 1 ? P3(i, j + 1, k) : bc[3] == BC_P ? P3(i, 0, k) : bc[3] == BC_N ? c0
+                 : bc[3] == BC_DF ? 0 : bc[3] == BC_NF ? P3(i, ny - 2, k) : -c0;
             zm = k > 0 ? P3(i, j, k - 1) : bc[4] == BC_P ? P3(i, j, nz - 1) : bc[4] == BC_N ? c0
                  : bc[4] == BC_DF ? 0 : -c0;
             zp = k < nz - 1 ? P3(i, j, k + 1) : bc[5] == BC_P ? P3(i, j, 0) : bc[5] == BC_N ? c0

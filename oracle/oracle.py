@@ -11,9 +11,14 @@ x and y, Gauss elimination (Thomas) along z, inverse transforms.
 
 Fields are numpy float64 arrays of shape (nz, ny, nx) (x fastest).
 Boundary codes: 0 periodic, 1 Neumann, 2 Dirichlet; bc = (x-, x+, y-, y+, z-, z+).
-Code 3 on both z faces: Dirichlet for a field on the z faces (the unknowns are
-the nz interior faces of an (nz+1)-cell grid, dzf holds those nz+1 widths).
-Axis kinds: 0 P, 1 NN, 2 DD, 3 ND, 4 DN, 5 face-located DD (z only).
+Codes 3 and 4 (at both ends of an axis) put the field on the faces of that
+axis: 3 Dirichlet on the boundary face (zero there, not an unknown), 4 Neumann
+on the boundary face (an unknown, mirrored about it).  Along x and y any pair
+of 3 and 4 (uniform spacing; the unknowns are the C-1, C+1 or C faces of C
+cells); along z only (3, 3), the nz interior faces of an (nz+1)-cell grid
+whose nz+1 widths dzf holds.
+Axis kinds: 0 P, 1 NN, 2 DD, 3 ND, 4 DN (cell-centred); 5 (3,3) DST-I,
+6 (4,4) DCT-I, 7 (3,4), 8 (4,3) (face-located).
 """
 from __future__ import annotations
 
@@ -27,8 +32,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cans_oracle.c")
 _LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_ld.so")}
 
-P, N, D, DF = 0, 1, 2, 3
-K_P, K_NN, K_DD, K_ND, K_DN, K_FD = 0, 1, 2, 3, 4, 5
+P, N, D, DF, NF = 0, 1, 2, 3, 4
+K_P, K_NN, K_DD, K_ND, K_DN, K_FD, K_FN, K_FDN, K_FND = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 
 def n_dz(bc, nz: int) -> int:
@@ -111,7 +116,8 @@ def axis_kind(lo: int, hi: int) -> int:
 
 
 def eigen(kind: int, n: int, ld: bool = False):
-    """Transform rows T (n x n, T[q, i]) and eigenvalues mu (n,) of one axis."""
+    """Transform rows T (n x n, T[q, i]) and eigenvalues mu (n,) of one axis
+    (T A = diag(mu) T for the axis's 1-D operator A)."""
     T = np.zeros((n, n)); mu = np.zeros(n)
     _lib(ld).oracle_eigen(kind, n, _dp(T), _dp(mu))
     return T, mu
@@ -165,7 +171,9 @@ def solve(f, bc, dx: float, dy: float, dzf, ld: bool = False, shift: float = 0.0
     Returns (p, removed_mean).
 
     For singular problems (every axis P or NN, shift 0) f is projected by its
-    dzf-weighted mean, which is returned, and p has zero weighted mean."""
+    dzf-weighted mean, which is returned, and p has zero weighted mean.  A
+    problem that a face-located (4, 4) axis would make singular is not
+    defined (ValueError), nor is code 4 with a single unknown."""
     f = _f64(f); dzf = _f64(dzf)
     nz, ny, nx = f.shape
     assert dzf.shape == (n_dz(bc, nz),)

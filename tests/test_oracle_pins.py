@@ -502,7 +502,7 @@ def test_face_z_kinds_and_validation():
     assert not O.is_singular((P, P, P, P, DF, DF))
     f = np.ones((4, 2, 2))
     with pytest.raises(ValueError):
-        O.solve(f, (DF, DF, P, P, DF, DF), 1.0, 1.0, np.ones(5))
+        O.solve(f, (DF, D, P, P, DF, DF), 1.0, 1.0, np.ones(5))  # a face code with a cell code
     with pytest.raises(AssertionError):
         O.solve(f, (P, P, P, P, DF, DF), 1.0, 1.0, np.ones(4))  # needs nz+1 widths
 
@@ -803,3 +803,183 @@ def test_dt_scaling_and_bounds():
     dzc = 0.5 * (dzf[1:] + dzf[:-1])
     hi = np.abs(u).max() / dx + np.abs(v).max() / dy + np.abs(w).max() / min(dzf.min(), dzc.min())
     assert np.abs(u).max() / dx <= rate * (1 + 1e-15) and rate <= hi
+
+
+# --------------------------------------------------------------------------- #
+# Face-located fields along x and y (codes 3 and 4 at both ends of an axis):
+# the unknowns sit on the faces, a Dirichlet face (3) holds zero and is not an
+# unknown, a Neumann face (4) is an unknown mirrored about itself.
+NF = 4
+FACE_PAIRS = [(DF, DF), (NF, NF), (DF, NF), (NF, DF)]
+FACE_KIND = {(DF, DF): O.K_FD, (NF, NF): O.K_FN, (DF, NF): O.K_FDN, (NF, DF): O.K_FND}
+
+
+def op1d_face(lo, hi, n):
+    """(w_{i-1} - 2 w_i + w_{i+1}) on n face unknowns: a neighbour beyond a
+    Dirichlet face is the face's zero; beyond a Neumann face it is the mirror
+    image of the unknown next to that face."""
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, i] -= 2.0
+        for nb, side, mirror in ((i - 1, lo, 1), (i + 1, hi, n - 2)):
+            if 0 <= nb < n:
+                A[i, nb] += 1.0
+            elif side == NF:
+                A[i, mirror] += 1.0
+    return A
+
+
+def op1d_any(pair, n):
+    return op1d_face(*pair, n) if pair[0] in (DF, NF) else op1d(*pair, n)
+
+
+def dense_L_faces(nx, ny, nz, bc, dx, dy, dzf):
+    """Kronecker sum of the three 1-D operators; x and y from op1d_any, z
+    from dense_L on a single x-y cell (whose x and y terms cancel)."""
+    Az = dense_L(1, 1, nz, (N, N, N, N, bc[4], bc[5]), 1.0, 1.0, dzf)
+    Ax = op1d_any(bc[0:2], nx) / dx**2
+    Ay = op1d_any(bc[2:4], ny) / dy**2
+    Ix, Iy, Iz = np.eye(nx), np.eye(ny), np.eye(nz)
+    return np.kron(Iz, np.kron(Iy, Ax)) + np.kron(Iz, np.kron(Ay, Ix)) + np.kron(Az, np.kron(Iy, Ix))
+
+
+def test_face_xy_kinds_and_validation():
+    for pair, kind in FACE_KIND.items():
+        assert O.axis_kind(*pair) == kind
+    for bad in [(DF, D), (NF, N), (P, NF), (NF, P)]:
+        assert O.axis_kind(*bad) == -1
+    f = np.ones((4, 3, 4))
+    # z takes only the face-located Dirichlet pair
+    for zp in [(NF, NF), (DF, NF), (NF, DF)]:
+        bc = (P, P, P, P) + zp
+        with pytest.raises(ValueError):
+            O.solve(f, bc, 1.0, 1.0, np.ones(O.n_dz(bc, 4)))
+    # a (4, 4) axis in an otherwise singular problem is not defined ...
+    with pytest.raises(ValueError):
+        O.solve(f, (NF, NF, P, P, N, N), 1.0, 1.0, np.ones(4))
+    # ... with a shift, or a Dirichlet direction, it is
+    O.solve(f, (NF, NF, P, P, N, N), 1.0, 1.0, np.ones(4), shift=-1.0)
+    O.solve(f, (NF, NF, P, P, D, N), 1.0, 1.0, np.ones(4))
+    # code 4 needs two unknowns on its axis
+    with pytest.raises(ValueError):
+        O.solve(np.ones((4, 3, 1)), (DF, NF, P, P, D, D), 1.0, 1.0, np.ones(4))
+
+
+@pytest.mark.parametrize("pair", FACE_PAIRS)
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 8, 12, 16])
+def test_face_eigenpairs_bruteforce(pair, n):
+    """Rows of T are left eigenvectors of the face operator (T A = mu T), mu
+    is its full spectrum, and T has full rank."""
+    A = op1d_face(*pair, n)
+    T, mu = O.eigen(FACE_KIND[pair], n)
+    assert np.abs(T @ A - mu[:, None] * T).max() < 1e-13
+    ev = np.linalg.eigvals(A)
+    assert np.abs(ev.imag).max() < 1e-12
+    np.testing.assert_allclose(np.sort(mu), np.sort(ev.real), atol=1e-12)
+    assert np.linalg.matrix_rank(T) == n
+
+
+def test_face_dst1_single_unknown():
+    """One interior face between two cells: w = f / (-2/h^2)."""
+    T, mu = O.eigen(O.K_FD, 1)
+    assert T[0, 0] == pytest.approx(1.0) and mu[0] == pytest.approx(-2.0)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 9, 16, 31])
+def test_face_transforms_match_scipy(n):
+    """The face transforms are scipy's type-1 and type-3 DST/DCT (which carry
+    a factor 2): (3,3) DST-I, (4,4) DCT-I, (3,4) DST-III, (4,3) DCT-III; and
+    the inverse transform undoes each."""
+    rng = np.random.default_rng(100 + n)
+    x = rng.standard_normal((1, 1, n))
+    fx = lambda k: O.transform(x, 0, k)[0, 0]
+    v = x[0, 0]
+    np.testing.assert_allclose(fx(O.K_FD), scipy.fft.dst(v, type=1) / 2, atol=1e-12)
+    np.testing.assert_allclose(fx(O.K_FN), scipy.fft.dct(v, type=1) / 2, atol=1e-12)
+    np.testing.assert_allclose(fx(O.K_FDN), scipy.fft.dst(v, type=3) / 2, atol=1e-12)
+    np.testing.assert_allclose(fx(O.K_FND), scipy.fft.dct(v, type=3) / 2, atol=1e-12)
+    for k in (O.K_FD, O.K_FN, O.K_FDN, O.K_FND):
+        back = O.transform(O.transform(x, 0, k), 0, k, inverse=True)
+        np.testing.assert_allclose(back, x, atol=1e-12)
+
+
+@pytest.mark.parametrize("yp", [(P, P), (N, D), (DF, DF), (NF, DF)])
+@pytest.mark.parametrize("xp", FACE_PAIRS)
+def test_face_xy_dense_lu(xp, yp):
+    """Face-located x (and y) fields: the oracle's solve equals a dense solve
+    of the Kronecker-sum operator assembled here, on a stretched z, with and
+    without a shift, and apply_L equals the dense operator."""
+    nx, ny, nz = 5, 4, 6
+    seed = 7 * sum(xp) + sum(yp)
+    zp = (N, N) if seed % 2 else (D, N)
+    bc = xp + yp + zp
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0) * np.random.default_rng(seed).uniform(0.8, 1.2, nz)
+    A0 = dense_L_faces(nx, ny, nz, bc, 0.7, 1.3, dzf)
+    rng = np.random.default_rng(seed + 1)
+    for s in (0.0, -4.0):
+        f = rng.standard_normal((nz, ny, nx))
+        if s == 0.0 and np.linalg.matrix_rank(A0) < A0.shape[0]:
+            with pytest.raises(ValueError):
+                O.solve(f, bc, 0.7, 1.3, dzf)
+            continue
+        p, rem = O.solve(f, bc, 0.7, 1.3, dzf, shift=s)
+        pd = np.linalg.solve(A0 + s * np.eye(A0.shape[0]), f.ravel()).reshape(f.shape)
+        assert rel(p, pd) < 1e-12, (bc, s, rel(p, pd))
+        assert rem == 0.0
+        np.testing.assert_allclose(O.apply_L(f, bc, 0.7, 1.3, dzf, shift=s).ravel(),
+                                   A0 @ f.ravel() + s * f.ravel(), rtol=1e-12, atol=1e-9)
+        assert O.residual(p, f, bc, 0.7, 1.3, dzf, shift=s) < 1e-13
+
+
+def test_face_xy_closed_form():
+    """Uniform spacing: products of the face eigenvectors (written here from
+    the sine/cosine series of each pair) are solved exactly by f / lambda."""
+    nx, ny, nz, hx, hy, hz = 9, 8, 7, 0.4, 0.25, 0.5
+    i = np.arange(nx, dtype=float); j = np.arange(ny, dtype=float); k = np.arange(nz) + 0.5
+    # x (3,3): sin(pi (q+1)(i+1)/(nx+1));  y (4,3): cos(pi (2q+1) j/(2 ny));  z Dirichlet cells: DST-II
+    bc = (DF, DF, NF, DF, D, D)
+    for qx, qy, qz, s in [(0, 0, 0, 0.0), (3, 2, 4, 0.0), (8, 7, 6, -3.0), (5, 1, 2, -30.0)]:
+        ex = np.sin(np.pi * (qx + 1) * (i + 1) / (nx + 1)); lx = -4 * np.sin(np.pi * (qx + 1) / (2 * (nx + 1))) ** 2
+        ey = np.cos(np.pi * (2 * qy + 1) * j / (2 * ny)); ly = -4 * np.sin(np.pi * (2 * qy + 1) / (4 * ny)) ** 2
+        ez = np.sin(np.pi * (qz + 1) * k / nz); lz = -4 * np.sin(np.pi * (qz + 1) / (2 * nz)) ** 2
+        f = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        p, _ = O.solve(f, bc, hx, hy, np.full(nz, hz), shift=s)
+        lam = lx / hx**2 + ly / hy**2 + lz / hz**2 + s
+        assert rel(p, f / lam) < 1e-12, (qx, qy, qz, s)
+    # x (4,4): cos(pi q i/(nx-1));  y (3,4): sin(pi (2q+1)(j+1)/(2 ny));  shift keeps q = 0 regular
+    bc = (NF, NF, DF, NF, N, N)
+    for qx, qy, qz, s in [(0, 0, 0, -2.0), (4, 3, 2, 0.0), (8, 7, 6, -0.5)]:
+        ex = np.cos(np.pi * qx * i / (nx - 1)); lx = -4 * np.sin(np.pi * qx / (2 * (nx - 1))) ** 2
+        ey = np.sin(np.pi * (2 * qy + 1) * (j + 1) / (2 * ny)); ly = -4 * np.sin(np.pi * (2 * qy + 1) / (4 * ny)) ** 2
+        ez = np.cos(np.pi * qz * k / nz); lz = -4 * np.sin(np.pi * qz / (2 * nz)) ** 2
+        f = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        p, _ = O.solve(f, bc, hx, hy, np.full(nz, hz), shift=s)
+        lam = lx / hx**2 + ly / hy**2 + lz / hz**2 + s
+        assert rel(p, f / lam) < 1e-12, (qx, qy, qz, s)
+
+
+def test_face_xy_quadratic_exact():
+    """The three-point difference is exact for quadratics: w = x (Lx - x) on
+    the faces of (3,3) maps to -2; w = (x - Lx)^2 on (4,3)'s faces (zero slope
+    at the Neumann face x = 0 is not needed: the mirror makes the stencil
+    use w(-h) = w(h), exact for an even quadratic about x = 0) maps to 2."""
+    nx, ny, nz, h = 9, 4, 3, 0.3
+    xf = (np.arange(nx) + 1) * h            # interior faces of nx+1 cells
+    Lx = (nx + 1) * h
+    w = np.broadcast_to(xf * (Lx - xf), (nz, ny, nx)).copy()
+    out = O.apply_L(w, (DF, DF, P, P, P, P), h, 1.0, np.ones(nz))
+    np.testing.assert_allclose(out, -2.0, atol=1e-12)
+    xf = np.arange(nx) * h                  # faces 0 .. nx-1, Neumann at 0, Dirichlet at nx h
+    w = np.broadcast_to(xf**2 - (nx * h) ** 2, (nz, ny, nx)).copy()
+    out = O.apply_L(w, (NF, DF, P, P, P, P), h, 1.0, np.ones(nz))
+    np.testing.assert_allclose(out, 2.0, atol=1e-11)
+
+
+def test_face_xy_long_double_agrees():
+    nx, ny, nz = 7, 6, 5
+    bc = (NF, DF, DF, DF, N, D)
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    f = np.random.default_rng(3).standard_normal((nz, ny, nx))
+    p, _ = O.solve(f, bc, 0.3, 0.4, dzf, shift=-1.0)
+    pl, _ = O.solve(f, bc, 0.3, 0.4, dzf, ld=True, shift=-1.0)
+    assert rel(p, pl) < 1e-13
