@@ -15,8 +15,11 @@
  *     dzc_k = (dzf_k + dzf_{k+1})/2, mirror ghost cell at a wall.
  * Boundary conditions are homogeneous and located on the cell faces
  * (staggered): periodic p_0 = p_n; Neumann p_0 = p_1; Dirichlet p_0 = -p_1.
- * Along z a field may instead live on the cell faces themselves, with zero
- * on the wall faces (CANS_BC_DIRICHLET_FACE below).
+ * A field may instead live on the cell faces of an axis themselves (a
+ * velocity component along its own direction, as in the implicit diffusion
+ * steps of eq. (up_id_2)): CANS_BC_DIRICHLET_FACE and CANS_BC_NEUMANN_FACE
+ * below, which take the DST-I, DCT-I and type-III transforms (the rest of
+ * the transform types Section 3 lists for the CPU solver).
  *
  * Layout of every field: double, x fastest, element (i,j,k) at
  * i + nx*(j + ny*k), i.e. a C array [nz][ny][nx].
@@ -48,14 +51,29 @@ enum cans_bc {
          [(w_{k+1}-w_k)/dz_{k+1} - (w_k-w_{k-1})/dz_k] / ((dz_k + dz_{k+1})/2)
        with w_{-1} = w_nz = 0.  Never singular; element (i,j,k) of rhs and p
        is the value on face k (between cells k and k+1). */
-    CANS_BC_DIRICHLET_FACE = 3
+    CANS_BC_DIRICHLET_FACE = 3,
+    /* A field located on the faces of x or y (codes 3 and 4, both ends of the
+       axis one of them): code 3 is Dirichlet on the boundary face (the field
+       is zero there and the face is no unknown), code 4 Neumann on the
+       boundary face (the face is an unknown and the field is mirrored about
+       it, w_{-1} = w_1).  With C cells of width dx along x the nx unknowns
+       are the C-1 interior faces for (3,3) (DST-I), all C+1 faces for (4,4)
+       (DCT-I), and the C faces other than the Dirichlet one for (3,4) (a
+       DST-III) and (4,3) (a DCT-III); element i is the i-th of those faces
+       from x-.  The operator is (w_{i-1} - 2 w_i + w_{i+1})/dx^2.  Along z
+       only (3,3).  A problem that a (4,4) pair would make singular (shift 0,
+       every other axis periodic or Neumann) is unsupported; so are the
+       dense transform, the projection step and the time-step bound on such
+       an axis. */
+    CANS_BC_NEUMANN_FACE = 4
 };
 
 enum cans_status {
     CANS_OK = 0,
     CANS_ERR_INVALID_ARG = -1,  /* bad size, spacing, pointer or boundary pair */
     CANS_ERR_UNSUPPORTED = -2,  /* valid problem the library does not handle
-                                   (odd, > 4096 or non-{2,3,5}-smooth x/y length,
+                                   (an x/y transform line that is odd, > 4096 or not
+                                   {2,3,5}-smooth -- see cans_poisson_plan --,
                                    periodic z that is stretched or shorter
                                    than 3 cells, a transform form the options
                                    do not allow, shift > 0) */
@@ -144,7 +162,11 @@ void cans_default_opts(cans_opts *opts);
  *   dz     = host array of nz cell widths dzf (> 0), copied into the plan; a
  *            periodic z must be uniform.  With CANS_BC_DIRICHLET_FACE on z:
  *            the nz+1 widths of the cells around the face-located unknowns.
- *   nx, ny even, at most 4096, with nx/2, ny/2 products of 2, 3 and 5;
+ *   nx, ny: the line the transform sees -- the line itself, or for a
+ *            face-located (3,3) / (4,4) pair its odd / even extension of
+ *            2(n+1) / 2(n-1) reals -- has an even length of at most 4096
+ *            whose half is a product of 2, 3 and 5 (so n even for the
+ *            cell-centred pairs and the face pairs (3,4), (4,3));
  *   nz >= 1 (>= 3 if periodic).
  * The plan owns its tables and device workspace (allocated on the current
  * device).  One solve may be in flight per plan at a time.

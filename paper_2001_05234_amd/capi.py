@@ -24,7 +24,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported problem", -3: "alloc
           -6: "problem exceeds the fixed scratch of the no-allocation solve"}
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 XFORM_AUTO, XFORM_FFT, XFORM_DENSE = 0, 1, 2
-BC_PERIODIC, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET_FACE = 0, 1, 2, 3
+BC_PERIODIC, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET_FACE, BC_NEUMANN_FACE = 0, 1, 2, 3, 4
 HISTORY = 17
 
 

@@ -190,8 +190,13 @@ int launch_div_xfwd(const Problem &pb, const double *u, const double *v, const d
     DivArgs d{u, v, w, pb.d_dzf, pb.nx, pb.ny, pb.nz,
               pb.bc[0] == CANS_BC_PERIODIC, pb.bc[2] == CANS_BC_PERIODIC, pb.bc[4] == CANS_BC_PERIODIC,
               1.0 / pb.ax.h, 1.0 / pb.ay.h, 1.0 / gdt};
-    CANS_KIND_SWITCH(pb.ax.kind,
-        hipLaunchKernelGGL(k_div_xfwd<KD>, grid, dim3(kThreads), sh, s, out, nlines, g, pb.ax.d_tw64, d));
+    // the projection step takes periodic or wall (Neumann) pressure boundaries
+    if (pb.ax.kind == K_P)
+        hipLaunchKernelGGL(k_div_xfwd<K_P>, grid, dim3(kThreads), sh, s, out, nlines, g, pb.ax.d_tw64, d);
+    else if (pb.ax.kind == K_NN)
+        hipLaunchKernelGGL(k_div_xfwd<K_NN>, grid, dim3(kThreads), sh, s, out, nlines, g, pb.ax.d_tw64, d);
+    else
+        return CANS_ERR_UNSUPPORTED;
     return check_launch();
 }
 

@@ -36,9 +36,10 @@ static inline int norm_rows(const Problem &pb)
 // rows j0 .. j0 + nr - 1 (nr <= 2) of plane k, block-wide, in chunks of
 // kResidChunk points of a row.  Each thread first loads all it needs of the
 // chunk into registers: its kResidU points of the two rows and of the rows
-// just below and above them (by the y ghost rule of the face at a domain
+// just below and above them (by the y rule of `beyond` at a domain
 // boundary: periodic wraps, Neumann mirrors, Dirichlet mirrors with the sign
-// flipped), so every global load is in flight at once.  The rows themselves
+// flipped; a face-located field is zero beyond a Dirichlet face and mirrored
+// about a Neumann face), so every global load is in flight at once.  The rows themselves
 // go to LDS (`rows`, 2 (kResidChunk + 2) doubles) for the x neighbours; the
 // planes above and below and f are loaded after the barrier, again all at
 // once.  The arithmetic per point is lap_point's.  put(l, e, r) receives every
@@ -66,13 +67,8 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
         if (l == nr + 1) j = j0 + nr;
         if (l > nr + 1) j = j0 + nr - 1;  // not used
         sg[l] = 1.0;
-        if (j < 0) {
-            sg[l] = la.bc[2] == CANS_BC_PERIODIC || la.bc[2] == CANS_BC_NEUMANN ? 1.0 : -1.0;
-            j = la.bc[2] == CANS_BC_PERIODIC ? ny - 1 : 0;
-        } else if (j >= ny) {
-            sg[l] = la.bc[3] == CANS_BC_PERIODIC || la.bc[3] == CANS_BC_NEUMANN ? 1.0 : -1.0;
-            j = la.bc[3] == CANS_BC_PERIODIC ? 0 : ny - 1;
-        }
+        if (j < 0) beyond(la.bc[2], true, ny, j, sg[l]);
+        else if (j >= ny) beyond(la.bc[3], false, ny, j, sg[l]);
         rp[l] = pk + sy * j;
     }
     const double *zm_pl = k > 0 ? pk - sz : p + sz * (nz - 1);  // wrap plane at a boundary
@@ -107,11 +103,11 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
             if (l < nr) {
                 const double *row = rp[l + 1];
                 if ((t & 1) == 0)
-                    rows[l * rs] = e0 > 0 ? row[e0 - 1] : ghost(la.bc[0], row[0], row[n - 1]);
+                    rows[l * rs] = e0 > 0 ? row[e0 - 1] : across(la.bc[0], true, row, 0, 0, n, 1);
                 else if (e0 + kResidChunk < n)
                     rows[l * rs + kResidChunk + 1] = row[e0 + kResidChunk];
                 else
-                    rows[l * rs + 1 + (n - e0)] = ghost(la.bc[1], row[n - 1], row[0]);
+                    rows[l * rs + 1 + (n - e0)] = across(la.bc[1], false, row, n - 1, n - 1, n, 1);
             }
         }
         __syncthreads();
@@ -181,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile<AX_X, float> tile{reinterpret_cast<cx<float> *>(smem), g.L, g.RS, g.psh};
     double *rows = reinterpret_cast<double *>(smem + rows_off);  // after the transform tile
-    const int n = g.n, L = g.L;
+    const int n = g.nl, L = g.L;
     int k, j0, lv;
     rslice_of(blockIdx.x, H, bpp, L, la.ny, la.nz, k, j0, lv);
     RAcc acc;

@@ -20,7 +20,11 @@ struct BlockSync {
     case K_NN: { constexpr int KD = K_NN; __VA_ARGS__; } break;      \
     case K_DD: { constexpr int KD = K_DD; __VA_ARGS__; } break;      \
     case K_ND: { constexpr int KD = K_ND; __VA_ARGS__; } break;      \
-    default: { constexpr int KD = K_DN; __VA_ARGS__; } break;        \
+    case K_DN: { constexpr int KD = K_DN; __VA_ARGS__; } break;      \
+    case K_S1: { constexpr int KD = K_S1; __VA_ARGS__; } break;      \
+    case K_C1: { constexpr int KD = K_C1; __VA_ARGS__; } break;      \
+    case K_FDN: { constexpr int KD = K_FDN; __VA_ARGS__; } break;    \
+    default: { constexpr int KD = K_FND; __VA_ARGS__; } break;       \
     }
 
 static inline int check_launch()

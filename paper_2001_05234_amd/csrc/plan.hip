@@ -64,21 +64,30 @@ int alloc(cans_plan_s *pl, T **dst, size_t count)
 
 #define CANS_TRY(x) do { int rc_ = (x); if (rc_ != CANS_OK) return rc_; } while (0)
 
-int validate(int nx, int ny, int nz, const int *bc, double dx, double dy, const double *dz)
+int validate(int nx, int ny, int nz, const int *bc, double dx, double dy, const double *dz, double shift)
 {
     if (!bc || !dz || nx < 1 || ny < 1 || nz < 1) return CANS_ERR_INVALID_ARG;
     if (!(dx > 0) || !(dy > 0) || !std::isfinite(dx) || !std::isfinite(dy)) return CANS_ERR_INVALID_ARG;
     for (int i = 0; i < 6; ++i)
-        if (bc[i] < 0 || bc[i] > 3) return CANS_ERR_INVALID_ARG;
-    // a face-located field only along z (axis_kind rejects code 3)
-    if (axis_kind(bc[0], bc[1]) < 0 || axis_kind(bc[2], bc[3]) < 0 || z_kind(bc[4], bc[5]) < 0)
-        return CANS_ERR_INVALID_ARG;
+        if (bc[i] < 0 || bc[i] > CANS_BC_NEUMANN_FACE) return CANS_ERR_INVALID_ARG;
+    // face-located pairs on x and y; on z only the Dirichlet face pair
+    const int kx = axis_kind(bc[0], bc[1]), ky = axis_kind(bc[2], bc[3]);
+    if (kx < 0 || ky < 0 || z_kind(bc[4], bc[5]) < 0) return CANS_ERR_INVALID_ARG;
     for (int k = 0; k < z_widths(nz, bc[4]); ++k)
         if (!(dz[k] > 0) || !std::isfinite(dz[k])) return CANS_ERR_INVALID_ARG;
-    // even lengths up to 4096 (an FP64 line tile of two LDS buffers fits 64 KiB)
-    if (nx % 2 || ny % 2 || nx > 4096 || ny > 4096) return CANS_ERR_UNSUPPORTED;
+    // the line the FFT sees (the line itself, or its odd / even extension for
+    // a face-located Dirichlet / Neumann pair): even, up to 4096 reals (an FP64
+    // line tile of two LDS buffers fits 64 KiB), half of it {2,3,5}-smooth
+    const int fx = fft_len(kx, nx), fy = fft_len(ky, ny);
+    if (fx < 2 || fy < 2 || fx % 2 || fy % 2 || fx > 4096 || fy > 4096) return CANS_ERR_UNSUPPORTED;
     XGeom g{};
-    if (!factor(nx / 2, g) || !factor(ny / 2, g)) return CANS_ERR_UNSUPPORTED;
+    if (!factor(fx / 2, g) || !factor(fy / 2, g)) return CANS_ERR_UNSUPPORTED;
+    // a face-located Neumann pair (DCT-I) in a problem it would make singular
+    // is not handled (its compatibility weights differ from the cell form's)
+    const int kz = z_kind(bc[4], bc[5]);
+    if (shift == 0.0 && (kz == K_P || kz == K_NN) && has_zero_mode(kx) && has_zero_mode(ky) &&
+        (kx == K_C1 || ky == K_C1))
+        return CANS_ERR_UNSUPPORTED;
     if (bc[4] == CANS_BC_PERIODIC) {
         if (nz < 3) return CANS_ERR_UNSUPPORTED;
         for (int k = 1; k < nz; ++k)
@@ -94,10 +103,10 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h, double shift
     a.h = h;
     a.s = xform_scale(kind, n);
     for (int d = 0; d < 2; ++d)
-        if (!make_geom(a.gx64[d], AX_X, n, 8) || !make_geom(a.gx32[d], AX_X, n, 4) ||
-            !make_geom(a.gy64[d], AX_Y, n, 8) || !make_geom(a.gy32[d], AX_Y, n, 4))
+        if (!make_geom(a.gx64[d], AX_X, kind, n, 8) || !make_geom(a.gx32[d], AX_X, kind, n, 4) ||
+            !make_geom(a.gy64[d], AX_Y, kind, n, 8) || !make_geom(a.gy32[d], AX_Y, kind, n, 4))
             return CANS_ERR_UNSUPPORTED;
-    std::vector<cx<double>> t64 = twiddles(n);
+    std::vector<cx<double>> t64 = twiddles(fft_len(kind, n));
     std::vector<cx<float>> t32(t64.size());
     for (size_t i = 0; i < t64.size(); ++i) t32[i] = mk((float)t64[i].re, (float)t64[i].im);
     CANS_TRY(upload(pl, &a.d_tw64, t64.data(), t64.size()));
@@ -126,7 +135,7 @@ void split_bf16(const std::vector<long double> &W, int n, std::vector<unsigned s
 
 int build_dense(cans_plan_s *pl, Axis &a)
 {
-    if (!dense_ok(a.n)) return CANS_ERR_UNSUPPORTED;
+    if (!dense_ok(a.kind, a.n)) return CANS_ERR_UNSUPPORTED;
     std::vector<unsigned short> hi, lo;
     split_bf16(dense_forward(a.kind, a.n), a.n, hi, lo);
     CANS_TRY(upload(pl, &a.d_wf_hi, hi.data(), hi.size()));
@@ -166,14 +175,14 @@ int autotune(cans_plan_s *pl, Problem &pb)
         (void)hipEventElapsedTime(&ms, e0, e1);
         return ms;
     };
-    auto tune = [&](XGeom &slot, int axis, int n, int elem, auto launch) {
+    auto tune = [&](XGeom &slot, int axis, const Axis &ax, int elem, auto launch) {
         XGeom best = slot;
         float tbest = timeit(launch);
         const int L0 = slot.L;
         for (int L : {L0 / 4, L0 / 2, L0, L0 * 2, L0 * 4})
             for (int rmax : {8, 4}) {
                 XGeom g;
-                if (L < 1 || (L == L0 && rmax == 8) || !make_geom(g, axis, n, elem, L, rmax)) continue;
+                if (L < 1 || (L == L0 && rmax == 8) || !make_geom(g, axis, ax.kind, ax.n, elem, L, rmax)) continue;
                 slot = g;
                 const float t = timeit(launch);
                 if (t < tbest) {
@@ -185,23 +194,23 @@ int autotune(cans_plan_s *pl, Problem &pb)
     };
     if (rc == CANS_OK) {
         if (pl->opts.precision == CANS_PREC_FP64) {
-            tune(pb.ax.gx64[1], AX_X, pb.nx, 8, [&] { return launch_x_f64(pb, true, s64, s64, st); });
-            tune(pb.ax.gx64[0], AX_X, pb.nx, 8, [&] { return launch_x_f64(pb, false, s64, s64, st); });
-            tune(pb.ay.gy64[1], AX_Y, pb.ny, 8, [&] { return launch_y_f64(pb, true, s64, s64, st); });
-            tune(pb.ay.gy64[0], AX_Y, pb.ny, 8, [&] { return launch_y_f64(pb, false, s64, s64, st); });
+            tune(pb.ax.gx64[1], AX_X, pb.ax, 8, [&] { return launch_x_f64(pb, true, s64, s64, st); });
+            tune(pb.ax.gx64[0], AX_X, pb.ax, 8, [&] { return launch_x_f64(pb, false, s64, s64, st); });
+            tune(pb.ay.gy64[1], AX_Y, pb.ay, 8, [&] { return launch_y_f64(pb, true, s64, s64, st); });
+            tune(pb.ay.gy64[0], AX_Y, pb.ay, 8, [&] { return launch_y_f64(pb, false, s64, s64, st); });
         } else {
             if (!pb.ax.dense) {
                 // the forward tile is also the residual kernel's: only candidates
                 // whose residual LDS fits
-                tune(pb.ax.gx32[1], AX_X, pb.nx, 4, [&] {
+                tune(pb.ax.gx32[1], AX_X, pb.ax, 4, [&] {
                     if (resid_xfwd_lds(pb, pb.ax.gx32[1]) > kResidLdsMax) return (int)CANS_ERR_UNSUPPORTED;
                     return launch_x_fwd_32(pb, pb.ws, s64, pb.ws.a32, nullptr, st);
                 });
-                tune(pb.ax.gx32[0], AX_X, pb.nx, 4,
+                tune(pb.ax.gx32[0], AX_X, pb.ax, 4,
                      [&] { return launch_x_inv_32(pb, pb.ws, pb.ws.a32, s64, false, nullptr, st); });
             }
-            tune(pb.ay.gy32[1], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, true, pb.ws.a32, nullptr, st); });
-            tune(pb.ay.gy32[0], AX_Y, pb.ny, 4, [&] { return launch_y_32(pb, false, pb.ws.a32, nullptr, st); });
+            tune(pb.ay.gy32[1], AX_Y, pb.ay, 4, [&] { return launch_y_32(pb, true, pb.ws.a32, nullptr, st); });
+            tune(pb.ay.gy32[0], AX_Y, pb.ay, 4, [&] { return launch_y_32(pb, false, pb.ws.a32, nullptr, st); });
         }
         if (hipStreamSynchronize(st) != hipSuccess) rc = CANS_ERR_HIP;
     }
@@ -500,7 +509,7 @@ int cans_poisson_plan_batched(cans_plan_t *out, int count, const cans_desc *desc
     CANS_TRY(check_opts(o));
     for (int i = 0; i < count; ++i)
         CANS_TRY(validate(descs[i].nx, descs[i].ny, descs[i].nz, descs[i].bc, descs[i].dx, descs[i].dy,
-                          descs[i].dz));
+                          descs[i].dz, o.shift));
     cans_plan_s *pl = new (std::nothrow) cans_plan_s();
     if (!pl) return CANS_ERR_ALLOC;
     pl->opts = o;

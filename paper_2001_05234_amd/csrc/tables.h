@@ -14,8 +14,17 @@
 
 namespace cans {
 
+inline bool face_code(int c) { return c == CANS_BC_DIRICHLET_FACE || c == CANS_BC_NEUMANN_FACE; }
+
+// transform kind of an x or y axis from its two boundary codes, -1 if the
+// pair is invalid
 inline int axis_kind(int lo, int hi)
 {
+    if (face_code(lo) || face_code(hi)) {
+        if (!face_code(lo) || !face_code(hi)) return -1;
+        if (lo == CANS_BC_DIRICHLET_FACE) return hi == CANS_BC_DIRICHLET_FACE ? K_S1 : K_FDN;
+        return hi == CANS_BC_NEUMANN_FACE ? K_C1 : K_FND;
+    }
     if (lo == CANS_BC_PERIODIC || hi == CANS_BC_PERIODIC)
         return (lo == CANS_BC_PERIODIC && hi == CANS_BC_PERIODIC) ? K_P : -1;
     if (lo == CANS_BC_NEUMANN && hi == CANS_BC_NEUMANN) return K_NN;
@@ -77,12 +86,16 @@ inline int tile_lines(int axis, int n, int elem)
 // bytes of LDS a tile takes
 inline size_t tile_bytes(int axis, const XGeom &g, int elem) { return (size_t)tile_slots(axis, g) * 2 * elem; }
 
-// Geometry of an n-point transform tile; L = 0 takes the default lines per
-// tile, rmax the radix preference.  False if the tile does not fit.
-inline bool make_geom(XGeom &g, int axis, int n, int elem, int L = 0, int rmax = 8)
+// Geometry of the tile of a transform of `kind` over lines of nl reals; L =
+// 0 takes the default lines per tile, rmax the radix preference.  False if
+// the tile does not fit.
+inline bool make_geom(XGeom &g, int axis, int kind, int nl, int elem, int L = 0, int rmax = 8)
 {
+    const int n = fft_len(kind, nl);
     g = XGeom{};
+    if (n < 2 || n % 2) return false;
     g.n = n;
+    g.nl = nl;
     g.M = n / 2;
     g.L = L > 0 ? L : tile_lines(axis, n, elem);
     if (!is_pow2(g.L) || g.L > (axis == AX_X ? 64 : 32)) return false;
@@ -91,7 +104,7 @@ inline bool make_geom(XGeom &g, int axis, int n, int elem, int L = 0, int rmax =
     g.psh = elem == 8 ? 4 : 5;  // 256-byte LDS rows of 16-byte / 8-byte slots
     g.RS = g.M + ((g.M - 1) >> g.psh) + 1;
     g.magM = mag_of((unsigned)g.M);
-    g.magN = mag_of((unsigned)g.n);
+    g.magN = mag_of((unsigned)g.nl);
     if (!factor(g.M, g, rmax)) return false;
     if (tile_bytes(axis, g, elem) > 65536) return false;
     // every in-place stage must fit the per-thread capacity of a 256-thread block
@@ -113,7 +126,9 @@ inline long double mu_row(int kind, int n, int q)
     }
     case K_NN: th = pi * q / (2.0L * n); break;
     case K_DD: th = pi * (q + 1) / (2.0L * n); break;
-    default: th = pi * (2 * q + 1) / (4.0L * n); break;
+    case K_S1: th = pi * (q + 1) / (2.0L * (n + 1)); break;
+    case K_C1: th = pi * q / (2.0L * (n - 1)); break;
+    default: th = pi * (2 * q + 1) / (4.0L * n); break;  // ND, DN, FDN, FND
     }
     const long double s = sinl(th);
     return -4.0L * s * s;
@@ -143,12 +158,13 @@ inline std::vector<double> lambdas(int kind, int n, double h)
     return lam;
 }
 
-// Kind of the z axis: as axis_kind, plus a face-located field
-// (CANS_BC_DIRICHLET_FACE at both ends), which solves as Dirichlet-Dirichlet:
-// neither periodic nor singular.
+// Kind of the z axis: as axis_kind for the cell-centred pairs, plus a
+// face-located field with CANS_BC_DIRICHLET_FACE at both ends, which solves
+// as Dirichlet-Dirichlet: neither periodic nor singular.  No other face pair
+// on z.
 inline int z_kind(int lo, int hi)
 {
-    if (lo == CANS_BC_DIRICHLET_FACE || hi == CANS_BC_DIRICHLET_FACE)
+    if (face_code(lo) || face_code(hi))
         return (lo == CANS_BC_DIRICHLET_FACE && hi == CANS_BC_DIRICHLET_FACE) ? K_DD : -1;
     return axis_kind(lo, hi);
 }
@@ -218,8 +234,15 @@ inline void zcoef(int nz, int lo, int hi, const std::vector<double> &dzf, std::v
     if (hi == CANS_BC_DIRICHLET) { b[nz - 1] = (double)((long double)b[nz - 1] - cf[nz - 1]); c[nz - 1] = 0; }
 }
 
-// normalisation s of B T = s I
-inline int xform_scale(int kind, int n) { return (kind == K_ND || kind == K_DN) ? n / 2 : n; }
+// normalisation s of B T = s I (n: reals of a line)
+inline int xform_scale(int kind, int n)
+{
+    if (kind == K_S1 || kind == K_C1) return fft_len(kind, n);
+    return (kind == K_ND || kind == K_DN) ? n / 2 : n;
+}
+
+// face kinds: zero mode of DCT-I (q = 0), as P and NN
+inline bool has_zero_mode(int kind) { return kind == K_P || kind == K_NN || kind == K_C1; }
 
 // Row q of the forward transform of an axis as a dense vector (the same rows,
 // order and signs the FFT path produces): T[q][e], long double.
@@ -261,7 +284,7 @@ inline std::vector<long double> dense_inverse(int kind, int n)
     return B;
 }
 
-// dense transforms apply to n = 128 .. 512 in steps of 128
-inline bool dense_ok(int n) { return n >= 128 && n <= 512 && n % 128 == 0; }
+// dense transforms apply to the cell-centred kinds, n = 128 .. 512 in steps of 128
+inline bool dense_ok(int kind, int n) { return kind <= K_DN && n >= 128 && n <= 512 && n % 128 == 0; }
 
 }  // namespace cans

@@ -26,6 +26,19 @@
 //      inverse up to n/2.
 //   DN DST-IV = (-1)^q DCT-IV of the reversed line; own inverse up to n/2.
 // With B the inverse listed, B T = s I with s = n (P, NN, DD) or n/2 (ND, DN).
+//
+// Fields located on the faces of an axis (nl unknowns per line, n = 2M the
+// length of the extended line the FFT sees):
+//   S1  DST-I of nl = M-1 values, X_q = 2 sum_i x_i sin(pi (q+1)(i+1)/M):
+//       the real DFT of the line extended odd about 0 and M (zero there) to
+//       2M reals is -i X; its own inverse up to s = 2M.
+//   C1  DCT-I of nl = M+1 values, X_q = x_0 + (-1)^q x_M + 2 sum_{0<i<M}
+//       x_i cos(pi q i/M): the real DFT of the line extended even about 0
+//       and M; its own inverse up to s = 2M.
+//   FDN, FND  (Dirichlet face, Neumann face) and (Neumann face, Dirichlet
+//       face): the type-III sine and cosine transforms, i.e. the DD and NN
+//       pairs above run the other way round (DST-III forward, DST-II back;
+//       DCT-III forward, DCT-II back), s = n = nl.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,7 +47,22 @@
 
 namespace cans {
 
-enum Kind { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4 };
+enum Kind { K_P = 0, K_NN = 1, K_DD = 2, K_ND = 3, K_DN = 4, K_S1 = 5, K_C1 = 6, K_FDN = 7, K_FND = 8 };
+
+// the transform a kind runs (FDN and FND run DD and NN backwards), whether
+// it runs it backwards, and whether it is its own inverse
+constexpr int base_kind(int k) { return k == K_FDN ? K_DD : (k == K_FND ? K_NN : k); }
+constexpr bool flipped(int k) { return k == K_FDN || k == K_FND; }
+constexpr bool own_inverse(int k) { return k == K_ND || k == K_DN || k == K_S1 || k == K_C1; }
+// the packing map of the transform reads each input real twice (synthesis
+// of a half spectrum, or an extended line)
+constexpr bool reads_twice(int k, bool fwd)
+{
+    return base_kind(k) == K_S1 || base_kind(k) == K_C1 ||
+           ((flipped(k) ? fwd : !fwd) && (base_kind(k) == K_P || base_kind(k) == K_NN || base_kind(k) == K_DD));
+}
+// length of the extended real line of a kind with nl unknowns a line
+CANS_HD int fft_len(int kind, int nl) { return kind == K_S1 ? 2 * (nl + 1) : (kind == K_C1 ? 2 * (nl - 1) : nl); }
 
 constexpr int kMaxStages = 24;
 
@@ -158,7 +186,8 @@ CANS_HD unsigned udiv(unsigned n, unsigned d, unsigned mag)
 
 // Geometry of one transform tile.
 struct XGeom {
-    int n;      // real length (even)
+    int n;      // real length of the (extended) line the FFT sees (even)
+    int nl;     // reals of a line in memory: n, or n/2 -+ 1 for S1 / C1
     int M;      // n / 2
     int L;      // lines per tile (power of two)
     int lgL;
@@ -166,7 +195,7 @@ struct XGeom {
     int psh;    // x tiles: one pad slot every 2^psh slots (256-byte LDS rows)
     int nst;    // FFT stages
     unsigned magM;
-    unsigned magN;     // magic for / n
+    unsigned magN;     // magic for / nl
     int rad[kMaxStages];
     int str[kMaxStages];       // s of each stage (product of earlier radices)
     unsigned mag_s[kMaxStages];   // magic for / s
@@ -226,6 +255,18 @@ template <int KIND, bool FWD, typename T, typename Src>
 CANS_HD cx<T> pack(int m, const XGeom &g, const Src &src, const cx<T> *tw)
 {
     const int n = g.n, M = g.M;
+    if (KIND == K_S1 || KIND == K_C1) {
+        // the line extended to 2M reals: odd about 0 and M (zero there) for
+        // DST-I, even about them for DCT-I
+        auto ext = [&](int j) -> T {
+            if (KIND == K_S1) {
+                if (j == 0 || j == M) return T(0);
+                return j < M ? src(j - 1) : -src(2 * M - 1 - j);
+            }
+            return src(j <= M ? j : 2 * M - j);
+        };
+        return mk(ext(2 * m), ext(2 * m + 1));
+    }
     if (KIND == K_ND || KIND == K_DN) {
         const T a = src(2 * m), b = src(n - 1 - 2 * m);
         return ((KIND == K_ND) ? mk(a, b) : mk(b, a)) * tw[tw_pre4(M) + m];
@@ -272,6 +313,24 @@ CANS_HD void unpack(int k, const XGeom &g, const ZAt &Z, const Put &put, const c
 {
     const int n = g.n, M = g.M;
     const cx<T> z = Z(k);
+    if (KIND == K_S1 || KIND == K_C1) {
+        // V_k of the extended line (the real-DFT split below); DST-I keeps
+        // -Im V_k, k = 1..M-1, DCT-I Re V_k, k = 0..M
+        if (k == 0) {
+            if (KIND == K_C1) {
+                put(0, z.re + z.im);
+                put(M, z.re - z.im);
+            }
+            return;
+        }
+        const cx<T> zc = conj(Z(M - k));
+        const cx<T> E = scal(z + zc, T(0.5));
+        const cx<T> O = scal(mul_ni(z - zc), T(0.5));
+        const cx<T> V = E + tw[tw_split(M) + k] * O;
+        if (KIND == K_S1) put(k - 1, -V.im);
+        else put(k, V.re);
+        return;
+    }
     if (KIND == K_ND || KIND == K_DN) {
         const cx<T> u = z * tw[tw_post4(M) + k];
         put(2 * k, u.re);
@@ -433,10 +492,13 @@ template <int KIND, bool FWD, int AXIS, bool INPLACE, bool SRCTILE, typename T, 
 CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, const Put &put, Tile<AXIS, T> ta,
                             Tile<AXIS, T> tb, const cx<T> *tw, const Sync &sync)
 {
-    // DCT-IV and DST-IV are their own inverses: the FFT runs forward both ways
-    constexpr bool FFTF = FWD || KIND == K_ND || KIND == K_DN;
+    // the face pairs FDN / FND run DD / NN backwards; the transforms that
+    // are their own inverses run the FFT forward both ways
+    constexpr int BK = base_kind(KIND);
+    constexpr bool BF = flipped(KIND) ? !FWD : FWD;
+    constexpr bool FFTF = BF || own_inverse(BK);
     auto packed = [&](int m, int l) -> cx<T> {
-        return pack<KIND, FWD, T>(m, g, [&](int e) -> T { return src(e, l); }, tw);
+        return pack<BK, BF, T>(m, g, [&](int e) -> T { return src(e, l); }, tw);
     };
     Tile<AXIS, T> cur = ta, nxt = tb;
     if (g.nst == 0) {
@@ -463,7 +525,7 @@ CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, con
     for (int w = tid; w < total; w += nt) {
         int l, k;
         split_item<AXIS>(w, g.M, g.magM, g.lgL, g.L, l, k);
-        unpack<KIND, FWD, T>(
+        unpack<BK, BF, T>(
             k, g, [&](int kk) -> cx<T> { return cur.at(kk, l); }, [&](int q, T v) { put(q, l, v); }, tw);
     }
 }

@@ -26,7 +26,7 @@ void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile<AX_X, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
-    const int n = g.n;
+    const int n = g.nl;
     const long line0 = (long)blockIdx.x * g.L;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
@@ -38,9 +38,10 @@ void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
             else out[idx] = (Tout)v;
         }
     };
-    // inverse real-DFT / DCT / DST synthesis reads every input twice: stage
-    // the lines in LDS with coalesced loads first
-    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
+    // inverse real-DFT / DCT / DST synthesis and the extended lines of the
+    // face-located transforms read every input twice: stage the lines in LDS
+    // with coalesced loads first
+    constexpr bool STAGED = reads_twice(KIND, FWD);
     if constexpr (STAGED) {
         for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
             const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;

@@ -162,13 +162,39 @@ struct LapArgs {
     double shift;       // Helmholtz shift s: the operator is L_h + s
 };
 
-// neighbour across a wall by its ghost rule: periodic wraps, Neumann
-// mirrors, Dirichlet is antisymmetric.  A face-located field (code 3) takes
-// the antisymmetric ghost too, with its wall coupling halved in the tables:
-// (a/2)(w - (-w)) = a (w - 0) exactly, its zero wall value.
+// z neighbour across a wall by its ghost rule: periodic wraps, Neumann
+// mirrors, Dirichlet is antisymmetric.  A face-located z field (code 3)
+// takes the antisymmetric ghost too, with its wall coupling halved in the
+// tables: (a/2)(w - (-w)) = a (w - 0) exactly, its zero wall value.
 CANS_HD double ghost(int bc, double inner, double wrap)
 {
     return bc == 0 ? wrap : (bc == 1 ? inner : -inner);
+}
+
+// x and y: index and sign of the value that stands beyond the lower (lo) or
+// upper end of a line of n values.  Periodic wraps, Neumann mirrors,
+// Dirichlet mirrors with the sign flipped; a field on the faces of the axis
+// is zero beyond a Dirichlet face (sign 0) and mirrored about a Neumann face
+// it sits on (the second value from that end).
+CANS_HD void beyond(int bc, bool lo, int n, int &idx, double &sg)
+{
+    sg = 1.0;
+    switch (bc) {
+    case 0: idx = lo ? n - 1 : 0; break;
+    case 1: idx = lo ? 0 : n - 1; break;
+    case 2: idx = lo ? 0 : n - 1; sg = -1.0; break;
+    case 3: idx = lo ? 0 : n - 1; sg = 0.0; break;
+    default: idx = lo ? 1 : n - 2; break;
+    }
+}
+
+// the value beyond an end of the line through element e (index i, stride st)
+CANS_HD double across(int bc, bool lo, const double *p, size_t e, int i, int n, size_t st)
+{
+    int gi;
+    double sg;
+    beyond(bc, lo, n, gi, sg);
+    return sg * p[(ptrdiff_t)e + ((ptrdiff_t)gi - i) * (ptrdiff_t)st];
 }
 
 CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
@@ -183,10 +209,10 @@ CANS_HD double lap_point(const double *p, int i, int j, int k, const LapArgs &a)
              + a.zcf[k] * (q[sz] - c) - a.zaf[k] * (c - q[-(long)sz]) + a.shift * c;
     }
     const double c = p[e];
-    const double xm = i > 0 ? p[e - sx] : ghost(a.bc[0], c, p[e + (a.nx - 1) * sx]);
-    const double xp = i < a.nx - 1 ? p[e + sx] : ghost(a.bc[1], c, p[e - (a.nx - 1) * sx]);
-    const double ym = j > 0 ? p[e - sy] : ghost(a.bc[2], c, p[e + (a.ny - 1) * sy]);
-    const double yp = j < a.ny - 1 ? p[e + sy] : ghost(a.bc[3], c, p[e - (a.ny - 1) * sy]);
+    const double xm = i > 0 ? p[e - sx] : across(a.bc[0], true, p, e, i, a.nx, sx);
+    const double xp = i < a.nx - 1 ? p[e + sx] : across(a.bc[1], false, p, e, i, a.nx, sx);
+    const double ym = j > 0 ? p[e - sy] : across(a.bc[2], true, p, e, j, a.ny, sy);
+    const double yp = j < a.ny - 1 ? p[e + sy] : across(a.bc[3], false, p, e, j, a.ny, sy);
     const double zm = k > 0 ? p[e - sz] : ghost(a.bc[4], c, p[e + (a.nz - 1) * sz]);
     const double zp = k < a.nz - 1 ? p[e + sz] : ghost(a.bc[5], c, p[e - (a.nz - 1) * sz]);
     return (xm - 2.0 * c + xp) * a.idx2 + (ym - 2.0 * c + yp) * a.idy2

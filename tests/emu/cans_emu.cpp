@@ -24,13 +24,14 @@ struct NoSync {
 template <int KIND, bool FWD, int AXIS, typename T>
 void xform_k(const XGeom &g, int nx, int ny, int nz, std::vector<T> &a, const cx<T> *tw)
 {
-    // as the kernels: inverse real-DFT / DCT / DST synthesis stages its lines
-    // in the tile first
-    constexpr bool STAGED = !FWD && (KIND == K_P || KIND == K_NN || KIND == K_DD);
+    // as the kernels: transforms that read their input twice (inverse
+    // real-DFT / DCT / DST synthesis, the extended face lines) stage their
+    // lines in the tile first
+    constexpr bool STAGED = reads_twice(KIND, FWD);
     std::vector<cx<T>> b0(tile_slots(AXIS, g)), b1(tile_slots(AXIS, g));
     Tile<AXIS, T> ta{b0.data(), g.L, g.RS, g.psh}, tb{b1.data(), g.L, g.RS, g.psh};
     std::vector<T> out(a.size());
-    const int n = g.n;
+    const int n = g.nl;
     auto run = [&](auto gsrc, auto put) {
         if constexpr (STAGED) {
             for (int l = 0; l < g.L; ++l)
@@ -78,8 +79,8 @@ int xform(int kind, bool fwd, int axis, int nx, int ny, int nz, std::vector<T> &
 {
     const int n = axis == 0 ? nx : ny;
     XGeom g;
-    if (!make_geom(g, axis == 0 ? AX_X : AX_Y, n, sizeof(T), L, rmax)) return -2;
-    std::vector<cx<T>> tw = tw_as<T>(n);
+    if (!make_geom(g, axis == 0 ? AX_X : AX_Y, kind, n, sizeof(T), L, rmax)) return -2;
+    std::vector<cx<T>> tw = tw_as<T>(fft_len(kind, n));
 #define CASE(K)                                                                            \
     case K:                                                                                \
         if (axis == 0) {                                                                   \
@@ -91,7 +92,7 @@ int xform(int kind, bool fwd, int axis, int nx, int ny, int nz, std::vector<T> &
         }                                                                                  \
         break;
     switch (kind) {
-        CASE(K_P) CASE(K_NN) CASE(K_DD) CASE(K_ND) CASE(K_DN)
+        CASE(K_P) CASE(K_NN) CASE(K_DD) CASE(K_ND) CASE(K_DN) CASE(K_S1) CASE(K_C1) CASE(K_FDN) CASE(K_FND)
     }
 #undef CASE
     return 0;

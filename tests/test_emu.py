@@ -172,3 +172,63 @@ def test_c1_refine_converges():
     assert rel(p - O.weighted_mean(p, pr.dzf), po) < 1e-11
     # the update keeps the weighted mean pinned to FP64 accuracy
     assert abs(O.weighted_mean(p, pr.dzf)) < 1e-14 * np.abs(po).max()
+
+
+# --------------------------------------------------------------------------- #
+# Fields on the faces of x or y (codes 3 and 4): DST-I and DCT-I through the
+# odd / even extension of each line, the type-III face pairs as the DD / NN
+# transforms run the other way round.  The kernels' forward transform is
+# twice the oracle's T (its rows carry the factor 2 of the unnormalised
+# type-1 and type-3 forms) and B T = s I with s = 2(n+1), 2(n-1) or n.
+DF, NF = 3, 4
+FACE_SIZES = {O.K_FD: [1, 2, 4, 7, 11, 15, 47, 63, 127], O.K_FN: [2, 3, 4, 5, 9, 13, 17, 49, 65, 129],
+              O.K_FDN: [2, 4, 6, 8, 10, 16, 24, 48, 128], O.K_FND: [2, 4, 6, 8, 10, 16, 24, 48, 128]}
+FACE_BC = {O.K_FD: (DF, DF), O.K_FN: (NF, NF), O.K_FDN: (DF, NF), O.K_FND: (NF, DF)}
+
+
+def face_scale(kind, n):
+    return {O.K_FD: 2 * (n + 1), O.K_FN: 2 * (n - 1)}.get(kind, n)
+
+
+@pytest.mark.parametrize("kind,n", [(k, n) for k, ns in FACE_SIZES.items() for n in ns])
+def test_face_transforms(kind, n):
+    """Forward and inverse face transforms along x and y against the oracle,
+    FP64 and FP32, over every tile geometry the tuner may pick."""
+    rng = np.random.default_rng(10 * kind + n)
+    for axis in (0, 1):
+        f = rng.standard_normal((2, 5, n) if axis == 0 else (2, n, 7))
+        T = 2.0 * O.transform(f, axis, kind)
+        Bi = 0.5 * face_scale(kind, n) * O.transform(f, axis, kind, inverse=True)
+        assert rel(emu.xform(f, kind, True, axis), T) < 1e-13, axis
+        assert rel(emu.xform(f, kind, False, axis), Bi) < 1e-13, axis
+        assert rel(emu.xform(f, kind, True, axis, prec=32), T) < 3e-6, axis
+        tried = 0
+        for L in (1, 2, 4, 8, 16, 32, 64):
+            for rmax in (8, 4):
+                for fwd, ref in ((True, T), (False, Bi)):
+                    out = emu.xform_geom(f, kind, fwd, axis, 64, L, rmax)
+                    if out is not None:
+                        tried += 1
+                        assert rel(out, ref) < 1e-13, (axis, L, rmax, fwd)
+        assert tried > 0
+
+
+@pytest.mark.parametrize("yp", [(P, P), (D, N), (DF, DF), (NF, DF), (DF, NF)])
+@pytest.mark.parametrize("xp", [(DF, DF), (NF, NF), (DF, NF), (NF, DF)])
+def test_solve_face_located_xy(xp, yp):
+    """Face-located x (and y) fields: the library's tables, transforms, z
+    solve and residual stencil (refinement) against the oracle."""
+    nx = {(DF, DF): 15, (NF, NF): 17, (DF, NF): 16, (NF, DF): 16}[xp]
+    ny = {(P, P): 10, (D, N): 10, (DF, DF): 11, (NF, DF): 12, (DF, NF): 12}[yp]
+    nz = 7
+    zp = (D, N) if xp == (NF, NF) and yp == (P, P) else (N, N)
+    bc = xp + yp + zp
+    dzf = inputs.tanh_dzf(nz, 1.5, 2.0)
+    f = np.random.default_rng(sum(bc) + 60).standard_normal((nz, ny, nx))
+    po, mo = O.solve(f, bc, 0.3, 0.4, dzf)
+    assert mo == 0.0
+    pe, info = emu.solve(f, bc, 0.3, 0.4, dzf)
+    assert rel(pe, po) < 1e-12 and info[0] == 0.0
+    pr, info = emu.solve(f, bc, 0.3, 0.4, dzf, max_iter=6, tol=1e-12)
+    assert info[2] == 1 and info[3] <= 1e-12
+    assert rel(pr, po) < 1e-10

@@ -438,6 +438,69 @@ def test_face_located_z(nz, bc):
                 assert rel(pg, po) < TOL_REF
 
 
+DF, NF = 3, 4
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("shape,bc", [
+    ((63, 40, 24), (DF, DF, P, P, N, N)),       # DST-I along x (extended line of 128)
+    ((65, 48, 20), (NF, NF, D, D, N, N)),       # DCT-I along x
+    ((64, 47, 30), (DF, NF, DF, DF, D, N)),     # (3,4) along x, DST-I along y
+    ((96, 49, 16), (NF, DF, NF, NF, N, D)),     # (4,3) along x, DCT-I along y
+    ((90, 36, 50), (P, P, DF, NF, DF, DF)),     # (3,4) along y, face-located z too
+    ((1023, 64, 32), (DF, DF, P, P, N, N)),     # DST-I over 1024-point FFTs, many tiles
+    ((1025, 24, 40), (NF, NF, P, P, D, N)),     # DCT-I over 1024-point FFTs
+])
+def test_face_located_xy(shape, bc):
+    """Fields on the faces of x or y (DST-I, DCT-I and the type-III face
+    pairs), FP64 and FP32 + refinement, Poisson and Helmholtz, element by
+    element against the oracle."""
+    nx, ny, nz = shape
+    dz = inputs.tanh_dzf(nz + 1 if bc[4] == DF else nz, 1.5, 2.0)
+    dx, dy = 2 * np.pi / (nx + 1), np.pi / (ny + 1)
+    rng = np.random.default_rng(nx + 3 * ny + nz)
+    f = rng.standard_normal((nz, ny, nx))
+    for s in (0.0, -25.0):
+        say("face-located x/y", shape, bc, "shift", s)
+        po, mo = O.solve(f, bc, dx, dy, dz, shift=s)
+        assert mo == 0.0
+        for precision in ("fp64", "fp32_refine"):
+            plan = capi.Plan(nx, ny, nz, bc, dx, dy, dz, precision=precision, tol=1e-10, max_iter=6, shift=s)
+            fd = torch.from_numpy(f).cuda()
+            pd = torch.zeros_like(fd)
+            plan.solve(fd, pd)
+            torch.cuda.synchronize()
+            pg, info = pd.cpu().numpy(), plan.info()
+            plan.close()
+            assert info["removed_mean"] == 0.0
+            if precision == "fp64":
+                check_fp64(pg, f, bc, dx, dy, dz, po, shift=s, case=f"face-located x/y {shape} {bc} shift {s}")
+            else:
+                assert info["converged"] and info["residual"] <= 1e-10, info
+                ro = O.residual(pg, f, bc, dx, dy, dz, shift=s)
+                assert ro <= 1.5e-10 and abs(info["residual"] - ro) <= 1e-3 * ro + 1e-16
+                assert rel(pg, po) < TOL_REF
+
+
+def test_face_located_xy_rejections():
+    """What the face-located x/y pairs do not take: a (4,4) axis in an
+    otherwise singular problem, the dense transform, the projection step."""
+    dz = np.full(8, 0.1)
+    for kw in ({}, {"precision": "fp32_refine", "xform_x": "dense"}):
+        bc = (NF, NF, P, P, N, N) if not kw else (DF, NF, P, P, N, N)
+        nx = 65 if not kw else 128
+        with pytest.raises(capi.CansError) as e:
+            capi.Plan(nx, 32, 8, bc, 0.1, 0.1, dz, **kw)
+        assert e.value.code == -2
+    capi.Plan(65, 32, 8, (NF, NF, P, P, N, N), 0.1, 0.1, dz, shift=-1.0).close()
+    plan = capi.Plan(63, 32, 8, (DF, DF, P, P, N, N), 0.1, 0.1, dz)
+    a = [torch.zeros((8, 32, 63), dtype=torch.float64, device="cuda") for _ in range(4)]
+    with pytest.raises(capi.CansError) as e:
+        plan.project(*a, 0.1)
+    assert e.value.code == -2
+    plan.close()
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("shape,bc", [((48, 40, 36), (P, P, P, P, N, N)), ((50, 24, 30), (N, N, P, P, N, N)),
                                       ((40, 30, 24), (P, P, N, N, P, P)), ((30, 20, 17), (N, N, N, N, N, N)),

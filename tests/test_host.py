@@ -51,8 +51,16 @@ def _plan(nx, ny, nz, bc, dx=1.0, dy=1.0, dz=None, opts=None):
 @pytest.mark.parametrize("args,code", [
     ((8, 8, 8, (0, 1, 0, 0, 1, 1)), -1),      # periodic paired with Neumann
     ((8, 8, 8, (0, 0, 0, 0, 3, 1)), -1),      # face-located z paired with Neumann
-    ((8, 8, 8, (3, 3, 0, 0, 1, 1)), -1),      # a face-located field only along z
-    ((8, 8, 8, (0, 0, 0, 0, 4, 4)), -1),      # unknown boundary code
+    ((8, 8, 8, (3, 1, 0, 0, 1, 1)), -1),      # a face code paired with a cell code
+    ((8, 8, 8, (0, 0, 4, 2, 1, 1)), -1),
+    ((8, 8, 8, (0, 0, 0, 0, 4, 4)), -1),      # z takes only the Dirichlet face pair
+    ((8, 8, 8, (0, 0, 0, 0, 3, 4)), -1),
+    ((8, 8, 8, (0, 0, 0, 0, 5, 5)), -1),      # unknown boundary code
+    ((6, 8, 8, (3, 3, 0, 0, 1, 1)), -2),      # DST-I of 6: extended line of 14 (7 is no radix)
+    ((8, 8, 8, (4, 4, 0, 0, 2, 2)), -2),      # DCT-I of 8: extended line of 14
+    ((7, 8, 8, (3, 4, 0, 0, 1, 1)), -2),      # type-III face pair of odd length
+    ((9, 8, 8, (4, 4, 0, 0, 1, 1)), -2),      # a (4,4) axis in an otherwise singular problem
+    ((4096, 8, 4, (3, 3, 0, 0, 1, 1)), -2),   # extended line longer than 4096
     ((0, 8, 8, (0, 0, 0, 0, 1, 1)), -1),      # empty axis
     ((8, 8, 0, (0, 0, 0, 0, 1, 1)), -1),
     ((7, 8, 8, (0, 0, 0, 0, 1, 1)), -2),      # odd length
