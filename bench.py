@@ -123,7 +123,7 @@ def workload_text(name, pr, xform_x):
     """What is solved: sizes, boundary pairs, grid and rhs of the problem."""
     import numpy as np
 
-    code = "PNDF"  # F: Dirichlet on a z-face-located field
+    code = ["P", "N", "D", "Fd", "Fn"]  # Fd / Fn: Dirichlet / Neumann face of a face-located field
     bc = "/".join(code[pr.bc[2 * a]] + code[pr.bc[2 * a + 1]] for a in range(3))
     grid = "uniform z" if np.allclose(pr.dzf, pr.dzf[0]) else "tanh-stretched z (a=1.5)"
     rhs = ("divergence of a seeded N(0,1) staggered velocity" if pr.rhs_kind == "divergence"
@@ -313,9 +313,12 @@ def main():
     ap.add_argument("--face-z", action="store_true",
                     help="the field on the nz-1 interior z faces of the config's grid, zero on the walls, "
                          "uniform random rhs (a side workload: with --solve-only or --fp64-only)")
+    ap.add_argument("--face-x", action="store_true",
+                    help="the field on the nx-1 interior x faces of the config's grid with walls in x (DST-I "
+                         "along x), uniform random rhs (a side workload: with --solve-only or --fp64-only)")
     args = ap.parse_args()
-    if (args.shift != 0.0 or args.face_z) and not (args.solve_only or args.fp64_only):
-        ap.error("--shift and --face-z time side workloads: add --solve-only or --fp64-only")
+    if (args.shift != 0.0 or args.face_z or args.face_x) and not (args.solve_only or args.fp64_only):
+        ap.error("--shift, --face-z and --face-x time side workloads: add --solve-only or --fp64-only")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -349,6 +352,11 @@ def main():
         # cells (the nz cell widths stay the plan's dz)
         pr = dataclasses.replace(pr, nz=pr.nz - 1, bc=tuple(pr.bc[:4]) + (3, 3), rhs_kind="uniform",
                                  seed=pr.seed + 1000)
+    if args.face_x:
+        # a velocity component on the x faces of the config's cells, between
+        # walls in x (zero on them): nx-1 unknowns, a DST-I of 2nx-real lines
+        pr = dataclasses.replace(pr, nx=pr.nx - 1, bc=(3, 3) + tuple(pr.bc[2:]), rhs_kind="uniform",
+                                 seed=pr.seed + 2000)
     say(f"[bench] generating {args.config} rhs {pr.nx}x{pr.ny}x{pr.nz}")
     f = pr.rhs()
     fd = torch.from_numpy(f).cuda()
@@ -367,7 +375,8 @@ def main():
             return
         ms64, _ = time_solves(plan64, fd, pd, args.steps, args.warmup, torch)
         print(json.dumps({"fp64_ms_per_step": ms64, "value": npts / (ms64 * 1e-3), "shift": args.shift,
-                          "face_z": args.face_z, "grid": [pr.nx, pr.ny, pr.nz]}), flush=True)
+                          "face_z": args.face_z, "face_x": args.face_x, "grid": [pr.nx, pr.ny, pr.nz]}),
+              flush=True)
         return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
@@ -396,8 +405,9 @@ def main():
                    "grid_points": npts, "corrections": info["iterations"], "graph": args.graph,
                    "residual": info["residual"], "residual_inf": info["residual_inf"], "wall_s": wall},
     }
-    if args.shift != 0.0 or args.face_z:
-        out["config"].update({"shift": args.shift, "face_z": args.face_z, "grid": [pr.nx, pr.ny, pr.nz]})
+    if args.shift != 0.0 or args.face_z or args.face_x:
+        out["config"].update({"shift": args.shift, "face_z": args.face_z, "face_x": args.face_x,
+                              "grid": [pr.nx, pr.ny, pr.nz]})
     if args.solve_only:
         print(json.dumps(out), flush=True)
         return

@@ -102,8 +102,9 @@ class Problem:
 def _axis_kind(lo, hi):
     if lo == P or hi == P:
         return "P" if lo == hi == P else None
-    # code 3 on both z faces: a z-face-located field, zero on the walls
-    return {(N, N): "NN", (D, D): "DD", (N, D): "ND", (D, N): "DN", (3, 3): "FD"}.get((lo, hi))
+    # codes 3 and 4: a field on the faces of the axis (Dirichlet / Neumann face)
+    return {(N, N): "NN", (D, D): "DD", (N, D): "ND", (D, N): "DN", (3, 3): "FD", (4, 4): "FN",
+            (3, 4): "FDN", (4, 3): "FND"}.get((lo, hi))
 
 
 def _is_singular(bc) -> bool:
