@@ -313,6 +313,9 @@ def main():
     ap.add_argument("--face-z", action="store_true",
                     help="the field on the nz-1 interior z faces of the config's grid, zero on the walls, "
                          "uniform random rhs (a side workload: with --solve-only or --fp64-only)")
+    ap.add_argument("--max-iter", type=int, default=4,
+                    help="most corrections the refinement plan enqueues per solve (cans_opts.max_iter); those "
+                         "after convergence are launched and return at once")
     ap.add_argument("--face-x", action="store_true",
                     help="the field on the nx-1 interior x faces of the config's grid with walls in x (DST-I "
                          "along x), uniform random rhs (a side workload: with --solve-only or --fp64-only)")
@@ -380,7 +383,8 @@ def main():
         return
     say("[bench] fp32+refine plan")
     plan = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision="fp32_refine",
-                     tol=1e-10, max_iter=4, autotune=not args.no_autotune, xform_x=args.xform_x, graph=args.graph,
+                     tol=1e-10, max_iter=args.max_iter, autotune=not args.no_autotune, xform_x=args.xform_x,
+                     graph=args.graph,
                      shift=args.shift)
     if args.kernel_only:
         # the stages before it fill the plan's spectral field as in a solve
@@ -401,7 +405,7 @@ def main():
         "metric": METRIC, "value": npts / (ms * 1e-3), "unit": "grid pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": workload_text(args.config, pr, args.xform_x),
+        "config": {"workload": workload_text(args.config, pr, plan.xform_mode(0)),
                    "grid_points": npts, "corrections": info["iterations"], "graph": args.graph,
                    "residual": info["residual"], "residual_inf": info["residual_inf"], "wall_s": wall},
     }

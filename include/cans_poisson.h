@@ -108,13 +108,23 @@ typedef struct cans_opts {
     double tol;         /* FP32_REFINE: stop when the relative residual
                            ||Pi f - L p||_2 / ||Pi f||_2 <= tol; default 1e-10 */
     int max_iter;       /* FP32_REFINE: most refinement steps enqueued per
-                           solve (0..16); default 4 */
+                           solve (0..16); default 4.  The solve is enqueued
+                           without a host synchronisation, so all max_iter
+                           steps are launched; those after convergence return
+                           at once but still cost their six launches (about
+                           12 us per step on MI355X, which is what separates
+                           max_iter 1 and 4 on a 32^3 grid: 0.108 vs 0.144
+                           ms).  Small problems that converge in one step
+                           gain from max_iter 1 or 2. */
     int autotune;       /* 1: at plan time, time candidate transform tiles
                            (lines per tile, radix-8 or radix-4 first) for
                            every transform kernel the plan uses on the
-                           current device and keep the fastest (allocates a
-                           temporary field and synchronises); 0: built-in
-                           choice.  Default 0. */
+                           current device and keep the fastest; with
+                           xform_x AUTO on an FP32_REFINE plan whose x axis
+                           the dense form takes, also time whole refined
+                           solves with either x form and keep the faster
+                           (allocates temporary fields and synchronises);
+                           0: built-in choice (FFT).  Default 0. */
     int graph;          /* 1: cans_poisson_solve records the solve's kernel
                            sequence into a HIP graph on its first call with a
                            given (rhs, p) pair and replays it on later calls
@@ -287,6 +297,17 @@ const char *cans_status_string(int code);
 
 /* Bytes of device workspace the plan holds. */
 size_t cans_poisson_workspace_bytes(cans_plan_t plan);
+
+/*
+ * The form a single-problem plan evaluates the transform of an axis in
+ * (axis 0 = x, 1 = y): CANS_XFORM_FFT or CANS_XFORM_DENSE, as the options
+ * fixed it or, for CANS_XFORM_AUTO with autotune = 1 on a refinement plan
+ * whose x axis the dense form takes, as the plan-time timing of whole
+ * refined solves chose it (the transforms F^x, F^y of eq. (poi_reduced)
+ * evaluated as FFTs or as dense matrix products); CANS_ERR_INVALID_ARG for
+ * a bad handle, axis or a batched plan.
+ */
+int cans_poisson_xform_mode(cans_plan_t plan, int axis);
 
 /*
  * Run one stage of a plan on device arrays of nx*ny*nz doubles (test and

@@ -38,7 +38,7 @@ EXPORTS = ["cans_default_opts", "cans_poisson_plan", "cans_poisson_plan_ex", "ca
            "cans_poisson_get_info", "cans_poisson_destroy", "cans_status_string",
            "cans_poisson_workspace_bytes", "cans_poisson_debug_stage", "cans_poisson_plan_batched",
            "cans_poisson_solve_batched", "cans_poisson_get_info_batched", "cans_poisson_project",
-           "cans_poisson_project_ex", "cans_poisson_solve_noalloc"]
+           "cans_poisson_project_ex", "cans_poisson_solve_noalloc", "cans_poisson_xform_mode"]
 
 
 class CansOpts(ctypes.Structure):
@@ -91,6 +91,7 @@ def load() -> ctypes.CDLL:
         "cans_poisson_destroy": ([vp], None),
         "cans_status_string": ([i], ctypes.c_char_p),
         "cans_poisson_workspace_bytes": ([vp], ctypes.c_size_t),
+        "cans_poisson_xform_mode": ([vp, i], i),
         "cans_poisson_debug_stage": ([vp, i, vp, vp, vp], i),
         "cans_poisson_plan_batched": ([pp, i, ctypes.POINTER(CansDesc), ctypes.POINTER(CansOpts)], i),
         "cans_poisson_solve_batched": ([vp, pp, pp, vp], i),
@@ -230,6 +231,14 @@ class Plan:
     @property
     def workspace_bytes(self) -> int:
         return int(self._lib.cans_poisson_workspace_bytes(self._h))
+
+    def xform_mode(self, axis: int) -> str:
+        """Form of the transform along axis 0 (x) or 1 (y) the plan uses:
+        "fft" or "dense" (``cans_poisson_xform_mode``)."""
+        m = int(self._lib.cans_poisson_xform_mode(self._h, int(axis)))
+        if m < 0:
+            raise CansError(m, "cans_poisson_xform_mode")
+        return {XFORM_FFT: "fft", XFORM_DENSE: "dense"}[m]
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -147,10 +147,29 @@ int build_dense(cans_plan_s *pl, Axis &a)
     return CANS_OK;
 }
 
+int solve_refine(const Problem &pb, const Work &w, const cans_opts &o, const double *rhs, double *p, hipStream_t s);
+
+// Deterministic pseudo-random values in [-1, 1) (a splitmix64-style mix of
+// the index): the scratch rhs of the plan-time choice of the x form.
+__global__ void k_fill_unit(double *a, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long h = (i + 1) * 0x9E3779B97F4A7C15ull;
+        h = (h ^ (h >> 30)) * 0xBF58476D1CE4E5B9ull;
+        h = (h ^ (h >> 27)) * 0x94D049BB133111EBull;
+        h ^= h >> 31;
+        a[i] = (double)(h >> 11) * 0x1.0p-52 - 1.0;
+    }
+}
+
 // Plan-time tuning of the transform tiles: for every transform kernel the
 // plan uses (x/y, forward/inverse, its precision), time the default tile and
 // the candidates with a quarter .. four times the lines per tile, each with
 // radix-8-first and radix-4-first plans, on a scratch field; keep the fastest.
+// Then, for a refinement plan whose x form is left to the library (AUTO) and
+// whose x axis the dense matrix-core form takes, time whole refined solves of
+// a scratch rhs with the FFT and with the dense x form and keep the faster
+// (the forms differ in kernel time and in the corrections they need).
 int autotune(cans_plan_s *pl, Problem &pb)
 {
     (void)pl;
@@ -211,6 +230,24 @@ int autotune(cans_plan_s *pl, Problem &pb)
             }
             tune(pb.ay.gy32[1], AX_Y, pb.ay, 4, [&] { return launch_y_32(pb, true, pb.ws.a32, nullptr, st); });
             tune(pb.ay.gy32[0], AX_Y, pb.ay, 4, [&] { return launch_y_32(pb, false, pb.ws.a32, nullptr, st); });
+            if (pl->opts.xform_x == CANS_XFORM_AUTO && dense_ok(pb.ax.kind, pb.nx)) {
+                double *p64 = nullptr;
+                if (hipMalloc(&p64, N * sizeof(double)) != hipSuccess) rc = CANS_ERR_ALLOC;
+                if (rc == CANS_OK) {
+                    hipLaunchKernelGGL(k_fill_unit, dim3(1024), dim3(256), 0, st, s64, N);
+                    if (hipGetLastError() != hipSuccess) rc = CANS_ERR_HIP;
+                }
+                if (rc == CANS_OK) rc = build_dense(pl, pb.ax);
+                if (rc == CANS_OK) {
+                    auto solve = [&] { return solve_refine(pb, pb.ws, pl->opts, s64, p64, st); };
+                    const float t_dense = timeit(solve);
+                    pb.ax.dense = false;
+                    const float t_fft = timeit(solve);
+                    pb.ax.dense = t_dense < t_fft;
+                }
+                (void)hipStreamSynchronize(st);
+                if (p64) (void)hipFree(p64);
+            }
         }
         if (hipStreamSynchronize(st) != hipSuccess) rc = CANS_ERR_HIP;
     }
@@ -264,13 +301,19 @@ int build_problem(cans_plan_s *pl, Problem &pb, int nx, int ny, int nz, const in
         CANS_TRY(alloc(pl, &pb.ws.partials, kNP * (size_t)(pb.ny + 8) * pb.nz));
         CANS_TRY(alloc(pl, &pb.ws.sums, kNP * 256));
     }
-    if (pl->opts.autotune) CANS_TRY(autotune(pl, pb));
     std::vector<double> info(I_SIZE, 0.0);
     CANS_TRY(upload(pl, &pb.ws.info, info.data(), I_SIZE));
     int zero = 0;
     CANS_TRY(upload(pl, &pb.ws.flag, &zero, 1));
     const unsigned zc2[2] = {0u, 0u};
     CANS_TRY(upload(pl, &pb.ws.zctr, zc2, 2));
+    if (pl->opts.autotune) {
+        CANS_TRY(autotune(pl, pb));
+        // the tuning solves leave their record: start from a clean one
+        if (hipMemcpy(pb.ws.info, info.data(), I_SIZE * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pb.ws.flag, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            return CANS_ERR_HIP;
+    }
     return CANS_OK;
 }
 
@@ -675,6 +718,12 @@ int cans_poisson_get_info_batched(cans_plan_t plan, int index, cans_info *out)
 }
 
 size_t cans_poisson_workspace_bytes(cans_plan_t plan) { return plan ? plan->bytes : 0; }
+
+int cans_poisson_xform_mode(cans_plan_t plan, int axis)
+{
+    if (!plan || plan->probs.size() != 1 || (axis != 0 && axis != 1)) return CANS_ERR_INVALID_ARG;
+    return axis == 0 && plan->probs[0].ax.dense ? CANS_XFORM_DENSE : CANS_XFORM_FFT;
+}
 
 int cans_poisson_debug_stage(cans_plan_t plan, int stage, const double *in, double *out, hipStream_t stream)
 {

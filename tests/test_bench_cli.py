@@ -33,6 +33,6 @@ def test_workload_text_and_digest():
     pr = inputs.config("c3")
     assert "1024x512x384, bc PP/PP/NN" in bench.workload_text("c3", pr, "auto")
     face = dataclasses.replace(pr, nz=pr.nz - 1, bc=tuple(pr.bc[:4]) + (3, 3), rhs_kind="uniform")
-    assert "1024x512x383, bc PP/PP/FF" in bench.workload_text("c3", face, "auto")
+    assert "1024x512x383, bc PP/PP/FdFd" in bench.workload_text("c3", face, "auto")
     d = bench.source_digest()
     assert len(d) == 16 and int(d, 16) >= 0

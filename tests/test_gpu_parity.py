@@ -325,6 +325,38 @@ def test_autotuned_plans(name):
     assert rel(demean(pg, pr.bc, pr.dzf), po) < TOL_REF
 
 
+def test_autotune_x_form_choice():
+    """xform_x AUTO with autotune on a refinement plan whose x axis the dense
+    form takes: the plan times whole refined solves with either x form, keeps
+    one, reports it, and solves to the oracle with it; fixed forms report
+    themselves."""
+    nx, ny, nz = 512, 48, 32
+    bc = (D, N, P, P, D, D)
+    dz = np.full(nz, 1.0 / nz)
+    f = np.random.default_rng(23).uniform(-1, 1, (nz, ny, nx))
+    po, _ = O.solve(f, bc, 1.0 / nx, 1.0 / ny, dz)
+    fd = torch.from_numpy(f).cuda()
+    for xf, want in (("auto", None), ("dense", "dense"), ("fft", "fft")):
+        plan = capi.Plan(nx, ny, nz, bc, 1.0 / nx, 1.0 / ny, dz, precision="fp32_refine", tol=1e-10,
+                         max_iter=6, xform_x=xf, autotune=xf == "auto")
+        mode = plan.xform_mode(0)
+        say("x form", xf, "->", mode)
+        assert mode == want if want else mode in ("fft", "dense")
+        assert plan.xform_mode(1) == "fft"
+        pd = torch.zeros_like(fd)
+        plan.solve(fd, pd)
+        torch.cuda.synchronize()
+        info = plan.info()
+        plan.close()
+        assert info["converged"] and info["residual"] <= 1e-10, (xf, info)
+        assert rel(pd.cpu().numpy(), po) < TOL_REF
+    plan = capi.Plan(nx, ny, nz, bc, 1.0 / nx, 1.0 / ny, dz, autotune=True)
+    assert plan.xform_mode(0) == "fft"
+    with pytest.raises(capi.CansError):
+        plan.xform_mode(2)
+    plan.close()
+
+
 def test_graph_mode_matches_direct_launches():
     """opts.graph: the first solve with a (rhs, p) pair records the kernel
     sequence into a HIP graph and later solves replay it.  Replays (with
