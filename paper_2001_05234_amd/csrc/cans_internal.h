@@ -88,6 +88,92 @@ struct Problem {
     size_t npts() const { return (size_t)nx * ny * nz; }
 };
 
+// ---- grouped launches of a batch -------------------------------------------
+// A batched plan runs each step of the solve as one launch per kernel variant
+// over all the problems that take it (the same transform kind, or the same z
+// solve shape).  Each block finds its problem in `start` (first block of each
+// problem, multiples of 8) and reads the problem's job record.
+struct XJob {            // x transform of one problem
+    const void *in;
+    void *out;
+    long nlines;
+    const void *tw;
+    const double *info;
+    const int *done;
+    const double *dzf;
+    double *wsum_part;
+    int ny;
+    unsigned nblk;       // blocks of this problem (the launch may give it a few more, which return)
+    XGeom g;
+};
+struct YJob {            // y transform of one problem, in place
+    void *data;
+    const void *tw;
+    const int *done;
+    int nx, ny, ntx;
+    unsigned nblk;
+    XGeom g;
+};
+struct ZJob {            // partitioned z solve of one problem
+    void *data;
+    const int *done;
+    int S;               // its segments (the launch's blocks may hold more waves)
+    unsigned nblk;
+    ZArgs a;
+};
+struct RJob {            // residual pass of one problem (fused with the x transform, or norms only)
+    const double *f, *p;
+    float *out;
+    const void *tw;
+    const double *dzf, *info;
+    double *partials;
+    const int *done;
+    int H, bpp, L, rows_off;
+    unsigned nblk;
+    LapArgs la;
+    XGeom g;
+};
+struct FJob {            // per-problem reductions: reset, rhs mean, convergence check
+    double *partials;
+    double *info;
+    int *flag;
+    int nb_mean, nb_xfwd, nb_norm;   // partials of the first x transform, the fused and the norm pass
+    int singular;
+    double inv_wvol;
+};
+
+// One grouped launch: its device tables and shape.
+struct GroupLaunch {
+    int key = 0;                 // kernel variant (transform kind, or z shape code)
+    int np = 0;                  // problems
+    unsigned blocks = 0;         // grid
+    int threads = kThreads;
+    size_t lds = 0;              // dynamic LDS: the largest member's
+    const void *jobs = nullptr;  // device job records
+    const unsigned *start = nullptr;
+};
+
+int launch_x_fwd_32_grp(const GroupLaunch &gl, hipStream_t s);
+int launch_x_inv_32_grp(const GroupLaunch &gl, bool update, hipStream_t s);
+int launch_x_f64_grp(const GroupLaunch &gl, bool fwd, hipStream_t s);
+int launch_y_32_grp(const GroupLaunch &gl, bool fwd, hipStream_t s);
+int launch_y_f64_grp(const GroupLaunch &gl, bool fwd, hipStream_t s);
+int launch_zsolve_grp(const GroupLaunch &gl, bool fp32, hipStream_t s);
+int launch_resid_xfwd_grp(const GroupLaunch &gl, hipStream_t s);
+int launch_resid_norm_grp(const GroupLaunch &gl, hipStream_t s);
+int launch_reset_grp(const FJob *jobs, int np, hipStream_t s);
+int launch_mean_rhs_grp(const FJob *jobs, int np, hipStream_t s);
+int launch_finalize_grp(const FJob *jobs, int np, int which, int check, int max_iter, double tol, hipStream_t s);
+// job records (and, for z, the variant key and block shape; key < 0: this
+// problem's z solve is not a partitioned one and runs on its own)
+ZJob zjob_of(const Problem &pb, const Work &w, void *data, double *removed, const int *done, bool fp32, int &key,
+             int &threads, unsigned &nblk);
+RJob rjob_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out, const int *done,
+               size_t &lds);
+RJob rjob_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done, size_t &lds);
+// largest number of block partials a grouped check reduces in its one block
+constexpr int kDirectReduce = 4096;
+
 // ---- launchers (k_xform.hip, k_zsolve.hip, k_resid.hip, k_project.hip) -----
 // x transform of nlines contiguous lines; dir 1 forward, 0 inverse.
 // Tin/Tout: double or float; epi 0 store, 1 update p += v - info[I_MEANP].

@@ -12,25 +12,45 @@ namespace cans {
 // neighbours) and the same rows one plane up and down (z neighbours) are read
 // by the same XCD close in time and come from its L2: each p value reaches
 // HBM about once.  H is ceil(ny/8) rounded up to a multiple of L.
+// Short rows (nx <= kFlatMaxN) take the flat form instead: block b takes the
+// L consecutive rows (x lines j + ny k, across planes) from b L on, and forms
+// their residual in groups of up to G rows of one plane spread over the
+// block's threads (a slice of a small grid would leave most XCDs idle, and a
+// short row most threads).  RSlice.H = 0 marks it, with bpp = G.
 struct RSlice {
-    int L, H, bpp;   // rows per block, slice height, blocks per plane and slice
+    int L, H, bpp;   // rows per block, slice height, blocks per plane and slice (flat: 0, G)
 };
+
+constexpr int kFlatMaxN = 512;
+constexpr int kResidU = 4;                       // points of a row per thread and chunk
+constexpr int kResidChunk = kResidU * kThreads;  // 1024
+constexpr int kRowsD = 2 * (kResidChunk + 4);    // doubles of the `rows` LDS buffer (either form)
+
+// rows of a flat group: as many as fill a chunk, with their two neighbour
+// rows and ghosts inside `rows`
+static __host__ __device__ inline int flat_group(int n)
+{
+    const int g1 = kResidChunk / n, g2 = kRowsD / (n + 2) - 2;
+    const int g = g1 < g2 ? g1 : g2;
+    return g > 1 ? g : 1;
+}
 
 static inline RSlice rslice(const Problem &pb, int L)
 {
+    if (pb.nx <= kFlatMaxN) return RSlice{L, 0, flat_group(pb.nx)};
     const int h8 = (pb.ny + 7) / 8;
     const int H = (h8 + L - 1) / L * L;
     return RSlice{L, H, H / L};
 }
 
-static inline int rslice_blocks(const Problem &pb, const RSlice &rs) { return 8 * pb.nz * rs.bpp; }
+static inline int rslice_blocks(const Problem &pb, const RSlice &rs)
+{
+    if (rs.H == 0) return (int)(((long)pb.ny * pb.nz + rs.L - 1) / rs.L);
+    return 8 * pb.nz * rs.bpp;
+}
 
 // rows of the norm-only kernel (x lines per block)
-static inline int norm_rows(const Problem &pb)
-{
-    (void)pb;
-    return 2;
-}
+static inline int norm_rows(const Problem &pb) { return pb.nx <= kFlatMaxN ? flat_group(pb.nx) : 2; }
 
 // The residual r = (f - mf) - L_h p (eq. (poi), plus the plan's shift) of the
 // rows j0 .. j0 + nr - 1 (nr <= 2) of plane k, block-wide, in chunks of
@@ -40,13 +60,10 @@ static inline int norm_rows(const Problem &pb)
 // boundary: periodic wraps, Neumann mirrors, Dirichlet mirrors with the sign
 // flipped; a face-located field is zero beyond a Dirichlet face and mirrored
 // about a Neumann face), so every global load is in flight at once.  The rows themselves
-// go to LDS (`rows`, 2 (kResidChunk + 2) doubles) for the x neighbours; the
+// go to LDS (`rows`, 2 (kResidChunk + 2) of its kRowsD doubles) for the x neighbours; the
 // planes above and below and f are loaded after the barrier, again all at
 // once.  The arithmetic per point is lap_point's.  put(l, e, r) receives every
 // residual; acc accumulates the block's partial sums.
-constexpr int kResidU = 4;                       // points of a row per thread and chunk
-constexpr int kResidChunk = kResidU * kThreads;  // 1024
-
 struct RAcc {
     double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
 };
@@ -161,8 +178,161 @@ static __device__ inline void rslice_of(unsigned b, int H, int bpp, int L, int n
     lv = (k < nz && j0 < ny) ? min(L, ny - j0) : 0;
 }
 
+// The flat form of the residual: rows j0 .. j0 + nr - 1 of plane k with
+// nr nx <= kResidChunk, one point per thread and slot.  The nr rows and the
+// rows next to them (by the y rule of `beyond`) go to `rows` first (stride
+// nx + 2, an x ghost at each end), every load in flight at once; then the x
+// ghosts; then each thread loads the planes above and below and f of its
+// points, all at once, and forms lap_point's expression from LDS.
+template <typename Put>
+__device__ void resid_rows_flat(const double *__restrict__ f, const double *__restrict__ p, int k, int j0, int nr,
+                                const LapArgs &la, double mf, double wk, double *rows, Put put, RAcc &acc)
+{
+    const int n = la.nx, ny = la.ny, nz = la.nz;
+    const size_t sy = (size_t)n, sz = (size_t)n * ny;
+    const double *pk = p + sz * k;
+    const int t = (int)threadIdx.x, rs = n + 2;
+    const unsigned mag = mag_of((unsigned)n);
+    // the rows next to the group: ordinary rows, or by the y rule beyond a face
+    int jlo = j0 - 1, jhi = j0 + nr;
+    double slo = 1.0, shi = 1.0;
+    if (jlo < 0) beyond(la.bc[2], true, ny, jlo, slo);
+    if (jhi >= ny) beyond(la.bc[3], false, ny, jhi, shi);
+    constexpr int SU = 2 * kResidU;  // (nr + 2) nx <= kResidChunk + 2 kFlatMaxN values, SU a thread
+    const int tot = (nr + 2) * n;
+    double v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const int idx = min(t + u * kThreads, tot - 1);  // clamped: every load issued unconditionally
+        const int r = (int)udiv((unsigned)idx, (unsigned)n, mag), e = idx - r * n;
+        const int j = r == 0 ? jlo : (r == nr + 1 ? jhi : j0 + r - 1);
+        const double sg = r == 0 ? slo : (r == nr + 1 ? shi : 1.0);
+        v[u] = sg * pk[sy * j + e];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const int idx = t + u * kThreads;
+        if (idx < tot) {
+            const int r = (int)udiv((unsigned)idx, (unsigned)n, mag), e = idx - r * n;
+            rows[r * rs + 1 + e] = v[u];
+        }
+    }
+    __syncthreads();
+    if (t < 2 * nr) {  // x ghosts of the group's own rows
+        double *row = rows + (1 + (t >> 1)) * rs + 1;
+        if ((t & 1) == 0) row[-1] = across(la.bc[0], true, row, 0, 0, n, 1);
+        else row[n] = across(la.bc[1], false, row, n - 1, n - 1, n, 1);
+    }
+    __syncthreads();
+    const double *zm_pl = k > 0 ? pk - sz : p + sz * (nz - 1);  // wrap plane at a boundary
+    const double *zp_pl = k < nz - 1 ? pk + sz : p;
+    const bool zm_in = k > 0, zp_in = k < nz - 1;
+    const double zaf = la.zaf[k], zcf = la.zcf[k];
+    const double *fk = f + sz * k;
+    const int np = nr * n;
+    double zmv[kResidU], zpv[kResidU], fvv[kResidU];
+    int rr[kResidU], ee[kResidU];
+#pragma unroll
+    for (int u = 0; u < kResidU; ++u) {
+        const int idx = min(t + u * kThreads, np - 1);
+        const int r = (int)udiv((unsigned)idx, (unsigned)n, mag), e = idx - r * n;
+        rr[u] = r;
+        ee[u] = e;
+        const size_t o = sy * (j0 + r) + e;
+        zmv[u] = zm_pl[o];
+        zpv[u] = zp_pl[o];
+        fvv[u] = fk[o];
+    }
+#pragma unroll
+    for (int u = 0; u < kResidU; ++u) {
+        if (t + u * kThreads < np) {
+            const double *q = rows + (rr[u] + 1) * rs + 1 + ee[u];
+            const double cc = q[0];
+            const double xm = q[-1], xp = q[1], ym = q[-rs], yp = q[rs];
+            const double zm = zm_in ? zmv[u] : ghost(la.bc[4], cc, zmv[u]);
+            const double zp = zp_in ? zpv[u] : ghost(la.bc[5], cc, zpv[u]);
+            const double fv = fvv[u] - mf;
+            const double lap = (xm - 2.0 * cc + xp) * la.idx2 + (ym - 2.0 * cc + yp) * la.idy2 +
+                               zcf * (zp - cc) - zaf * (cc - zm) + la.shift * cc;
+            const double r = fv - lap;
+            put(rr[u], ee[u], r);
+            acc.srr += r * r;
+            acc.sff += fv * fv;
+            acc.rmax = fmax(acc.rmax, fabs(r));
+            acc.fmx = fmax(acc.fmx, fabs(fv));
+            acc.spw += wk * cc;
+        }
+    }
+    __syncthreads();  // `rows` free for the next group
+}
+
+// The residual rows of block blk in either mapping (H > 0: XCD slices, rows
+// of one plane in pairs; H = 0: flat, bpp = G rows a group).  put(l, e, r)
+// receives line l of the block; line0 and lv give its first line and count.
+template <typename Put>
+__device__ __forceinline__ void resid_block(const double *__restrict__ f, const double *__restrict__ p, int H,
+                                            int bpp, int L, const LapArgs &la, double mf,
+                                            const double *__restrict__ dzf, double *rows, unsigned blk, Put put,
+                                            RAcc &acc, long &line0, int &lv)
+{
+    const int ny = la.ny;
+    if (H > 0) {
+        int k, j0;
+        rslice_of(blk, H, bpp, L, ny, la.nz, k, j0, lv);
+        line0 = (long)k * ny + j0;
+        for (int l0 = 0; l0 < lv; l0 += 2)
+            resid_pair(f, p, k, j0 + l0, min(2, lv - l0), la, mf, dzf[k], rows,
+                       [&](int l, int e, double r) { put(l0 + l, e, r); }, acc);
+        return;
+    }
+    const long nlines = (long)ny * la.nz;
+    line0 = (long)blk * L;
+    lv = line0 < nlines ? (int)min((long)L, nlines - line0) : 0;
+    for (int l0 = 0; l0 < lv;) {
+        const long line = line0 + l0;
+        const int k = (int)(line / ny), j = (int)(line - (long)k * ny);
+        const int nr = min(min(bpp, lv - l0), ny - j);
+        resid_rows_flat(f, p, k, j, nr, la, mf, dzf[k], rows, [&](int l, int e, double r) { put(l0 + l, e, r); },
+                        acc);
+        l0 += nr;
+    }
+}
+
 // The residual fused with the forward x transform of its rows (FP32 out);
 // block partials: sums of |r|^2, |f - mean|^2, dzf p; maxima of |r|, |f - mean|.
+// The bodies take the block index, so that one launch can serve one problem
+// (blk = blockIdx.x) or a group of problems (the *_grp kernels).
+template <int KIND>
+__device__ __forceinline__ void resid_xfwd_body(const double *__restrict__ f, const double *__restrict__ p,
+                                                float *out, int H, int bpp, const XGeom &g, int rows_off,
+                                                const cx<float> *__restrict__ tw, const LapArgs &la,
+                                                const double *__restrict__ dzf, const double *__restrict__ info,
+                                                double *__restrict__ partials, const int *__restrict__ done,
+                                                unsigned blk)
+{
+    if (*done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile<AX_X, float> tile{reinterpret_cast<cx<float> *>(smem), g.L, g.RS, g.psh};
+    double *rows = reinterpret_cast<double *>(smem + rows_off);  // after the transform tile
+    const int n = g.nl, L = g.L;
+    RAcc acc;
+    long line0;
+    int lv;
+    resid_block(f, p, H, bpp, L, la, info[I_REMOVED], dzf, rows, blk,
+                [&](int l, int e, double r) { tile_real(tile, e, l) = (float)r; }, acc, line0, lv);
+    if (lv > 0) {
+        for (int idx = threadIdx.x; idx < (L - lv) * n; idx += kThreads)
+            tile_real(tile, idx % n, lv + idx / n) = 0.f;
+        __syncthreads();
+        auto src = [&](int e, int l) -> float { return tile_real(tile, e, l); };
+        auto put = [&](int q, int l, float v) {
+            if (l < lv) out[(size_t)(line0 + l) * n + q] = v;
+        };
+        tile_transform<KIND, true, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    }
+    put_partial(partials, blk, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restrict__ f,
                                                          const double *__restrict__ p, float *out, int H, int bpp,
@@ -173,34 +343,26 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
                                                          double *__restrict__ partials,
                                                          const int *__restrict__ done)
 {
-    if (*done) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile<AX_X, float> tile{reinterpret_cast<cx<float> *>(smem), g.L, g.RS, g.psh};
-    double *rows = reinterpret_cast<double *>(smem + rows_off);  // after the transform tile
-    const int n = g.nl, L = g.L;
-    int k, j0, lv;
-    rslice_of(blockIdx.x, H, bpp, L, la.ny, la.nz, k, j0, lv);
-    RAcc acc;
-    if (lv > 0) {
-        const double mf = info[I_REMOVED];
-        for (int l0 = 0; l0 < lv; l0 += 2)
-            resid_pair(f, p, k, j0 + l0, min(2, lv - l0), la, mf, dzf[k], rows,
-                       [&](int l, int e, double r) { tile_real(tile, e, l0 + l) = (float)r; }, acc);
-        for (int idx = threadIdx.x; idx < (L - lv) * n; idx += kThreads)
-            tile_real(tile, idx % n, lv + idx / n) = 0.f;
-        __syncthreads();
-        const long line0 = (long)k * la.ny + j0;
-        auto src = [&](int e, int l) -> float { return tile_real(tile, e, l); };
-        auto put = [&](int q, int l, float v) {
-            if (l < lv) out[(size_t)(line0 + l) * n + q] = v;
-        };
-        tile_transform<KIND, true, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
-    }
-    put_partial(partials, blockIdx.x, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
+    resid_xfwd_body<KIND>(f, p, out, H, bpp, g, rows_off, tw, la, dzf, info, partials, done, blockIdx.x);
 }
 
 // Residual norms only (the check after a correction): the same block
 // partials over norm_rows() rows a block.
+__device__ __forceinline__ void resid_norm_body(const double *__restrict__ f, const double *__restrict__ p, int H,
+                                                int bpp, int L, const LapArgs &la, const double *__restrict__ dzf,
+                                                const double *__restrict__ info, double *__restrict__ partials,
+                                                const int *__restrict__ done, unsigned blk)
+{
+    if (*done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *rows = reinterpret_cast<double *>(smem);
+    RAcc acc;
+    long line0;
+    int lv;
+    resid_block(f, p, H, bpp, L, la, info[I_REMOVED], dzf, rows, blk, [](int, int, double) {}, acc, line0, lv);
+    put_partial(partials, blk, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
+}
+
 __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restrict__ f,
                                                          const double *__restrict__ p, int H, int bpp, int L,
                                                          LapArgs la, const double *__restrict__ dzf,
@@ -208,16 +370,30 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
                                                          double *__restrict__ partials,
                                                          const int *__restrict__ done)
 {
-    if (*done) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    double *rows = reinterpret_cast<double *>(smem);
-    int k, j0, lv;
-    rslice_of(blockIdx.x, H, bpp, L, la.ny, la.nz, k, j0, lv);
-    RAcc acc;
-    for (int l0 = 0; l0 < lv; l0 += 2)
-        resid_pair(f, p, k, j0 + l0, min(2, lv - l0), la, info[I_REMOVED], dzf[k], rows, [](int, int, double) {},
-                   acc);
-    put_partial(partials, blockIdx.x, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
+    resid_norm_body(f, p, H, bpp, L, la, dzf, info, partials, done, blockIdx.x);
+}
+
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_resid_xfwd_grp(const RJob *__restrict__ jobs,
+                                                             const unsigned *__restrict__ start, int np)
+{
+    const int q = group_find(start, np, blockIdx.x);
+    const RJob &j = jobs[q];
+    const unsigned blk = blockIdx.x - start[q];
+    if (blk >= j.nblk) return;
+    resid_xfwd_body<KIND>(j.f, j.p, j.out, j.H, j.bpp, j.g, j.rows_off, static_cast<const cx<float> *>(j.tw), j.la,
+                          j.dzf, j.info, j.partials, j.done, blk);
+}
+
+__global__ __launch_bounds__(kThreads) void k_resid_norm_grp(const RJob *__restrict__ jobs,
+                                                             const unsigned *__restrict__ start, int np)
+{
+    const int q = group_find(start, np, blockIdx.x);
+    const RJob &j = jobs[q];
+    const unsigned blk = blockIdx.x - start[q];
+    if (blk >= j.nblk) return;
+    resid_norm_body(j.f, j.p, j.H, j.bpp, j.L, j.la, j.dzf, j.info, j.partials, j.done, blk);
 }
 
 // First level of the block-partial reductions: block b reduces its contiguous
@@ -245,10 +421,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce1(const double *__restrict__
 // Sum the first-level sums in a fixed order, record the relative residual of
 // check number `check` (2-norm, and the max norm beside it) and decide:
 // converged (<= tol, 2-norm) or out of steps.
-__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nblk,
-                                                       int check, int max_iter, double tol,
-                                                       double inv_wvol, int singular,
-                                                       double *__restrict__ info, int *__restrict__ flag)
+__device__ __forceinline__ void finalize_body(const double *__restrict__ partials, int nblk, int check, int max_iter,
+                                              double tol, double inv_wvol, int singular, double *__restrict__ info,
+                                              int *__restrict__ flag)
 {
     if (flag[0]) return;
     double a = 0, b = 0, c = 0, d = 0, e = 0;
@@ -279,16 +454,30 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict_
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nblk,
+                                                       int check, int max_iter, double tol,
+                                                       double inv_wvol, int singular,
+                                                       double *__restrict__ info, int *__restrict__ flag)
+{
+    finalize_body(partials, nblk, check, max_iter, tol, inv_wvol, singular, info, flag);
+}
+
 // Exact FP64 weighted mean of the rhs from the first pass's block sums:
 // info[I_REMOVED] = sum dzf f / (nx ny sum dzf) when singular, else 0.
-__global__ __launch_bounds__(kThreads) void k_mean_rhs(const double *__restrict__ partials, int nblk,
-                                                       double inv_wvol, int singular,
-                                                       double *__restrict__ info)
+__device__ __forceinline__ void mean_rhs_body(const double *__restrict__ partials, int nblk, double inv_wvol,
+                                              int singular, double *__restrict__ info)
 {
     double a = 0, b = 0, c = 0;
     for (int i = threadIdx.x; i < nblk; i += kThreads) a += partials[(size_t)kNP * i];
     block_sum3(a, b, c);
     if (threadIdx.x == 0) info[I_REMOVED] = singular ? a * inv_wvol : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mean_rhs(const double *__restrict__ partials, int nblk,
+                                                       double inv_wvol, int singular,
+                                                       double *__restrict__ info)
+{
+    mean_rhs_body(partials, nblk, inv_wvol, singular, info);
 }
 
 // Start-of-solve state, written by a kernel so the sequence can be captured.
@@ -299,6 +488,31 @@ __global__ void k_reset(double *__restrict__ info, int *__restrict__ flag)
     if (t == 0) flag[0] = 0;
 }
 
+// The per-problem reductions of a grouped batch, one block per problem:
+// start-of-solve state, the rhs mean after the first x transform, and the
+// check after a residual pass (which = 0: the fused pass's partials, 1: the
+// norm pass's).
+__global__ __launch_bounds__(kThreads) void k_reset_grp(const FJob *__restrict__ jobs)
+{
+    const FJob &j = jobs[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t < I_SIZE) j.info[t] = (t >= I_HIST || t == I_LAST) ? -1.0 : 0.0;
+    if (t == 0) j.flag[0] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mean_rhs_grp(const FJob *__restrict__ jobs)
+{
+    const FJob &j = jobs[blockIdx.x];
+    mean_rhs_body(j.partials, j.nb_mean, j.inv_wvol, j.singular, j.info);
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize_grp(const FJob *__restrict__ jobs, int which, int check,
+                                                           int max_iter, double tol)
+{
+    const FJob &j = jobs[blockIdx.x];
+    finalize_body(j.partials, which == 0 ? j.nb_xfwd : j.nb_norm, check, max_iter, tol, j.inv_wvol, j.singular,
+                  j.info, j.flag);
+}
 
 __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ f, const double *__restrict__ p,
                                                      float *out, long nlines, int n, unsigned magn,
@@ -372,7 +586,7 @@ int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const d
                       hipStream_t s)
 {
     const RSlice rs = rslice(pb, norm_rows(pb));
-    const size_t sh = (size_t)2 * (kResidChunk + 2) * sizeof(double);
+    const size_t sh = (size_t)kRowsD * sizeof(double);
     hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)rslice_blocks(pb, rs)), dim3(kThreads), sh, s, f, p, rs.H,
                        rs.bpp, rs.L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
     return check_launch();
@@ -382,16 +596,23 @@ int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const d
 // transform tile, then the FP64 rows
 size_t resid_xfwd_lds(const Problem &pb, const XGeom &g)
 {
-    return (tile_lds(AX_X, g, sizeof(float)) + 15) / 16 * 16 + (size_t)2 * (kResidChunk + 2) * sizeof(double);
+    return (tile_lds(AX_X, g, sizeof(float)) + 15) / 16 * 16 + (size_t)kRowsD * sizeof(double);
 }
 
 // dynamic LDS beyond the default 64 KiB for the residual kernels: up to the
 // 160 KiB of a CU less each kernel's static LDS (its reductions)
 int plan_resid(const Problem &pb)
 {
-    const void *ks[] = {(const void *)k_resid_xfwd<K_P>, (const void *)k_resid_xfwd<K_NN>,
-                        (const void *)k_resid_xfwd<K_DD>, (const void *)k_resid_xfwd<K_ND>,
-                        (const void *)k_resid_xfwd<K_DN>, (const void *)k_resid_norm};
+    const void *ks[] = {(const void *)k_resid_xfwd<K_P>,   (const void *)k_resid_xfwd<K_NN>,
+                        (const void *)k_resid_xfwd<K_DD>,  (const void *)k_resid_xfwd<K_ND>,
+                        (const void *)k_resid_xfwd<K_DN>,  (const void *)k_resid_xfwd<K_S1>,
+                        (const void *)k_resid_xfwd<K_C1>,  (const void *)k_resid_xfwd<K_FDN>,
+                        (const void *)k_resid_xfwd<K_FND>, (const void *)k_resid_norm,
+                        (const void *)k_resid_xfwd_grp<K_P>,   (const void *)k_resid_xfwd_grp<K_NN>,
+                        (const void *)k_resid_xfwd_grp<K_DD>,  (const void *)k_resid_xfwd_grp<K_ND>,
+                        (const void *)k_resid_xfwd_grp<K_DN>,  (const void *)k_resid_xfwd_grp<K_S1>,
+                        (const void *)k_resid_xfwd_grp<K_C1>,  (const void *)k_resid_xfwd_grp<K_FDN>,
+                        (const void *)k_resid_xfwd_grp<K_FND>, (const void *)k_resid_norm_grp};
     (void)pb;
     for (const void *k : ks) {
         hipFuncAttributes fa;
@@ -402,9 +623,9 @@ int plan_resid(const Problem &pb)
     return CANS_OK;
 }
 
-// Up to this many block partials the last-level kernel reads them directly
-// (one launch per check instead of two; small problems are launch-bound).
-constexpr int kDirectReduce = 4096;
+// Up to kDirectReduce block partials the last-level kernel reads them
+// directly (one launch per check instead of two; small problems are
+// launch-bound).
 
 int launch_finalize(const Problem &pb, const Work &w, int nblk, int check, int max_iter, double tol, hipStream_t s)
 {
@@ -465,6 +686,84 @@ int launch_copy_info(const double *src, double *dst, hipStream_t s)
 int launch_reset(const Problem &pb, const Work &w, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.info, w.flag);
+    return check_launch();
+}
+
+// ---- grouped residual passes and reductions of a batch ---------------------
+RJob rjob_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out, const int *done,
+               size_t &lds)
+{
+    const XGeom &g = pb.ax.gx32[1];
+    const RSlice rs = rslice(pb, g.L);
+    lds = resid_xfwd_lds(pb, g);
+    RJob j{};
+    j.f = f;
+    j.p = p;
+    j.out = out;
+    j.tw = pb.ax.d_tw32;
+    j.dzf = pb.d_dzf;
+    j.info = w.info;
+    j.partials = w.partials;
+    j.done = done;
+    j.H = rs.H;
+    j.bpp = rs.bpp;
+    j.L = rs.L;
+    j.rows_off = (int)((tile_lds(AX_X, g, sizeof(float)) + 15) / 16 * 16);
+    j.nblk = (unsigned)rslice_blocks(pb, rs);
+    j.la = lapargs(pb);
+    j.g = g;
+    return j;
+}
+
+RJob rjob_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done, size_t &lds)
+{
+    const RSlice rs = rslice(pb, norm_rows(pb));
+    lds = (size_t)kRowsD * sizeof(double);
+    RJob j{};
+    j.f = f;
+    j.p = p;
+    j.dzf = pb.d_dzf;
+    j.info = w.info;
+    j.partials = w.partials;
+    j.done = done;
+    j.H = rs.H;
+    j.bpp = rs.bpp;
+    j.L = rs.L;
+    j.nblk = (unsigned)rslice_blocks(pb, rs);
+    j.la = lapargs(pb);
+    return j;
+}
+
+int launch_resid_xfwd_grp(const GroupLaunch &gl, hipStream_t s)
+{
+    const RJob *j = static_cast<const RJob *>(gl.jobs);
+    CANS_KIND_SWITCH(gl.key, hipLaunchKernelGGL(k_resid_xfwd_grp<KD>, dim3(gl.blocks), dim3(kThreads), gl.lds, s, j,
+                                                gl.start, gl.np));
+    return check_launch();
+}
+
+int launch_resid_norm_grp(const GroupLaunch &gl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resid_norm_grp, dim3(gl.blocks), dim3(kThreads), gl.lds, s,
+                       static_cast<const RJob *>(gl.jobs), gl.start, gl.np);
+    return check_launch();
+}
+
+int launch_reset_grp(const FJob *jobs, int np, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_grp, dim3(np), dim3(64), 0, s, jobs);
+    return check_launch();
+}
+
+int launch_mean_rhs_grp(const FJob *jobs, int np, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mean_rhs_grp, dim3(np), dim3(kThreads), 0, s, jobs);
+    return check_launch();
+}
+
+int launch_finalize_grp(const FJob *jobs, int np, int which, int check, int max_iter, double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_grp, dim3(np), dim3(kThreads), 0, s, jobs, which, check, max_iter, tol);
     return check_launch();
 }
 }  // namespace cans

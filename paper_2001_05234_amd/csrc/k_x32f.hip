@@ -22,4 +22,14 @@ int launch_x_fwd_32(const Problem &pb, const Work &w, const double *in, float *o
     return check_launch();
 }
 
+
+int launch_x_fwd_32_grp(const GroupLaunch &gl, hipStream_t s)
+{
+    const XJob *j = static_cast<const XJob *>(gl.jobs);
+    CANS_KIND_SWITCH(gl.key,
+        hipLaunchKernelGGL((k_xform_x_grp<KD, true, float, double, float, 0>), dim3(gl.blocks), dim3(kThreads),
+                           gl.lds, s, j, gl.start, gl.np));
+    return check_launch();
+}
+
 }  // namespace cans

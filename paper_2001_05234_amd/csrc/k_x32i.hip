@@ -30,4 +30,16 @@ int launch_x_inv_32(const Problem &pb, const Work &w, const float *in, double *p
     return check_launch();
 }
 
+
+int launch_x_inv_32_grp(const GroupLaunch &gl, bool update, hipStream_t s)
+{
+    const XJob *j = static_cast<const XJob *>(gl.jobs);
+    CANS_KIND_SWITCH(gl.key,
+        if (update) hipLaunchKernelGGL((k_xform_x_grp<KD, false, float, float, double, 1>), dim3(gl.blocks),
+                                       dim3(kThreads), gl.lds, s, j, gl.start, gl.np);
+        else hipLaunchKernelGGL((k_xform_x_grp<KD, false, float, float, double, 0>), dim3(gl.blocks),
+                                dim3(kThreads), gl.lds, s, j, gl.start, gl.np));
+    return check_launch();
+}
+
 }  // namespace cans

@@ -17,4 +17,16 @@ int launch_x_f64(const Problem &pb, bool fwd, const double *in, double *out, hip
     return check_launch();
 }
 
+
+int launch_x_f64_grp(const GroupLaunch &gl, bool fwd, hipStream_t s)
+{
+    const XJob *j = static_cast<const XJob *>(gl.jobs);
+    CANS_KIND_SWITCH(gl.key,
+        if (fwd) hipLaunchKernelGGL((k_xform_x_grp<KD, true, double, double, double, 0>), dim3(gl.blocks),
+                                    dim3(kThreads), gl.lds, s, j, gl.start, gl.np);
+        else hipLaunchKernelGGL((k_xform_x_grp<KD, false, double, double, double, 0>), dim3(gl.blocks),
+                                dim3(kThreads), gl.lds, s, j, gl.start, gl.np));
+    return check_launch();
+}
+
 }  // namespace cans

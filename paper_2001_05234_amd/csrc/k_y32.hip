@@ -17,4 +17,16 @@ int launch_y_32(const Problem &pb, bool fwd, float *data, const int *done, hipSt
     return check_launch();
 }
 
+
+int launch_y_32_grp(const GroupLaunch &gl, bool fwd, hipStream_t s)
+{
+    const YJob *j = static_cast<const YJob *>(gl.jobs);
+    CANS_KIND_SWITCH(gl.key,
+        if (fwd) hipLaunchKernelGGL((k_xform_y_grp<KD, true, float, float>), dim3(gl.blocks), dim3(kThreads),
+                                    gl.lds, s, j, gl.start, gl.np);
+        else hipLaunchKernelGGL((k_xform_y_grp<KD, false, float, float>), dim3(gl.blocks), dim3(kThreads),
+                                gl.lds, s, j, gl.start, gl.np));
+    return check_launch();
+}
+
 }  // namespace cans

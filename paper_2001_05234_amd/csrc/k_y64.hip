@@ -16,4 +16,16 @@ int launch_y_f64(const Problem &pb, bool fwd, const double *in, double *out, hip
                                 in, out, pb.nx, pb.ny, ntx, g, pb.ay.d_tw64, nullptr));
     return check_launch();
 }
+
+int launch_y_f64_grp(const GroupLaunch &gl, bool fwd, hipStream_t s)
+{
+    const YJob *j = static_cast<const YJob *>(gl.jobs);
+    CANS_KIND_SWITCH(gl.key,
+        if (fwd) hipLaunchKernelGGL((k_xform_y_grp<KD, true, double, double>), dim3(gl.blocks), dim3(kThreads),
+                                    gl.lds, s, j, gl.start, gl.np);
+        else hipLaunchKernelGGL((k_xform_y_grp<KD, false, double, double>), dim3(gl.blocks), dim3(kThreads),
+                                gl.lds, s, j, gl.start, gl.np));
+    return check_launch();
+}
+
 }  // namespace cans

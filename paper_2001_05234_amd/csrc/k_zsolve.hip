@@ -20,9 +20,12 @@ static ZArgs zargs(const Problem &pb, const Work &w, double *removed);
 
 // Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
 // into S segments of at most MMAX levels held in registers; a wave holds
-// 64/CPB segments of the same columns (see zsolve_core.h).
-template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC, bool PAD = false>
-__global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const int *__restrict__ done)
+// 64/CPB segments of the same columns (see zsolve_core.h).  The body solves
+// block `blk`'s columns with S segments; the waves beyond S (a grouped launch
+// sized for the group's deepest problem) only take part in the barriers.
+template <typename T, int MMAX, int CPB, bool FULL, bool CYC, bool PAD>
+__device__ __forceinline__ void zsolve_part_body(T *data, const ZArgs &ag, const int *__restrict__ done,
+                                                 unsigned blk, int S)
 {
     if (done && *done) return;
     constexpr int NQ = CYC ? 8 : 6;  // interface coefficients per segment
@@ -32,7 +35,7 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     constexpr int SPW = 64 / CPB;  // segments per wave
     // PAD: S * MMAX levels (<= 512 for every launched shape), padding rows
     // beyond nz
-    const int nzp = PAD ? (int)(blockDim.x >> 6) * SPW * MMAX : ag.nz;
+    const int nzp = PAD ? S * MMAX : ag.nz;
     for (int i = threadIdx.x; i < nzp; i += blockDim.x)
         zpad_row(ag, i, zabc[i], zabc[512 + i], zabc[1024 + i]);
     ZArgs a = ag;
@@ -43,16 +46,18 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int c = lane % CPB, seg = w * SPW + lane / CPB;
-    const int S = (int)(blockDim.x >> 6) * SPW;
+    const bool act = seg < S;
     auto C = [&](int q, int s) -> double & { return coef[q * 1024 + s * CPB + c]; };
-    const size_t col = (size_t)blockIdx.x * CPB + c;
-    const ZSeg sg = zseg(nzp, S, seg);
+    const size_t col = (size_t)blk * CPB + c;
+    const ZSeg sg = zseg(nzp, S, act ? seg : 0);
     ZLane<MMAX, CYC> L;
-    zp_load<MMAX, FULL, PAD>(L, data, a, col, sg);
-    double out[NQ];
-    zp_reduce<MMAX, FULL>(L, a, sg, out);
+    if (act) {
+        zp_load<MMAX, FULL, PAD>(L, data, a, col, sg);
+        double out[NQ];
+        zp_reduce<MMAX, FULL>(L, a, sg, out);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) C(q, seg) = out[q];
+        for (int q = 0; q < NQ; ++q) C(q, seg) = out[q];
+    }
     __syncthreads();
     if (w == 0 && lane < CPB) {
         zp_interface<CYC>(
@@ -61,30 +66,50 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const 
             [&](int s) -> double & { return C(7, s); });
     }
     __syncthreads();
-    const double xL = seg > 0 ? C(5, seg - 1) : 0.0;
-    const double xR = seg < S - 1 ? C(4, seg + 1) : 0.0;
+    const double xL = act && seg > 0 ? C(5, seg - 1) : 0.0;
+    const double xR = act && seg < S - 1 ? C(4, seg + 1) : 0.0;
     if constexpr (CYC) {
-        const double xL2 = seg > 0 ? C(7, seg - 1) : 0.0;
-        const double xR2 = seg < S - 1 ? C(6, seg + 1) : 0.0;
-        zp_finish<MMAX, FULL>(L, a, sg, xL, xR, xL2, xR2);
-        // Sherman-Morrison: the column's first and last values of A'^-1 f and
-        // A'^-1 u come from its first and last segment
-        double y0, z0, yl, zl;
-        zp_ends<MMAX, FULL>(L, sg, &y0, &z0, &yl, &zl);
-        if (seg == 0) { ends[c] = y0; ends[64 + c] = z0; }
-        if (seg == S - 1) { ends[128 + c] = yl; ends[192 + c] = zl; }
+        const double xL2 = act && seg > 0 ? C(7, seg - 1) : 0.0;
+        const double xR2 = act && seg < S - 1 ? C(6, seg + 1) : 0.0;
+        if (act) {
+            zp_finish<MMAX, FULL>(L, a, sg, xL, xR, xL2, xR2);
+            // Sherman-Morrison: the column's first and last values of A'^-1 f
+            // and A'^-1 u come from its first and last segment
+            double y0, z0, yl, zl;
+            zp_ends<MMAX, FULL>(L, sg, &y0, &z0, &yl, &zl);
+            if (seg == 0) { ends[c] = y0; ends[64 + c] = z0; }
+            if (seg == S - 1) { ends[128 + c] = yl; ends[192 + c] = zl; }
+        }
         __syncthreads();
-        zp_sherman_morrison<MMAX, FULL>(L, a, sg, ends[c], ends[64 + c], ends[128 + c], ends[192 + c]);
+        if (act) zp_sherman_morrison<MMAX, FULL>(L, a, sg, ends[c], ends[64 + c], ends[128 + c], ends[192 + c]);
     } else {
-        zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
+        if (act) zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
     }
-    zp_store<MMAX, FULL, PAD>(L, data, a, col, sg);
-    if (a.singular && blockIdx.x == 0) {
+    if (act) zp_store<MMAX, FULL, PAD>(L, data, a, col, sg);
+    if (a.singular && blk == 0) {
         // the singular column, left out above: projected rhs, pinned last
         // row, zero weighted mean, by one thread with coef as workspace
         __syncthreads();
         if (threadIdx.x == 0) zsolve_singular_ws<T>(0, data, a, coef, coef + 512, 1);
     }
+}
+
+template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC, bool PAD = false>
+__global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const int *__restrict__ done)
+{
+    zsolve_part_body<T, MMAX, CPB, FULL, CYC, PAD>(data, ag, done, blockIdx.x, (int)(blockDim.x >> 6) * (64 / CPB));
+}
+
+
+template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC, bool PAD>
+__global__ __launch_bounds__(NTMAX) void k_zsolve_part_grp(const ZJob *__restrict__ jobs,
+                                                           const unsigned *__restrict__ start, int np)
+{
+    const int q = group_find(start, np, blockIdx.x);
+    const ZJob &j = jobs[q];
+    const unsigned blk = blockIdx.x - start[q];
+    if (blk >= j.nblk) return;
+    zsolve_part_body<T, MMAX, CPB, FULL, CYC, PAD>(static_cast<T *>(j.data), j.a, j.done, blk, j.S);
 }
 
 // ---------------------------------------------------------------------------
@@ -427,4 +452,69 @@ int launch_zsolve_32(const Problem &pb, const Work &w, float *data, double *remo
 {
     return launch_zsolve<float>(pb, w, data, removed, done, s);
 }
+
+// ---------------------------------------------------------------------------
+// Grouped z solves: problems whose partitioned solve takes the same kernel
+// variant (segment depth, columns per block, thread bound, full / padded
+// segments, periodic or not) share one launch.  Variant codes:
+//   0, 1    periodic, 8-level segments, full / ragged
+//   2, 3    8-level segments, full / padded
+//   4 .. 7  16-level segments of 64 columns: 768 threads full / padded, 1024 full / padded
+//   8 .. 11 the same with 32 columns
+ZJob zjob_of(const Problem &pb, const Work &w, void *data, double *removed, const int *done, bool fp32, int &key,
+             int &threads, unsigned &nblk)
+{
+    ZJob j{};
+    key = -1;
+    const PipePlan &pp = fp32 ? pb.zpipe32 : pb.zpipe64;
+    const ZPart zp = zpart_shape(pb.nz, pb.cyclic != 0);
+    if (pp.on || zp.mmax == 0) return j;  // the pipelined or the plain solve: launched on its own
+    const int S = (zp.threads / 64) * (64 / zp.cpb);
+    const bool full = pb.nz == S * zp.mmax;
+    const bool small = zp.threads <= 768;
+    if (pb.cyclic) key = full ? 0 : 1;
+    else if (zp.mmax == 8) key = full ? 2 : 3;
+    else key = (zp.cpb == 64 ? 4 : 8) + (small ? 0 : 2) + (full ? 0 : 1);
+    threads = zp.threads;
+    const size_t plane = (size_t)pb.nx * pb.ny;
+    nblk = (unsigned)((plane + zp.cpb - 1) / zp.cpb);
+    j.data = data;
+    j.done = done;
+    j.S = S;
+    j.nblk = nblk;
+    j.a = zargs(pb, w, removed);
+    return j;
+}
+
+template <typename T>
+static int launch_zgrp(const GroupLaunch &gl, hipStream_t s)
+{
+    const ZJob *j = static_cast<const ZJob *>(gl.jobs);
+    const dim3 grid(gl.blocks), block(gl.threads);
+#define CANS_ZG(MM, CPB, NT, FULLV, CYCV, PADV) \
+    hipLaunchKernelGGL((k_zsolve_part_grp<T, MM, CPB, NT, FULLV, CYCV, PADV>), grid, block, 0, s, j, gl.start, gl.np)
+    switch (gl.key) {
+    case 0: CANS_ZG(8, 64, 1024, true, true, false); break;
+    case 1: CANS_ZG(8, 64, 1024, false, true, false); break;
+    case 2: CANS_ZG(8, 64, 1024, true, false, false); break;
+    case 3: CANS_ZG(8, 64, 1024, true, false, true); break;
+    case 4: CANS_ZG(16, 64, 768, true, false, false); break;
+    case 5: CANS_ZG(16, 64, 768, true, false, true); break;
+    case 6: CANS_ZG(16, 64, 1024, true, false, false); break;
+    case 7: CANS_ZG(16, 64, 1024, true, false, true); break;
+    case 8: CANS_ZG(16, 32, 768, true, false, false); break;
+    case 9: CANS_ZG(16, 32, 768, true, false, true); break;
+    case 10: CANS_ZG(16, 32, 1024, true, false, false); break;
+    case 11: CANS_ZG(16, 32, 1024, true, false, true); break;
+    default: return CANS_ERR_INVALID_ARG;
+    }
+#undef CANS_ZG
+    return check_launch();
+}
+
+int launch_zsolve_grp(const GroupLaunch &gl, bool fp32, hipStream_t s)
+{
+    return fp32 ? launch_zgrp<float>(gl, s) : launch_zgrp<double>(gl, s);
+}
+
 }  // namespace cans

@@ -94,6 +94,21 @@ static __device__ inline unsigned xcd_remap(unsigned b, unsigned nblk)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Problem of block b in a grouped launch (one launch for the same kernel
+// over several problems): start[] holds the first block of each problem,
+// ascending, each a multiple of 8 so that b % 8 (the XCD of the block) is
+// also its local index's.
+static __device__ __forceinline__ int group_find(const unsigned *__restrict__ start, int np, unsigned b)
+{
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // z level of line `line` (rows j + ny*k) inside a tile starting at line0
 static __device__ inline int line_level(long line, long line0, int k0, int j0, int ny)
 {

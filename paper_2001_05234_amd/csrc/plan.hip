@@ -13,24 +13,42 @@
 
 #include "cans_internal.h"
 #include "dense_core.h"
+#include "kcommon.h"
 #include "tables.h"
 
 using namespace cans;
 
-// Batched solves run as one captured graph: the instances are spread over
-// kBranches capture streams (largest first, each to the least loaded branch)
-// so independent problems execute concurrently, and the whole batch is a
-// single hipGraphLaunch on the caller's stream.
-constexpr int kBranches = 8;
+// Batched solves (and single solves in graph mode) run as grouped launches:
+// every step of the solve is one launch per kernel variant over all the
+// problems that take it (x and residual steps grouped by the x transform
+// kind, y steps by the y kind, z solves by their partitioned shape), each
+// block finding its problem in a table of job records.  Problems a grouped
+// kernel does not cover (a dense x form, a pipelined or plain z solve, a
+// check over more block partials than one block reduces) take their own
+// launches at the same place of the sequence.  The sequence is captured once
+// per set of (rhs, p) arrays and replayed as a single hipGraphLaunch on the
+// caller's stream.
+struct GroupStep {
+    std::vector<GroupLaunch> grp;    // grouped launches
+    std::vector<int> solo;           // problems launched on their own
+};
+struct FTable {
+    const FJob *jobs = nullptr;
+    int n = 0;
+};
 
 struct BatchGraph {
     hipGraphExec_t exec = nullptr;
-    std::vector<const void *> key;   // rhs and p pointers the graph was captured with
+    std::vector<const void *> key;   // rhs and p pointers of the tables and the captured graph
     hipStream_t cap = nullptr;
-    hipStream_t side[kBranches] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[kBranches] = {};
-    std::vector<int> branch;         // branch of each instance
+    // job tables (device), rebuilt for a new key
+    void *d_tab = nullptr;
+    size_t tab_bytes = 0;
+    GroupStep xf, xi, yf, yi, z, rx, rn;
+    // reduction records: every problem (reset), and those whose rhs mean and
+    // checks one block reduces
+    FTable f_all, f_mean, f_x, f_n;
+    std::vector<int> fin_solo_x, fin_solo_n, mean_solo;  // the others: their own launches
 };
 
 struct cans_plan_s {
@@ -338,16 +356,11 @@ void free_graph(BatchGraph &g)
 {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
-    for (int b = 0; b < kBranches; ++b) {
-        if (g.side[b]) (void)hipStreamDestroy(g.side[b]);
-        if (g.join[b]) (void)hipEventDestroy(g.join[b]);
-        g.side[b] = nullptr;
-        g.join[b] = nullptr;
-    }
     if (g.cap) (void)hipStreamDestroy(g.cap);
-    if (g.fork) (void)hipEventDestroy(g.fork);
     g.cap = nullptr;
-    g.fork = nullptr;
+    if (g.d_tab) (void)hipFree(g.d_tab);
+    g.d_tab = nullptr;
+    g.tab_bytes = 0;
 }
 
 void free_plan(cans_plan_s *pl)
@@ -355,24 +368,6 @@ void free_plan(cans_plan_s *pl)
     free_graph(pl->g);
     for (void *p : pl->allocs) (void)hipFree(p);
     delete pl;
-}
-
-// longest-processing-time assignment of instances to graph branches
-std::vector<int> assign_branches(const std::vector<Problem> &probs)
-{
-    std::vector<int> order(probs.size()), br(probs.size(), 0);
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return probs[a].npts() > probs[b].npts(); });
-    double load[kBranches] = {};
-    for (int i : order) {
-        int best = 0;
-        for (int b = 1; b < kBranches; ++b)
-            if (load[b] < load[best]) best = b;
-        br[i] = best;
-        load[best] += (double)probs[i].npts();
-    }
-    return br;
 }
 
 int solve_fp64(const Problem &pb, const Work &w, const double *rhs, double *p, hipStream_t s)
@@ -490,6 +485,258 @@ int carve_work(const Problem &pb, int precision, unsigned char *base, Work &w)
     w.flag = reinterpret_cast<int *>(take(sizeof(int)));
     w.zctr = reinterpret_cast<unsigned *>(take(2 * sizeof(unsigned)));
     return off <= (size_t)CANS_NOALLOC_SCRATCH_BYTES ? CANS_OK : CANS_ERR_TOO_LARGE;
+}
+
+}  // namespace
+
+namespace {
+
+// Host side of one grouped launch while the tables are being built.
+struct HostGroup {
+    GroupLaunch gl;
+    std::vector<unsigned char> jobs;
+    std::vector<unsigned> start;
+};
+
+template <typename J>
+void add_member(std::vector<HostGroup> &gs, int key, const J &job, unsigned nblk, int threads, size_t lds)
+{
+    HostGroup *g = nullptr;
+    for (HostGroup &h : gs)
+        if (h.gl.key == key) g = &h;
+    if (!g) {
+        gs.emplace_back();
+        g = &gs.back();
+        g->gl.key = key;
+        g->gl.threads = 0;
+    }
+    g->start.push_back(g->gl.blocks);
+    g->gl.blocks += (nblk + 7) / 8 * 8;  // every problem starts on a multiple of 8 (its XCD order)
+    g->gl.np += 1;
+    g->gl.threads = std::max(g->gl.threads, threads);
+    g->gl.lds = std::max(g->gl.lds, lds);
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&job);
+    g->jobs.insert(g->jobs.end(), b, b + sizeof(J));
+}
+
+// One block of bytes holding every table, each at a 256-byte boundary.
+struct Staging {
+    std::vector<unsigned char> bytes;
+    size_t put(const void *src, size_t n)
+    {
+        const size_t off = (bytes.size() + 255) / 256 * 256;
+        bytes.resize(off + n);
+        std::memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+};
+
+XJob xjob(const Problem &pb, const void *in, void *out, const XGeom &g, const void *tw, const double *info,
+          const int *done, const double *dzf, double *wsum_part)
+{
+    XJob j{};
+    j.in = in;
+    j.out = out;
+    j.nlines = (long)pb.ny * pb.nz;
+    j.tw = tw;
+    j.info = info;
+    j.done = done;
+    j.dzf = dzf;
+    j.wsum_part = wsum_part;
+    j.ny = pb.ny;
+    j.nblk = (unsigned)((j.nlines + g.L - 1) / g.L);
+    j.g = g;
+    return j;
+}
+
+YJob yjob(const Problem &pb, void *data, const XGeom &g, const void *tw, const int *done)
+{
+    YJob j{};
+    j.data = data;
+    j.tw = tw;
+    j.done = done;
+    j.nx = pb.nx;
+    j.ny = pb.ny;
+    j.ntx = (pb.nx + g.L - 1) / g.L;
+    j.nblk = (unsigned)(j.ntx * pb.nz);
+    j.g = g;
+    return j;
+}
+
+// The job tables of a plan's problems for one set of (rhs, p) arrays.
+int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
+{
+    BatchGraph &bg = pl->g;
+    const bool refine = pl->opts.precision == CANS_PREC_FP32_REFINE;
+    const size_t es = refine ? sizeof(float) : sizeof(double);
+    std::vector<HostGroup> xf, xi, yf, yi, z, rx, rn;
+    GroupStep *steps[] = {&bg.xf, &bg.xi, &bg.yf, &bg.yi, &bg.z, &bg.rx, &bg.rn};
+    for (GroupStep *st : steps) *st = GroupStep{};
+    bg.fin_solo_x.clear();
+    bg.fin_solo_n.clear();
+    bg.mean_solo.clear();
+    std::vector<FJob> f_all, f_mean, f_x, f_n;
+    for (int i = 0; i < (int)pl->probs.size(); ++i) {
+        const Problem &pb = pl->probs[i];
+        const Work &w = pb.ws;
+        const XGeom &gxf = refine ? pb.ax.gx32[1] : pb.ax.gx64[1], &gxi = refine ? pb.ax.gx32[0] : pb.ax.gx64[0];
+        const XGeom &gyf = refine ? pb.ay.gy32[1] : pb.ay.gy64[1], &gyi = refine ? pb.ay.gy32[0] : pb.ay.gy64[0];
+        const void *twx = refine ? (const void *)pb.ax.d_tw32 : (const void *)pb.ax.d_tw64;
+        const void *twy = refine ? (const void *)pb.ay.d_tw32 : (const void *)pb.ay.d_tw64;
+        void *data = refine ? (void *)w.a32 : (void *)p[i];
+        const int *done = refine ? w.flag : nullptr;
+        if (pb.ax.dense) {
+            bg.xf.solo.push_back(i);
+            bg.xi.solo.push_back(i);
+            bg.rx.solo.push_back(i);
+        } else {
+            const XJob jf = refine ? xjob(pb, rhs[i], w.a32, gxf, twx, nullptr, done, pb.d_dzf, w.partials)
+                                   : xjob(pb, rhs[i], p[i], gxf, twx, nullptr, nullptr, nullptr, nullptr);
+            const XJob ji = refine ? xjob(pb, w.a32, p[i], gxi, twx, w.info, done, nullptr, nullptr)
+                                   : xjob(pb, p[i], p[i], gxi, twx, nullptr, nullptr, nullptr, nullptr);
+            add_member(xf, pb.ax.kind, jf, jf.nblk, kThreads, tile_lds(AX_X, gxf, es));
+            add_member(xi, pb.ax.kind, ji, ji.nblk, kThreads, tile_lds(AX_X, gxi, es));
+            if (refine) {
+                size_t lds = 0;
+                const RJob r = rjob_xfwd(pb, w, rhs[i], p[i], w.a32, w.flag, lds);
+                if (lds > kResidLdsMax) return CANS_ERR_UNSUPPORTED;
+                add_member(rx, pb.ax.kind, r, r.nblk, kThreads, lds);
+            }
+        }
+        const YJob jyf = yjob(pb, data, gyf, twy, done), jyi = yjob(pb, data, gyi, twy, done);
+        add_member(yf, pb.ay.kind, jyf, jyf.nblk, kThreads, tile_lds(AX_Y, gyf, es));
+        add_member(yi, pb.ay.kind, jyi, jyi.nblk, kThreads, tile_lds(AX_Y, gyi, es));
+        int zkey = -1, zthr = 0;
+        unsigned znb = 0;
+        const ZJob zj = zjob_of(pb, w, data, refine ? nullptr : w.info + I_REMOVED, done, refine, zkey, zthr, znb);
+        if (zkey < 0) bg.z.solo.push_back(i);
+        else add_member(z, zkey, zj, znb, zthr, 0);
+        if (refine) {
+            size_t lds = 0;
+            const RJob r = rjob_norm(pb, w, rhs[i], p[i], w.flag, lds);
+            add_member(rn, 0, r, r.nblk, kThreads, lds);
+            FJob f{};
+            f.partials = w.partials;
+            f.info = w.info;
+            f.flag = w.flag;
+            f.nb_mean = xfwd_blocks(pb);
+            f.nb_xfwd = resid_blocks_xfwd(pb);
+            f.nb_norm = resid_blocks_norm(pb);
+            f.singular = pb.singular;
+            f.inv_wvol = 1.0 / (pb.wsum * pb.nx * pb.ny);
+            f_all.push_back(f);
+            if (f.nb_mean <= kDirectReduce) f_mean.push_back(f); else bg.mean_solo.push_back(i);
+            if (f.nb_xfwd <= kDirectReduce) f_x.push_back(f); else bg.fin_solo_x.push_back(i);
+            if (f.nb_norm <= kDirectReduce) f_n.push_back(f); else bg.fin_solo_n.push_back(i);
+        }
+    }
+    // lay the tables out in one device block
+    Staging st;
+    std::vector<HostGroup> *hs[] = {&xf, &xi, &yf, &yi, &z, &rx, &rn};
+    std::vector<std::vector<std::pair<size_t, size_t>>> offs(7);
+    for (int k = 0; k < 7; ++k)
+        for (HostGroup &h : *hs[k])
+            offs[k].push_back({st.put(h.jobs.data(), h.jobs.size()), st.put(h.start.data(), h.start.size() * 4)});
+    std::vector<FJob> *fs[] = {&f_all, &f_mean, &f_x, &f_n};
+    size_t foff[4];
+    for (int k = 0; k < 4; ++k) foff[k] = st.put(fs[k]->data(), fs[k]->size() * sizeof(FJob));
+    if (st.bytes.size() > bg.tab_bytes) {
+        if (bg.d_tab) (void)hipFree(bg.d_tab);
+        bg.d_tab = nullptr;
+        bg.tab_bytes = 0;
+        if (hipMalloc(&bg.d_tab, st.bytes.size()) != hipSuccess) return CANS_ERR_ALLOC;
+        bg.tab_bytes = st.bytes.size();
+    }
+    if (!st.bytes.empty() && hipMemcpy(bg.d_tab, st.bytes.data(), st.bytes.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return CANS_ERR_HIP;
+    unsigned char *base = static_cast<unsigned char *>(bg.d_tab);
+    for (int k = 0; k < 7; ++k)
+        for (size_t g = 0; g < hs[k]->size(); ++g) {
+            GroupLaunch gl = (*hs[k])[g].gl;
+            gl.jobs = base + offs[k][g].first;
+            gl.start = reinterpret_cast<const unsigned *>(base + offs[k][g].second);
+            steps[k]->grp.push_back(gl);
+        }
+    bg.f_all = {reinterpret_cast<const FJob *>(base + foff[0]), (int)f_all.size()};
+    bg.f_mean = {reinterpret_cast<const FJob *>(base + foff[1]), (int)f_mean.size()};
+    bg.f_x = {reinterpret_cast<const FJob *>(base + foff[2]), (int)f_x.size()};
+    bg.f_n = {reinterpret_cast<const FJob *>(base + foff[3]), (int)f_n.size()};
+    return CANS_OK;
+}
+
+template <typename F>
+int each_group(const GroupStep &st, F launch)
+{
+    for (const GroupLaunch &gl : st.grp) CANS_TRY(launch(gl));
+    return CANS_OK;
+}
+
+// The grouped sequence of one batched solve, in the order of solve_fp64 /
+// solve_refine.
+int enqueue_grouped(cans_plan_s *pl, const double *const *rhs, double *const *p, hipStream_t s)
+{
+    const BatchGraph &bg = pl->g;
+    const std::vector<Problem> &P = pl->probs;
+    if (pl->opts.precision == CANS_PREC_FP64) {
+        CANS_TRY(each_group(bg.xf, [&](const GroupLaunch &g) { return launch_x_f64_grp(g, true, s); }));
+        CANS_TRY(each_group(bg.yf, [&](const GroupLaunch &g) { return launch_y_f64_grp(g, true, s); }));
+        CANS_TRY(each_group(bg.z, [&](const GroupLaunch &g) { return launch_zsolve_grp(g, false, s); }));
+        for (int i : bg.z.solo) CANS_TRY(launch_zsolve_f64(P[i], P[i].ws, p[i], P[i].ws.info + I_REMOVED, s));
+        CANS_TRY(each_group(bg.yi, [&](const GroupLaunch &g) { return launch_y_f64_grp(g, false, s); }));
+        CANS_TRY(each_group(bg.xi, [&](const GroupLaunch &g) { return launch_x_f64_grp(g, false, s); }));
+        return CANS_OK;
+    }
+    const cans_opts &o = pl->opts;
+    auto ystep = [&](bool fwd) {
+        return each_group(fwd ? bg.yf : bg.yi, [&](const GroupLaunch &g) { return launch_y_32_grp(g, fwd, s); });
+    };
+    auto zstep = [&](bool first) {
+        CANS_TRY(each_group(bg.z, [&](const GroupLaunch &g) { return launch_zsolve_grp(g, true, s); }));
+        for (int i : bg.z.solo)
+            CANS_TRY(launch_zsolve_32(P[i], P[i].ws, P[i].ws.a32, nullptr, first ? nullptr : P[i].ws.flag, s));
+        return (int)CANS_OK;
+    };
+    auto xinv = [&](bool update) {
+        CANS_TRY(each_group(bg.xi, [&](const GroupLaunch &g) { return launch_x_inv_32_grp(g, update, s); }));
+        for (int i : bg.xi.solo)
+            CANS_TRY(launch_x_inv_32(P[i], P[i].ws, P[i].ws.a32, p[i], update, update ? P[i].ws.flag : nullptr, s));
+        return (int)CANS_OK;
+    };
+    auto rxstep = [&]() {
+        CANS_TRY(each_group(bg.rx, [&](const GroupLaunch &g) { return launch_resid_xfwd_grp(g, s); }));
+        for (int i : bg.rx.solo) CANS_TRY(launch_resid_xfwd(P[i], P[i].ws, rhs[i], p[i], P[i].ws.a32, P[i].ws.flag, s));
+        return (int)CANS_OK;
+    };
+    auto check = [&](int which, int it) {
+        const FTable &t = which == 0 ? bg.f_x : bg.f_n;
+        if (t.n) CANS_TRY(launch_finalize_grp(t.jobs, t.n, which, it, o.max_iter, o.tol, s));
+        for (int i : which == 0 ? bg.fin_solo_x : bg.fin_solo_n)
+            CANS_TRY(launch_finalize(P[i], P[i].ws, which == 0 ? resid_blocks_xfwd(P[i]) : resid_blocks_norm(P[i]), it,
+                                     o.max_iter, o.tol, s));
+        return (int)CANS_OK;
+    };
+    CANS_TRY(launch_reset_grp(bg.f_all.jobs, bg.f_all.n, s));
+    CANS_TRY(each_group(bg.xf, [&](const GroupLaunch &g) { return launch_x_fwd_32_grp(g, s); }));
+    for (int i : bg.xf.solo) CANS_TRY(launch_x_fwd_32(P[i], P[i].ws, rhs[i], P[i].ws.a32, nullptr, s));
+    if (bg.f_mean.n) CANS_TRY(launch_mean_rhs_grp(bg.f_mean.jobs, bg.f_mean.n, s));
+    for (int i : bg.mean_solo) CANS_TRY(launch_mean_rhs(P[i], P[i].ws, s));
+    CANS_TRY(ystep(true));
+    CANS_TRY(zstep(true));
+    CANS_TRY(ystep(false));
+    CANS_TRY(xinv(false));
+    // check 0, fused with the forward x transform the first correction needs
+    CANS_TRY(rxstep());
+    CANS_TRY(check(0, 0));
+    for (int it = 1; it <= o.max_iter; ++it) {
+        CANS_TRY(ystep(true));
+        CANS_TRY(zstep(false));
+        CANS_TRY(ystep(false));
+        CANS_TRY(xinv(true));
+        CANS_TRY(each_group(bg.rn, [&](const GroupLaunch &g) { return launch_resid_norm_grp(g, s); }));
+        CANS_TRY(check(1, it));
+        if (it < o.max_iter) CANS_TRY(rxstep());
+    }
+    return CANS_OK;
 }
 
 }  // namespace
@@ -659,35 +906,18 @@ int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, doubl
     }
     BatchGraph &g = plan->g;
     if (!g.exec || g.key != key) {
-        // (re)capture the whole batch; kernels only, so replays are exact
+        // new arrays: rebuild the job tables (after the work that may still
+        // read the old ones) and capture the grouped sequence once
         if (g.exec) {
+            if (hipStreamSynchronize(stream) != hipSuccess) return CANS_ERR_HIP;
             (void)hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
         }
-        if (!g.cap) {
-            if (hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&g.fork, hipEventDisableTiming) != hipSuccess)
-                return CANS_ERR_HIP;
-            for (int b = 0; b < kBranches; ++b)
-                if (hipStreamCreateWithFlags(&g.side[b], hipStreamNonBlocking) != hipSuccess ||
-                    hipEventCreateWithFlags(&g.join[b], hipEventDisableTiming) != hipSuccess)
-                    return CANS_ERR_HIP;
-            g.branch = assign_branches(plan->probs);
-        }
+        g.key.clear();
+        if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess) return CANS_ERR_HIP;
+        CANS_TRY(build_groups(plan, rhs, p));
         if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return CANS_ERR_HIP;
-        int rc = CANS_OK;
-        if (hipEventRecord(g.fork, g.cap) != hipSuccess) rc = CANS_ERR_HIP;
-        for (int b = 0; b < kBranches && rc == CANS_OK; ++b)
-            if (hipStreamWaitEvent(g.side[b], g.fork, 0) != hipSuccess) rc = CANS_ERR_HIP;
-        for (size_t i = 0; i < n && rc == CANS_OK; ++i) {
-            const Problem &pb = plan->probs[i];
-            hipStream_t s = g.side[g.branch[i]];
-            rc = plan->opts.precision == CANS_PREC_FP64 ? solve_fp64(pb, pb.ws, rhs[i], p[i], s)
-                                                        : solve_refine(pb, pb.ws, plan->opts, rhs[i], p[i], s);
-        }
-        for (int b = 0; b < kBranches && rc == CANS_OK; ++b)
-            if (hipEventRecord(g.join[b], g.side[b]) != hipSuccess || hipStreamWaitEvent(g.cap, g.join[b], 0) != hipSuccess)
-                rc = CANS_ERR_HIP;
+        const int rc = enqueue_grouped(plan, rhs, p, g.cap);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(g.cap, &graph);
         if (rc != CANS_OK || ec != hipSuccess) {

@@ -14,20 +14,19 @@ namespace cans {
 // FP64, so the exact weighted mean of the rhs is known in refinement mode.
 // At least 4 waves per SIMD: the staged FP64 inverses would otherwise take
 // 145 VGPRs and run 3 (the cap costs them a small spill and is faster).
+// xform_x_body is the work of block `blk`; the kernels below run it for one
+// problem (blk = blockIdx.x) or for a group of problems (grouped launches).
 template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
-                                                      const cx<T> *__restrict__ tw,
-                                                      const double *__restrict__ info,
-                                                      const int *__restrict__ done,
-                                                      const double *__restrict__ dzf, int ny,
-                                                      double *__restrict__ wsum_part)
+__device__ __forceinline__ void xform_x_body(const Tin *in, Tout *out, long nlines, const XGeom &g,
+                                             const cx<T> *__restrict__ tw, const double *__restrict__ info,
+                                             const int *__restrict__ done, const double *__restrict__ dzf,
+                                             int ny, double *__restrict__ wsum_part, unsigned blk)
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile<AX_X, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
     const int n = g.nl;
-    const long line0 = (long)blockIdx.x * g.L;
+    const long line0 = (long)blk * g.L;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
     auto put = [&](int q, int l, T v) {
@@ -66,23 +65,47 @@ void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g,
             double z1 = 0, z2 = 0;
             block_sum3(acc, z1, z2);
             if (threadIdx.x == 0) {
-                wsum_part[kNP * blockIdx.x] = acc;
+                wsum_part[kNP * blk] = acc;
             }
         }
     }
 }
 
+template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_xform_x(const Tin *in, Tout *out, long nlines, XGeom g, const cx<T> *__restrict__ tw,
+               const double *__restrict__ info, const int *__restrict__ done, const double *__restrict__ dzf,
+               int ny, double *__restrict__ wsum_part)
+{
+    xform_x_body<KIND, FWD, T, Tin, Tout, EPI>(in, out, nlines, g, tw, info, done, dzf, ny, wsum_part, blockIdx.x);
+}
+
+
+template <int KIND, bool FWD, typename T, typename Tin, typename Tout, int EPI>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_xform_x_grp(const XJob *__restrict__ jobs, const unsigned *__restrict__ start, int np)
+{
+    const int p = group_find(start, np, blockIdx.x);
+    const XJob &j = jobs[p];
+    const unsigned blk = blockIdx.x - start[p];
+    if (blk >= j.nblk) return;
+    xform_x_body<KIND, FWD, T, Tin, Tout, EPI>(static_cast<const Tin *>(j.in), static_cast<Tout *>(j.out),
+                                               j.nlines, j.g, static_cast<const cx<T> *>(j.tw), j.info, j.done,
+                                               j.dzf, j.ny, j.wsum_part, blk);
+}
+
 // y transform: tile (t, k) holds columns i0 .. i0+L-1 of plane k, all ny
-// rows; each global row segment of L elements is contiguous.
+// rows; each global row segment of L elements is contiguous.  Block `blk` of
+// `nblk` (tile order remapped so that each XCD runs a contiguous range).
 template <int KIND, bool FWD, typename T, typename Tio>
-__global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, int nx, int ny, int ntx, XGeom g,
-                                                      const cx<T> *__restrict__ tw,
-                                                      const int *__restrict__ done)
+__device__ __forceinline__ void xform_y_body(const Tio *in, Tio *out, int nx, int ny, int ntx, const XGeom &g,
+                                             const cx<T> *__restrict__ tw, const int *__restrict__ done,
+                                             unsigned blk, unsigned nblk)
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile<AX_Y, T> tile{reinterpret_cast<cx<T> *>(smem), g.L, g.RS, g.psh};
-    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const unsigned t = xcd_remap(blk, nblk);
     const int i0 = (int)(t % ntx) * g.L;
     const size_t base = (size_t)(t / ntx) * nx * ny;
     auto put = [&](int q, int l, T v) {
@@ -90,23 +113,33 @@ __global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, i
         if (i < nx) out[base + (size_t)q * nx + i] = (Tio)v;
     };
     // y tiles read their rows directly (staging through LDS measured slower)
-    constexpr bool STAGED = false;
-    if constexpr (STAGED) {
-        for (int idx = threadIdx.x; idx < ny * g.L; idx += kThreads) {
-            const int l = idx & (g.L - 1), e = idx >> g.lgL, i = i0 + l;
-            tile_real(tile, e, l) = i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
-        }
-        __syncthreads();
-        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
-        tile_transform<KIND, FWD, AX_Y, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
-    } else {
-        auto src = [&](int e, int l) -> T {
-            const int i = i0 + l;
-            return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
-        };
-        tile_transform<KIND, FWD, AX_Y, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
-                                                     BlockSync());
-    }
+    auto src = [&](int e, int l) -> T {
+        const int i = i0 + l;
+        return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+    };
+    tile_transform<KIND, FWD, AX_Y, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+}
+
+template <int KIND, bool FWD, typename T, typename Tio>
+__global__ __launch_bounds__(kThreads) void k_xform_y(const Tio *in, Tio *out, int nx, int ny, int ntx, XGeom g,
+                                                      const cx<T> *__restrict__ tw,
+                                                      const int *__restrict__ done)
+{
+    xform_y_body<KIND, FWD, T, Tio>(in, out, nx, ny, ntx, g, tw, done, blockIdx.x, gridDim.x);
+}
+
+
+template <int KIND, bool FWD, typename T, typename Tio>
+__global__ __launch_bounds__(kThreads) void k_xform_y_grp(const YJob *__restrict__ jobs,
+                                                          const unsigned *__restrict__ start, int np)
+{
+    const int p = group_find(start, np, blockIdx.x);
+    const YJob &j = jobs[p];
+    const unsigned blk = blockIdx.x - start[p];
+    if (blk >= j.nblk) return;
+    Tio *d = static_cast<Tio *>(j.data);
+    xform_y_body<KIND, FWD, T, Tio>(d, d, j.nx, j.ny, j.ntx, j.g, static_cast<const cx<T> *>(j.tw), j.done, blk,
+                                    j.nblk);
 }
 
 // ---------------------------------------------------------------------------

@@ -189,3 +189,39 @@ def test_batched_velocity_components():
                 assert info["converged"] and info["residual"] <= 1e-10, (i, info)
                 assert rel(pg, po) < 1e-8, (i, rel(pg, po))
         plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_grouped_batch_matches_single_solves(c5, precision):
+    """The batch runs each step as one launch per kernel variant over all its
+    problems (grouped launches).  Each member's result and info equal, bit
+    for bit, the same problem solved by a single-problem plan with direct
+    launches: C5 members of every transform kind, periodic and bounded z of
+    several depths in one grouped z launch, and members whose z solve runs on
+    its own (the pipelined solve at nz = 200, the plain one at nz = 600)."""
+    P, N, D = 0, 1, 2
+    probs, rhs = list(c5[0][:10]), list(c5[1][:10])
+    for nx, ny, nz, bc in [(64, 48, 200, (P, P, N, N, N, D)), (32, 24, 600, (D, N, P, P, N, N)),
+                           (40, 32, 40, (N, D, D, D, P, P)), (24, 40, 72, (P, P, P, P, P, P))]:
+        dzf = np.full(nz, 2.0 / nz) if bc[4] == P else inputs.tanh_dzf(nz, 1.5, 2.0)
+        probs.append(inputs.Problem(nx, ny, nz, bc, 1.0 / nx, 2.0 / ny, dzf))
+        f = np.random.default_rng(nz + nx).standard_normal((nz, ny, nx))
+        if O.is_singular(bc):
+            f -= O.weighted_mean(f, dzf)
+        rhs.append(f)
+    say("grouped batch", precision, len(probs), "problems")
+    plan = capi.BatchedPlan(probs, precision=precision, tol=1e-10, max_iter=4)
+    fs = [torch.from_numpy(f).cuda() for f in rhs]
+    ps = [torch.zeros_like(f) for f in fs]
+    plan.solve(fs, ps)
+    torch.cuda.synchronize()
+    for i, pr in enumerate(probs):
+        single = capi.Plan(pr.nx, pr.ny, pr.nz, pr.bc, pr.dx, pr.dy, pr.dzf, precision=precision, tol=1e-10,
+                           max_iter=4)
+        p1 = torch.zeros_like(fs[i])
+        single.solve(fs[i], p1)
+        torch.cuda.synchronize()
+        assert torch.equal(p1, ps[i]), (i, pr.nx, pr.ny, pr.nz, pr.bc)
+        assert single.info() == plan.info(i), (i, single.info(), plan.info(i))
+        single.close()
+    plan.close()
