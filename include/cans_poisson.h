@@ -120,9 +120,11 @@ typedef struct cans_opts {
                            (lines per tile, radix-8 or radix-4 first) for
                            every transform kernel the plan uses on the
                            current device and keep the fastest; with
-                           xform_x AUTO on an FP32_REFINE plan whose x axis
-                           the dense form takes, also time whole refined
-                           solves with either x form and keep the faster
+                           xform_x AUTO on a single-problem FP32_REFINE plan
+                           whose x axis the dense form takes, also time whole
+                           refined solves with either x form and keep the
+                           faster (batched plans keep the FFT form, which
+                           joins the batch's grouped launches)
                            (allocates temporary fields and synchronises);
                            0: built-in choice (FFT).  Default 0. */
     int graph;          /* 1: cans_poisson_solve records the solve's kernel

@@ -117,8 +117,10 @@ struct YJob {            // y transform of one problem, in place
 struct ZJob {            // partitioned z solve of one problem
     void *data;
     const int *done;
-    int S;               // its segments (the launch's blocks may hold more waves)
-    unsigned nblk;
+    int S;               // its segments
+    int G;               // its column groups a block (the launch's blocks may hold more waves)
+    unsigned ngroups;    // its column groups
+    unsigned nblk;       // ceil(ngroups / G)
     ZArgs a;
 };
 struct RJob {            // residual pass of one problem (fused with the x transform, or norms only)
@@ -168,6 +170,7 @@ int launch_finalize_grp(const FJob *jobs, int np, int which, int check, int max_
 // problem's z solve is not a partitioned one and runs on its own)
 ZJob zjob_of(const Problem &pb, const Work &w, void *data, double *removed, const int *done, bool fp32, int &key,
              int &threads, unsigned &nblk);
+int zgroup_share(int key, int waves, int S);
 RJob rjob_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out, const int *done,
                size_t &lds);
 RJob rjob_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done, size_t &lds);

@@ -21,17 +21,22 @@ static ZArgs zargs(const Problem &pb, const Work &w, double *removed);
 // Partitioned column solve: CPB adjacent columns per block (64 or 32), z split
 // into S segments of at most MMAX levels held in registers; a wave holds
 // 64/CPB segments of the same columns (see zsolve_core.h).  The body solves
-// block `blk`'s columns with S segments; the waves beyond S (a grouped launch
-// sized for the group's deepest problem) only take part in the barriers.
+// G column groups of block `blk` (groups blk G .. blk G + G - 1), each with S
+// segments: wave w takes segment w % S of group w / S when a wave holds one
+// segment (CPB = 64); with two segments a wave (CPB = 32) G is 1.  A grouped
+// launch sizes its blocks for its deepest problem, so a shallower one puts
+// several column groups in a block; waves beyond G S only take part in the
+// barriers.
 template <typename T, int MMAX, int CPB, bool FULL, bool CYC, bool PAD>
 __device__ __forceinline__ void zsolve_part_body(T *data, const ZArgs &ag, const int *__restrict__ done,
-                                                 unsigned blk, int S)
+                                                 unsigned blk, int S, int G)
 {
     if (done && *done) return;
     constexpr int NQ = CYC ? 8 : 6;  // interface coefficients per segment
+    constexpr int GMAX = CYC ? 4 : 16;  // column groups a block (4 x 64 column ends for the periodic form)
     __shared__ double coef[NQ * 1024];
     __shared__ double zabc[3 * 512];  // the z coefficients, staged once per block
-    __shared__ double ends[CYC ? 4 * 64 : 1];  // CYC: first/last values per column
+    __shared__ double ends[CYC ? 4 * 64 * GMAX : 1];  // CYC: first/last values per column
     constexpr int SPW = 64 / CPB;  // segments per wave
     // PAD: S * MMAX levels (<= 512 for every launched shape), padding rows
     // beyond nz
@@ -45,10 +50,11 @@ __device__ __forceinline__ void zsolve_part_body(T *data, const ZArgs &ag, const
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int c = lane % CPB, seg = w * SPW + lane / CPB;
-    const bool act = seg < S;
-    auto C = [&](int q, int s) -> double & { return coef[q * 1024 + s * CPB + c]; };
-    const size_t col = (size_t)blk * CPB + c;
+    const int gi = SPW == 1 ? w / S : 0;                             // column group of the wave
+    const int c = lane % CPB, seg = SPW == 1 ? w - gi * S : w * SPW + lane / CPB;
+    const bool act = gi < G && seg < S;
+    auto C = [&](int q, int s) -> double & { return coef[q * 1024 + (gi * S + s) * CPB + c]; };
+    const size_t col = ((size_t)blk * G + gi) * CPB + c;
     const ZSeg sg = zseg(nzp, S, act ? seg : 0);
     ZLane<MMAX, CYC> L;
     if (act) {
@@ -59,7 +65,7 @@ __device__ __forceinline__ void zsolve_part_body(T *data, const ZArgs &ag, const
         for (int q = 0; q < NQ; ++q) C(q, seg) = out[q];
     }
     __syncthreads();
-    if (w == 0 && lane < CPB) {
+    if (act && seg == 0 && lane < CPB) {  // the first wave of each group
         zp_interface<CYC>(
             S, [&](int s, int q) -> double & { return C(q, s); }, [&](int s) -> double & { return C(4, s); },
             [&](int s) -> double & { return C(5, s); }, [&](int s) -> double & { return C(6, s); },
@@ -71,17 +77,18 @@ __device__ __forceinline__ void zsolve_part_body(T *data, const ZArgs &ag, const
     if constexpr (CYC) {
         const double xL2 = act && seg > 0 ? C(7, seg - 1) : 0.0;
         const double xR2 = act && seg < S - 1 ? C(6, seg + 1) : 0.0;
+        double *E = ends + gi * 4 * 64;
         if (act) {
             zp_finish<MMAX, FULL>(L, a, sg, xL, xR, xL2, xR2);
             // Sherman-Morrison: the column's first and last values of A'^-1 f
             // and A'^-1 u come from its first and last segment
             double y0, z0, yl, zl;
             zp_ends<MMAX, FULL>(L, sg, &y0, &z0, &yl, &zl);
-            if (seg == 0) { ends[c] = y0; ends[64 + c] = z0; }
-            if (seg == S - 1) { ends[128 + c] = yl; ends[192 + c] = zl; }
+            if (seg == 0) { E[c] = y0; E[64 + c] = z0; }
+            if (seg == S - 1) { E[128 + c] = yl; E[192 + c] = zl; }
         }
         __syncthreads();
-        if (act) zp_sherman_morrison<MMAX, FULL>(L, a, sg, ends[c], ends[64 + c], ends[128 + c], ends[192 + c]);
+        if (act) zp_sherman_morrison<MMAX, FULL>(L, a, sg, E[c], E[64 + c], E[128 + c], E[192 + c]);
     } else {
         if (act) zp_finish<MMAX, FULL>(L, a, sg, xL, xR);
     }
@@ -97,9 +104,9 @@ __device__ __forceinline__ void zsolve_part_body(T *data, const ZArgs &ag, const
 template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC, bool PAD = false>
 __global__ __launch_bounds__(NTMAX) void k_zsolve_part(T *data, ZArgs ag, const int *__restrict__ done)
 {
-    zsolve_part_body<T, MMAX, CPB, FULL, CYC, PAD>(data, ag, done, blockIdx.x, (int)(blockDim.x >> 6) * (64 / CPB));
+    zsolve_part_body<T, MMAX, CPB, FULL, CYC, PAD>(data, ag, done, blockIdx.x, (int)(blockDim.x >> 6) * (64 / CPB),
+                                                   1);
 }
-
 
 template <typename T, int MMAX, int CPB, int NTMAX, bool FULL, bool CYC, bool PAD>
 __global__ __launch_bounds__(NTMAX) void k_zsolve_part_grp(const ZJob *__restrict__ jobs,
@@ -109,7 +116,7 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part_grp(const ZJob *__restric
     const ZJob &j = jobs[q];
     const unsigned blk = blockIdx.x - start[q];
     if (blk >= j.nblk) return;
-    zsolve_part_body<T, MMAX, CPB, FULL, CYC, PAD>(static_cast<T *>(j.data), j.a, j.done, blk, j.S);
+    zsolve_part_body<T, MMAX, CPB, FULL, CYC, PAD>(static_cast<T *>(j.data), j.a, j.done, blk, j.S, j.G);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,7 +463,10 @@ int launch_zsolve_32(const Problem &pb, const Work &w, float *data, double *remo
 // ---------------------------------------------------------------------------
 // Grouped z solves: problems whose partitioned solve takes the same kernel
 // variant (segment depth, columns per block, thread bound, full / padded
-// segments, periodic or not) share one launch.  Variant codes:
+// segments, periodic or not) share one launch; the launch's blocks hold the
+// waves of its deepest member, and a member of S segments puts G = waves / S
+// column groups in each of its blocks (CPB = 64; at most 4 periodic).
+// Variant codes:
 //   0, 1    periodic, 8-level segments, full / ragged
 //   2, 3    8-level segments, full / padded
 //   4 .. 7  16-level segments of 64 columns: 768 threads full / padded, 1024 full / padded
@@ -477,11 +487,12 @@ ZJob zjob_of(const Problem &pb, const Work &w, void *data, double *removed, cons
     else key = (zp.cpb == 64 ? 4 : 8) + (small ? 0 : 2) + (full ? 0 : 1);
     threads = zp.threads;
     const size_t plane = (size_t)pb.nx * pb.ny;
-    nblk = (unsigned)((plane + zp.cpb - 1) / zp.cpb);
     j.data = data;
     j.done = done;
     j.S = S;
-    j.nblk = nblk;
+    j.G = 1;
+    j.ngroups = (unsigned)((plane + zp.cpb - 1) / zp.cpb);
+    nblk = j.nblk = j.ngroups;
     j.a = zargs(pb, w, removed);
     return j;
 }
@@ -510,6 +521,15 @@ static int launch_zgrp(const GroupLaunch &gl, hipStream_t s)
     }
 #undef CANS_ZG
     return check_launch();
+}
+
+// column groups a block of `waves` waves gives a member of S segments
+int zgroup_share(int key, int waves, int S)
+{
+    if (key >= 8) return 1;  // two segments a wave (32 columns)
+    const int g = waves / S;
+    const int cap = key <= 1 ? 4 : 16;
+    return g < 1 ? 1 : (g > cap ? cap : g);
 }
 
 int launch_zsolve_grp(const GroupLaunch &gl, bool fp32, hipStream_t s)

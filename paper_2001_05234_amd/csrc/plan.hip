@@ -248,7 +248,9 @@ int autotune(cans_plan_s *pl, Problem &pb)
             }
             tune(pb.ay.gy32[1], AX_Y, pb.ay, 4, [&] { return launch_y_32(pb, true, pb.ws.a32, nullptr, st); });
             tune(pb.ay.gy32[0], AX_Y, pb.ay, 4, [&] { return launch_y_32(pb, false, pb.ws.a32, nullptr, st); });
-            if (pl->opts.xform_x == CANS_XFORM_AUTO && dense_ok(pb.ax.kind, pb.nx)) {
+            // (single-problem plans only: in a batch the FFT form joins its
+            // kind's grouped launches, which a member timed alone does not see)
+            if (pl->opts.xform_x == CANS_XFORM_AUTO && pl->probs.size() == 1 && dense_ok(pb.ax.kind, pb.nx)) {
                 double *p64 = nullptr;
                 if (hipMalloc(&p64, N * sizeof(double)) != hipSuccess) rc = CANS_ERR_ALLOC;
                 if (rc == CANS_OK) {
@@ -576,6 +578,11 @@ int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
     bg.fin_solo_n.clear();
     bg.mean_solo.clear();
     std::vector<FJob> f_all, f_mean, f_x, f_n;
+    struct ZMember {
+        int key, threads;
+        ZJob job;
+    };
+    std::vector<ZMember> zmem;
     for (int i = 0; i < (int)pl->probs.size(); ++i) {
         const Problem &pb = pl->probs[i];
         const Work &w = pb.ws;
@@ -610,7 +617,7 @@ int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
         unsigned znb = 0;
         const ZJob zj = zjob_of(pb, w, data, refine ? nullptr : w.info + I_REMOVED, done, refine, zkey, zthr, znb);
         if (zkey < 0) bg.z.solo.push_back(i);
-        else add_member(z, zkey, zj, znb, zthr, 0);
+        else zmem.push_back({zkey, zthr, zj});
         if (refine) {
             size_t lds = 0;
             const RJob r = rjob_norm(pb, w, rhs[i], p[i], w.flag, lds);
@@ -629,6 +636,17 @@ int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
             if (f.nb_xfwd <= kDirectReduce) f_x.push_back(f); else bg.fin_solo_x.push_back(i);
             if (f.nb_norm <= kDirectReduce) f_n.push_back(f); else bg.fin_solo_n.push_back(i);
         }
+    }
+    // z: blocks of each variant's deepest member; a shallower member puts
+    // several column groups in a block
+    for (const ZMember &m : zmem) {
+        int waves = 0;
+        for (const ZMember &o : zmem)
+            if (o.key == m.key) waves = std::max(waves, o.threads / 64);
+        ZJob j = m.job;
+        j.G = zgroup_share(m.key, waves, j.S);
+        j.nblk = (j.ngroups + j.G - 1) / j.G;
+        add_member(z, m.key, j, j.nblk, 64 * waves, 0);
     }
     // lay the tables out in one device block
     Staging st;
