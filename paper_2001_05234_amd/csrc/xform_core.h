@@ -43,6 +43,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #define CANS_HD __host__ __device__ inline __attribute__((always_inline))
 
 namespace cans {
@@ -308,8 +310,10 @@ CANS_HD cx<T> pack(int m, const XGeom &g, const Src &src, const cx<T> *tw)
 
 // ---- unpacking map: the reals of output pair k from Z (the FFT result) -----
 // put(q, v) receives output real q of the line.
-template <int KIND, bool FWD, typename T, typename ZAt, typename Put>
-CANS_HD void unpack(int k, const XGeom &g, const ZAt &Z, const Put &put, const cx<T> *tw)
+// put2(q, a, b) receives the adjacent reals q, q+1 (the periodic pair's
+// outputs), put(q, v) every other one.
+template <int KIND, bool FWD, typename T, typename ZAt, typename Put, typename Put2>
+CANS_HD void unpack(int k, const XGeom &g, const ZAt &Z, const Put &put, const Put2 &put2, const cx<T> *tw)
 {
     const int n = g.n, M = g.M;
     const cx<T> z = Z(k);
@@ -350,11 +354,9 @@ CANS_HD void unpack(int k, const XGeom &g, const ZAt &Z, const Put &put, const c
         }
         if (KIND == K_P) {
             if (k == 0) {
-                put(0, V.re);
-                put(1, z.re - z.im);
+                put2(0, V.re, z.re - z.im);
             } else {
-                put(2 * k, V.re);
-                put(2 * k + 1, V.im);
+                put2(2 * k, V.re, V.im);
             }
             return;
         }
@@ -372,8 +374,7 @@ CANS_HD void unpack(int k, const XGeom &g, const ZAt &Z, const Put &put, const c
         return;
     }
     if (KIND == K_P) {
-        put(2 * k, z.re);
-        put(2 * k + 1, z.im);
+        put2(2 * k, z.re, z.im);
         return;
     }
     // undo Makhoul's reorder; DST-III multiplies by (-1)^i
@@ -525,8 +526,17 @@ CANS_HD void tile_transform(int tid, int nt, const XGeom &g, const Src &src, con
     for (int w = tid; w < total; w += nt) {
         int l, k;
         split_item<AXIS>(w, g.M, g.magM, g.lgL, g.L, l, k);
+        // a put that takes two adjacent reals stores them at once
+        auto put2 = [&](int q, T v0, T v1) {
+            if constexpr (std::is_invocable_v<const Put &, int, int, T, T>) {
+                put(q, l, v0, v1);
+            } else {
+                put(q, l, v0);
+                put(q + 1, l, v1);
+            }
+        };
         unpack<BK, BF, T>(
-            k, g, [&](int kk) -> cx<T> { return cur.at(kk, l); }, [&](int q, T v) { put(q, l, v); }, tw);
+            k, g, [&](int kk) -> cx<T> { return cur.at(kk, l); }, [&](int q, T v) { put(q, l, v); }, put2, tw);
     }
 }
 

@@ -29,44 +29,93 @@ __device__ __forceinline__ void xform_x_body(const Tin *in, Tout *out, long nlin
     const long line0 = (long)blk * g.L;
     const int k0 = (int)(line0 / ny), j0 = (int)(line0 - (long)k0 * ny);
     const double mp = EPI == 1 ? info[I_MEANP] : 0.0;
-    auto put = [&](int q, int l, T v) {
-        const long line = line0 + l;
-        if (line < nlines) {
-            const size_t idx = (size_t)line * n + q;
-            if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
-            else out[idx] = (Tout)v;
+    // output of line l, real q; two adjacent reals (q even, n even: an
+    // aligned pair) in one store
+    struct Put {
+        Tout *out;
+        long line0, nlines;
+        int n;
+        double mp;
+        __device__ void operator()(int q, int l, T v) const
+        {
+            const long line = line0 + l;
+            if (line < nlines) {
+                const size_t idx = (size_t)line * n + q;
+                if (EPI == 1) out[idx] = (Tout)((double)out[idx] + (double)v - mp);
+                else out[idx] = (Tout)v;
+            }
+        }
+        __device__ void operator()(int q, int l, T v0, T v1) const
+        {
+            const long line = line0 + l;
+            if (line < nlines) {
+                using V2 = typename std::conditional<sizeof(Tout) == 4, float2, double2>::type;
+                V2 *d = reinterpret_cast<V2 *>(out + (size_t)line * n + q);
+                V2 w;
+                if (EPI == 1) {
+                    const V2 o = *d;
+                    w.x = (Tout)((double)o.x + (double)v0 - mp);
+                    w.y = (Tout)((double)o.y + (double)v1 - mp);
+                } else {
+                    w.x = (Tout)v0;
+                    w.y = (Tout)v1;
+                }
+                *d = w;
+            }
         }
     };
-    // inverse real-DFT / DCT / DST synthesis and the extended lines of the
-    // face-located transforms read every input twice: stage the lines in LDS
-    // with coalesced loads first
-    constexpr bool STAGED = reads_twice(KIND, FWD);
-    if constexpr (STAGED) {
+    const Put put{out, line0, nlines, n, mp};
+    // The block's lines are staged in LDS first with coalesced loads, every
+    // load in flight at once (the syntheses of the inverses and the extended
+    // lines of the face-located transforms read each input twice; the forward
+    // transforms gain from the wide loads alone).  `acc` collects the partial
+    // weighted sum of the input when wsum_part is given.
+    double acc = 0;
+    if (g.nl == g.n) {
+        // the lines are contiguous: each thread loads its pairs of reals (one
+        // complex slot each) as vectors
+        using V2 = typename std::conditional<sizeof(Tin) == 4, float2, double2>::type;
+        constexpr int SP = sizeof(T) == 4 ? 16 : 8;  // slots a thread (tile capacity / kThreads)
+        const int M = g.M, P = M * g.L;
+        const long left = nlines - line0;
+        const int avail = (int)((left < g.L ? left : (long)g.L) * M);
+        const V2 *src2 = reinterpret_cast<const V2 *>(in + (size_t)line0 * n);
+        for (int base = 0; base < P; base += SP * kThreads) {  // one round for the default tiles
+            V2 v[SP];
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                const int idx = base + threadIdx.x + u * kThreads;
+                v[u] = src2[idx < avail ? idx : avail - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < SP; ++u) {
+                const int idx = base + threadIdx.x + u * kThreads;
+                if (idx < P) {
+                    const int l = (int)udiv((unsigned)idx, (unsigned)M, g.magM), m = idx - l * M;
+                    const bool ok = idx < avail;
+                    tile.at(m, l) = ok ? mk((T)v[u].x, (T)v[u].y) : mk(T(0), T(0));
+                    if (wsum_part && ok)
+                        acc += dzf[line_level(line0 + l, line0, k0, j0, ny)] * ((double)v[u].x + (double)v[u].y);
+                }
+            }
+        }
+    } else {
         for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
             const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
             const long line = line0 + l;
-            tile_real(tile, e, l) = line < nlines ? (T)in[line * n + e] : T(0);
+            const T x = line < nlines ? (T)in[line * n + e] : T(0);
+            tile_real(tile, e, l) = x;
+            if (wsum_part && line < nlines) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)in[line * n + e];
         }
-        __syncthreads();
-        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
-        tile_transform<KIND, FWD, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
-    } else {
-        double acc = 0;
-        auto src = [&](int e, int l) -> T {
-            const long line = line0 + l;
-            if (line >= nlines) return T(0);
-            const Tin x = in[line * n + e];
-            if (wsum_part) acc += dzf[line_level(line, line0, k0, j0, ny)] * (double)x;
-            return (T)x;
-        };
-        tile_transform<KIND, FWD, AX_X, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
-                                                     BlockSync());
-        if (wsum_part) {
-            double z1 = 0, z2 = 0;
-            block_sum3(acc, z1, z2);
-            if (threadIdx.x == 0) {
-                wsum_part[kNP * blk] = acc;
-            }
+    }
+    __syncthreads();
+    auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
+    tile_transform<KIND, FWD, AX_X, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    if (wsum_part) {
+        double z1 = 0, z2 = 0;
+        block_sum3(acc, z1, z2);
+        if (threadIdx.x == 0) {
+            wsum_part[kNP * blk] = acc;
         }
     }
 }
