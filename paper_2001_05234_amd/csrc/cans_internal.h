@@ -171,6 +171,7 @@ int launch_finalize_grp(const FJob *jobs, int np, int which, int check, int max_
 ZJob zjob_of(const Problem &pb, const Work &w, void *data, double *removed, const int *done, bool fp32, int &key,
              int &threads, unsigned &nblk);
 int zgroup_share(int key, int waves, int S);
+int resid_group_key(const Problem &pb, bool fused);
 RJob rjob_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out, const int *done,
                size_t &lds);
 RJob rjob_norm(const Problem &pb, const Work &w, const double *f, const double *p, const int *done, size_t &lds);

@@ -52,6 +52,9 @@ static inline int rslice_blocks(const Problem &pb, const RSlice &rs)
 // rows of the norm-only kernel (x lines per block)
 static inline int norm_rows(const Problem &pb) { return pb.nx <= kFlatMaxN ? flat_group(pb.nx) : 2; }
 
+// rows of exactly one chunk take the kernels' exact form
+static inline bool exact_rows(const Problem &pb) { return pb.nx == kResidChunk; }
+
 // The residual r = (f - mf) - L_h p (eq. (poi), plus the plan's shift) of the
 // rows j0 .. j0 + nr - 1 (nr <= 2) of plane k, block-wide, in chunks of
 // kResidChunk points of a row.  Each thread first loads all it needs of the
@@ -68,11 +71,12 @@ struct RAcc {
     double srr = 0, sff = 0, spw = 0, rmax = 0, fmx = 0;
 };
 
-template <typename Put>
+// EXACT: rows of exactly kResidChunk points (one chunk, no bounds to check).
+template <bool EXACT, typename Put>
 __device__ void resid_pair(const double *__restrict__ f, const double *__restrict__ p, int k, int j0, int nr,
                            const LapArgs &la, double mf, double wk, double *rows, Put put, RAcc &acc)
 {
-    const int n = la.nx, ny = la.ny, nz = la.nz;
+    const int n = EXACT ? kResidChunk : la.nx, ny = la.ny, nz = la.nz;
     const size_t sy = (size_t)n, sz = (size_t)n * ny;
     const double *pk = p + sz * k;
     const int t = (int)threadIdx.x, rs = kResidChunk + 2;
@@ -88,9 +92,12 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
         else if (j >= ny) beyond(la.bc[3], false, ny, j, sg[l]);
         rp[l] = pk + sy * j;
     }
-    const double *zm_pl = k > 0 ? pk - sz : p + sz * (nz - 1);  // wrap plane at a boundary
-    const double *zp_pl = k < nz - 1 ? pk + sz : p;
-    const bool zm_in = k > 0, zp_in = k < nz - 1;
+    // the planes below and above; at a wall the plane itself with the sign of
+    // its ghost rule (Neumann +, Dirichlet and the face-located z field -),
+    // so every point takes one multiply instead of a select
+    const double *zm_pl = k > 0 ? pk - sz : (la.bc[4] == 0 ? p + sz * (nz - 1) : pk);
+    const double *zp_pl = k < nz - 1 ? pk + sz : (la.bc[5] == 0 ? p : pk);
+    const double gzm = (k > 0 || la.bc[4] <= 1) ? 1.0 : -1.0, gzp = (k < nz - 1 || la.bc[5] <= 1) ? 1.0 : -1.0;
     const double zaf = la.zaf[k], zcf = la.zcf[k];
     const double *fk = f + sz * k;
     for (int e0 = 0; e0 < n; e0 += kResidChunk) {
@@ -102,7 +109,7 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
 #pragma unroll
             for (int u = 0; u < kResidU; ++u) {
                 const int e = e0 + t + u * kThreads;
-                c[l][u] = sg[l] * rp[l][e < n ? e : n - 1];
+                c[l][u] = sg[l] * rp[l][EXACT || e < n ? e : n - 1];
             }
         __syncthreads();  // the previous chunk's reads of `rows` are done
         // the rows' chunk in LDS, with the x neighbours just outside it
@@ -111,7 +118,7 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
 #pragma unroll
             for (int u = 0; u < kResidU; ++u) {
                 const int e = e0 + t + u * kThreads;
-                if (e < n) rows[l * rs + 1 + t + u * kThreads] = c[l + 1][u];
+                if (EXACT || e < n) rows[l * rs + 1 + t + u * kThreads] = c[l + 1][u];
             }
         if (t < 2 * 2) {
             // x neighbours just outside the chunk: the next chunk's first
@@ -137,7 +144,7 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
 #pragma unroll
             for (int u = 0; u < kResidU; ++u) {
                 const int e = e0 + t + u * kThreads;
-                const size_t o = ro + (e < n ? e : 0);
+                const size_t o = ro + (EXACT || e < n ? e : 0);
                 zmv[u] = zm_pl[o];
                 zpv[u] = zp_pl[o];
                 fvv[u] = fk[o];
@@ -146,12 +153,11 @@ __device__ void resid_pair(const double *__restrict__ f, const double *__restric
             for (int u = 0; u < kResidU; ++u) {
                 const int e = e0 + t + u * kThreads;
                 const int q = 1 + t + u * kThreads;
-                if (e < n) {
+                if (EXACT || e < n) {
                     const double cc = c[l + 1][u];
                     const double xm = rows[l * rs + q - 1], xp = rows[l * rs + q + 1];
                     const double ym = c[l][u], yp = c[l + 2][u];
-                    const double zm = zm_in ? zmv[u] : ghost(la.bc[4], cc, zmv[u]);
-                    const double zp = zp_in ? zpv[u] : ghost(la.bc[5], cc, zpv[u]);
+                    const double zm = gzm * zmv[u], zp = gzp * zpv[u];
                     const double fv = fvv[u] - mf;
                     const double lap = (xm - 2.0 * cc + xp) * la.idx2 + (ym - 2.0 * cc + yp) * la.idy2 +
                                        zcf * (zp - cc) - zaf * (cc - zm) + la.shift * cc;
@@ -224,9 +230,12 @@ __device__ void resid_rows_flat(const double *__restrict__ f, const double *__re
         else row[n] = across(la.bc[1], false, row, n - 1, n - 1, n, 1);
     }
     __syncthreads();
-    const double *zm_pl = k > 0 ? pk - sz : p + sz * (nz - 1);  // wrap plane at a boundary
-    const double *zp_pl = k < nz - 1 ? pk + sz : p;
-    const bool zm_in = k > 0, zp_in = k < nz - 1;
+    // the planes below and above; at a wall the plane itself with the sign of
+    // its ghost rule (Neumann +, Dirichlet and the face-located z field -),
+    // so every point takes one multiply instead of a select
+    const double *zm_pl = k > 0 ? pk - sz : (la.bc[4] == 0 ? p + sz * (nz - 1) : pk);
+    const double *zp_pl = k < nz - 1 ? pk + sz : (la.bc[5] == 0 ? p : pk);
+    const double gzm = (k > 0 || la.bc[4] <= 1) ? 1.0 : -1.0, gzp = (k < nz - 1 || la.bc[5] <= 1) ? 1.0 : -1.0;
     const double zaf = la.zaf[k], zcf = la.zcf[k];
     const double *fk = f + sz * k;
     const int np = nr * n;
@@ -249,8 +258,7 @@ __device__ void resid_rows_flat(const double *__restrict__ f, const double *__re
             const double *q = rows + (rr[u] + 1) * rs + 1 + ee[u];
             const double cc = q[0];
             const double xm = q[-1], xp = q[1], ym = q[-rs], yp = q[rs];
-            const double zm = zm_in ? zmv[u] : ghost(la.bc[4], cc, zmv[u]);
-            const double zp = zp_in ? zpv[u] : ghost(la.bc[5], cc, zpv[u]);
+            const double zm = gzm * zmv[u], zp = gzp * zpv[u];
             const double fv = fvv[u] - mf;
             const double lap = (xm - 2.0 * cc + xp) * la.idx2 + (ym - 2.0 * cc + yp) * la.idy2 +
                                zcf * (zp - cc) - zaf * (cc - zm) + la.shift * cc;
@@ -269,20 +277,22 @@ __device__ void resid_rows_flat(const double *__restrict__ f, const double *__re
 // The residual rows of block blk in either mapping (H > 0: XCD slices, rows
 // of one plane in pairs; H = 0: flat, bpp = G rows a group).  put(l, e, r)
 // receives line l of the block; line0 and lv give its first line and count.
-template <typename Put>
+// EX: the slice mapping over rows of exactly kResidChunk points only (its own
+// kernels, so that the general paths do not raise their register count).
+template <bool EX, typename Put>
 __device__ __forceinline__ void resid_block(const double *__restrict__ f, const double *__restrict__ p, int H,
                                             int bpp, int L, const LapArgs &la, double mf,
                                             const double *__restrict__ dzf, double *rows, unsigned blk, Put put,
                                             RAcc &acc, long &line0, int &lv)
 {
     const int ny = la.ny;
-    if (H > 0) {
+    if (EX || H > 0) {
         int k, j0;
         rslice_of(blk, H, bpp, L, ny, la.nz, k, j0, lv);
         line0 = (long)k * ny + j0;
         for (int l0 = 0; l0 < lv; l0 += 2)
-            resid_pair(f, p, k, j0 + l0, min(2, lv - l0), la, mf, dzf[k], rows,
-                       [&](int l, int e, double r) { put(l0 + l, e, r); }, acc);
+            resid_pair<EX>(f, p, k, j0 + l0, min(2, lv - l0), la, mf, dzf[k], rows,
+                           [&](int l, int e, double r) { put(l0 + l, e, r); }, acc);
         return;
     }
     const long nlines = (long)ny * la.nz;
@@ -302,7 +312,7 @@ __device__ __forceinline__ void resid_block(const double *__restrict__ f, const 
 // block partials: sums of |r|^2, |f - mean|^2, dzf p; maxima of |r|, |f - mean|.
 // The bodies take the block index, so that one launch can serve one problem
 // (blk = blockIdx.x) or a group of problems (the *_grp kernels).
-template <int KIND>
+template <int KIND, bool EX>
 __device__ __forceinline__ void resid_xfwd_body(const double *__restrict__ f, const double *__restrict__ p,
                                                 float *out, int H, int bpp, const XGeom &g, int rows_off,
                                                 const cx<float> *__restrict__ tw, const LapArgs &la,
@@ -318,8 +328,8 @@ __device__ __forceinline__ void resid_xfwd_body(const double *__restrict__ f, co
     RAcc acc;
     long line0;
     int lv;
-    resid_block(f, p, H, bpp, L, la, info[I_REMOVED], dzf, rows, blk,
-                [&](int l, int e, double r) { tile_real(tile, e, l) = (float)r; }, acc, line0, lv);
+    resid_block<EX>(f, p, H, bpp, L, la, info[I_REMOVED], dzf, rows, blk,
+                    [&](int l, int e, double r) { tile_real(tile, e, l) = (float)r; }, acc, line0, lv);
     if (lv > 0) {
         for (int idx = threadIdx.x; idx < (L - lv) * n; idx += kThreads)
             tile_real(tile, idx % n, lv + idx / n) = 0.f;
@@ -333,7 +343,7 @@ __device__ __forceinline__ void resid_xfwd_body(const double *__restrict__ f, co
     put_partial(partials, blk, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
 }
 
-template <int KIND>
+template <int KIND, bool EX>
 __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restrict__ f,
                                                          const double *__restrict__ p, float *out, int H, int bpp,
                                                          XGeom g, int rows_off, const cx<float> *__restrict__ tw,
@@ -343,11 +353,12 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd(const double *__restric
                                                          double *__restrict__ partials,
                                                          const int *__restrict__ done)
 {
-    resid_xfwd_body<KIND>(f, p, out, H, bpp, g, rows_off, tw, la, dzf, info, partials, done, blockIdx.x);
+    resid_xfwd_body<KIND, EX>(f, p, out, H, bpp, g, rows_off, tw, la, dzf, info, partials, done, blockIdx.x);
 }
 
 // Residual norms only (the check after a correction): the same block
 // partials over norm_rows() rows a block.
+template <bool EX>
 __device__ __forceinline__ void resid_norm_body(const double *__restrict__ f, const double *__restrict__ p, int H,
                                                 int bpp, int L, const LapArgs &la, const double *__restrict__ dzf,
                                                 const double *__restrict__ info, double *__restrict__ partials,
@@ -359,10 +370,11 @@ __device__ __forceinline__ void resid_norm_body(const double *__restrict__ f, co
     RAcc acc;
     long line0;
     int lv;
-    resid_block(f, p, H, bpp, L, la, info[I_REMOVED], dzf, rows, blk, [](int, int, double) {}, acc, line0, lv);
+    resid_block<EX>(f, p, H, bpp, L, la, info[I_REMOVED], dzf, rows, blk, [](int, int, double) {}, acc, line0, lv);
     put_partial(partials, blk, acc.srr, acc.sff, acc.spw, acc.rmax, acc.fmx);
 }
 
+template <bool EX>
 __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restrict__ f,
                                                          const double *__restrict__ p, int H, int bpp, int L,
                                                          LapArgs la, const double *__restrict__ dzf,
@@ -370,11 +382,11 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(const double *__restric
                                                          double *__restrict__ partials,
                                                          const int *__restrict__ done)
 {
-    resid_norm_body(f, p, H, bpp, L, la, dzf, info, partials, done, blockIdx.x);
+    resid_norm_body<EX>(f, p, H, bpp, L, la, dzf, info, partials, done, blockIdx.x);
 }
 
 
-template <int KIND>
+template <int KIND, bool EX>
 __global__ __launch_bounds__(kThreads) void k_resid_xfwd_grp(const RJob *__restrict__ jobs,
                                                              const unsigned *__restrict__ start, int np)
 {
@@ -382,10 +394,11 @@ __global__ __launch_bounds__(kThreads) void k_resid_xfwd_grp(const RJob *__restr
     const RJob &j = jobs[q];
     const unsigned blk = blockIdx.x - start[q];
     if (blk >= j.nblk) return;
-    resid_xfwd_body<KIND>(j.f, j.p, j.out, j.H, j.bpp, j.g, j.rows_off, static_cast<const cx<float> *>(j.tw), j.la,
+    resid_xfwd_body<KIND, EX>(j.f, j.p, j.out, j.H, j.bpp, j.g, j.rows_off, static_cast<const cx<float> *>(j.tw), j.la,
                           j.dzf, j.info, j.partials, j.done, blk);
 }
 
+template <bool EX>
 __global__ __launch_bounds__(kThreads) void k_resid_norm_grp(const RJob *__restrict__ jobs,
                                                              const unsigned *__restrict__ start, int np)
 {
@@ -393,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm_grp(const RJob *__restr
     const RJob &j = jobs[q];
     const unsigned blk = blockIdx.x - start[q];
     if (blk >= j.nblk) return;
-    resid_norm_body(j.f, j.p, j.H, j.bpp, j.L, j.la, j.dzf, j.info, j.partials, j.done, blk);
+    resid_norm_body<EX>(j.f, j.p, j.H, j.bpp, j.L, j.la, j.dzf, j.info, j.partials, j.done, blk);
 }
 
 // First level of the block-partial reductions: block b reduces its contiguous
@@ -576,9 +589,15 @@ int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const d
     const size_t sh = resid_xfwd_lds(pb, g);
     if (sh > kResidLdsMax) return CANS_ERR_UNSUPPORTED;
     const dim3 grid((unsigned)rslice_blocks(pb, rs));
-    CANS_KIND_SWITCH(pb.ax.kind,
-        hipLaunchKernelGGL(k_resid_xfwd<KD>, grid, dim3(kThreads), sh, s, f, p, out, rs.H, rs.bpp, g, (int)off,
-                           pb.ax.d_tw32, lapargs(pb), pb.d_dzf, w.info, w.partials, done));
+    if (exact_rows(pb)) {
+        CANS_KIND_SWITCH(pb.ax.kind,
+            hipLaunchKernelGGL((k_resid_xfwd<KD, true>), grid, dim3(kThreads), sh, s, f, p, out, rs.H, rs.bpp, g,
+                               (int)off, pb.ax.d_tw32, lapargs(pb), pb.d_dzf, w.info, w.partials, done));
+    } else {
+        CANS_KIND_SWITCH(pb.ax.kind,
+            hipLaunchKernelGGL((k_resid_xfwd<KD, false>), grid, dim3(kThreads), sh, s, f, p, out, rs.H, rs.bpp, g,
+                               (int)off, pb.ax.d_tw32, lapargs(pb), pb.d_dzf, w.info, w.partials, done));
+    }
     return check_launch();
 }
 
@@ -587,8 +606,12 @@ int launch_resid_norm(const Problem &pb, const Work &w, const double *f, const d
 {
     const RSlice rs = rslice(pb, norm_rows(pb));
     const size_t sh = (size_t)kRowsD * sizeof(double);
-    hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)rslice_blocks(pb, rs)), dim3(kThreads), sh, s, f, p, rs.H,
-                       rs.bpp, rs.L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
+    if (exact_rows(pb))
+        hipLaunchKernelGGL(k_resid_norm<true>, dim3((unsigned)rslice_blocks(pb, rs)), dim3(kThreads), sh, s, f, p,
+                           rs.H, rs.bpp, rs.L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
+    else
+        hipLaunchKernelGGL(k_resid_norm<false>, dim3((unsigned)rslice_blocks(pb, rs)), dim3(kThreads), sh, s, f, p,
+                           rs.H, rs.bpp, rs.L, lapargs(pb), pb.d_dzf, w.info, w.partials, done);
     return check_launch();
 }
 
@@ -603,16 +626,14 @@ size_t resid_xfwd_lds(const Problem &pb, const XGeom &g)
 // 160 KiB of a CU less each kernel's static LDS (its reductions)
 int plan_resid(const Problem &pb)
 {
-    const void *ks[] = {(const void *)k_resid_xfwd<K_P>,   (const void *)k_resid_xfwd<K_NN>,
-                        (const void *)k_resid_xfwd<K_DD>,  (const void *)k_resid_xfwd<K_ND>,
-                        (const void *)k_resid_xfwd<K_DN>,  (const void *)k_resid_xfwd<K_S1>,
-                        (const void *)k_resid_xfwd<K_C1>,  (const void *)k_resid_xfwd<K_FDN>,
-                        (const void *)k_resid_xfwd<K_FND>, (const void *)k_resid_norm,
-                        (const void *)k_resid_xfwd_grp<K_P>,   (const void *)k_resid_xfwd_grp<K_NN>,
-                        (const void *)k_resid_xfwd_grp<K_DD>,  (const void *)k_resid_xfwd_grp<K_ND>,
-                        (const void *)k_resid_xfwd_grp<K_DN>,  (const void *)k_resid_xfwd_grp<K_S1>,
-                        (const void *)k_resid_xfwd_grp<K_C1>,  (const void *)k_resid_xfwd_grp<K_FDN>,
-                        (const void *)k_resid_xfwd_grp<K_FND>, (const void *)k_resid_norm_grp};
+    const void *ks[] = {
+#define CANS_RX(K) (const void *)k_resid_xfwd<K, true>, (const void *)k_resid_xfwd<K, false>, \
+                   (const void *)k_resid_xfwd_grp<K, true>, (const void *)k_resid_xfwd_grp<K, false>
+        CANS_RX(K_P), CANS_RX(K_NN), CANS_RX(K_DD), CANS_RX(K_ND), CANS_RX(K_DN),
+        CANS_RX(K_S1), CANS_RX(K_C1), CANS_RX(K_FDN), CANS_RX(K_FND),
+#undef CANS_RX
+        (const void *)k_resid_norm<true>, (const void *)k_resid_norm<false>,
+        (const void *)k_resid_norm_grp<true>, (const void *)k_resid_norm_grp<false>};
     (void)pb;
     for (const void *k : ks) {
         hipFuncAttributes fa;
@@ -734,20 +755,31 @@ RJob rjob_norm(const Problem &pb, const Work &w, const double *f, const double *
     return j;
 }
 
+// group keys: 2 kind + exact (fused pass), exact (norm pass)
 int launch_resid_xfwd_grp(const GroupLaunch &gl, hipStream_t s)
 {
     const RJob *j = static_cast<const RJob *>(gl.jobs);
-    CANS_KIND_SWITCH(gl.key, hipLaunchKernelGGL(k_resid_xfwd_grp<KD>, dim3(gl.blocks), dim3(kThreads), gl.lds, s, j,
-                                                gl.start, gl.np));
+    if (gl.key & 1) {
+        CANS_KIND_SWITCH(gl.key >> 1, hipLaunchKernelGGL((k_resid_xfwd_grp<KD, true>), dim3(gl.blocks),
+                                                         dim3(kThreads), gl.lds, s, j, gl.start, gl.np));
+    } else {
+        CANS_KIND_SWITCH(gl.key >> 1, hipLaunchKernelGGL((k_resid_xfwd_grp<KD, false>), dim3(gl.blocks),
+                                                         dim3(kThreads), gl.lds, s, j, gl.start, gl.np));
+    }
     return check_launch();
 }
 
 int launch_resid_norm_grp(const GroupLaunch &gl, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resid_norm_grp, dim3(gl.blocks), dim3(kThreads), gl.lds, s,
-                       static_cast<const RJob *>(gl.jobs), gl.start, gl.np);
+    const RJob *j = static_cast<const RJob *>(gl.jobs);
+    if (gl.key)
+        hipLaunchKernelGGL(k_resid_norm_grp<true>, dim3(gl.blocks), dim3(kThreads), gl.lds, s, j, gl.start, gl.np);
+    else
+        hipLaunchKernelGGL(k_resid_norm_grp<false>, dim3(gl.blocks), dim3(kThreads), gl.lds, s, j, gl.start, gl.np);
     return check_launch();
 }
+
+int resid_group_key(const Problem &pb, bool fused) { return fused ? 2 * pb.ax.kind + exact_rows(pb) : exact_rows(pb); }
 
 int launch_reset_grp(const FJob *jobs, int np, hipStream_t s)
 {

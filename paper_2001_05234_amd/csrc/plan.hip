@@ -607,7 +607,7 @@ int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
                 size_t lds = 0;
                 const RJob r = rjob_xfwd(pb, w, rhs[i], p[i], w.a32, w.flag, lds);
                 if (lds > kResidLdsMax) return CANS_ERR_UNSUPPORTED;
-                add_member(rx, pb.ax.kind, r, r.nblk, kThreads, lds);
+                add_member(rx, resid_group_key(pb, true), r, r.nblk, kThreads, lds);
             }
         }
         const YJob jyf = yjob(pb, data, gyf, twy, done), jyi = yjob(pb, data, gyi, twy, done);
@@ -621,7 +621,7 @@ int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
         if (refine) {
             size_t lds = 0;
             const RJob r = rjob_norm(pb, w, rhs[i], p[i], w.flag, lds);
-            add_member(rn, 0, r, r.nblk, kThreads, lds);
+            add_member(rn, resid_group_key(pb, false), r, r.nblk, kThreads, lds);
             FJob f{};
             f.partials = w.partials;
             f.info = w.info;
