@@ -35,6 +35,7 @@ struct Axis {
     // tile geometry as an x or a y transform, FP64 / FP32, [0] inverse [1] forward
     XGeom gx64[2]{}, gx32[2]{};
     XGeom gy64[2]{}, gy32[2]{};
+    XGeom gxr32{};             // the forward FP32 x tile of the kernel fused with the residual
     double *d_lam = nullptr;   // mu(q)/h^2 in the transform's row order
     cx<double> *d_tw64 = nullptr;
     cx<float> *d_tw32 = nullptr;

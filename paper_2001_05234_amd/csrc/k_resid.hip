@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void k_dense_resid(const double *__restrict__ 
 int resid_blocks_xfwd(const Problem &pb)
 {
     if (pb.ax.dense) return (int)dense_grid(pb).x;
-    return rslice_blocks(pb, rslice(pb, pb.ax.gx32[1].L));
+    return rslice_blocks(pb, rslice(pb, pb.ax.gxr32.L));
 }
 
 int resid_blocks_norm(const Problem &pb) { return rslice_blocks(pb, rslice(pb, norm_rows(pb))); }
@@ -583,7 +583,7 @@ int launch_resid_xfwd(const Problem &pb, const Work &w, const double *f, const d
                            pb.d_dzf, w.info, w.partials, done);
         return check_launch();
     }
-    const XGeom &g = pb.ax.gx32[1];
+    const XGeom &g = pb.ax.gxr32;
     const RSlice rs = rslice(pb, g.L);
     const size_t off = (tile_lds(AX_X, g, sizeof(float)) + 15) / 16 * 16;
     const size_t sh = resid_xfwd_lds(pb, g);
@@ -714,7 +714,7 @@ int launch_reset(const Problem &pb, const Work &w, hipStream_t s)
 RJob rjob_xfwd(const Problem &pb, const Work &w, const double *f, const double *p, float *out, const int *done,
                size_t &lds)
 {
-    const XGeom &g = pb.ax.gx32[1];
+    const XGeom &g = pb.ax.gxr32;
     const RSlice rs = rslice(pb, g.L);
     lds = resid_xfwd_lds(pb, g);
     RJob j{};

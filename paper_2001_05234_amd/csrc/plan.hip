@@ -124,6 +124,7 @@ int build_axis(cans_plan_s *pl, Axis &a, int kind, int n, double h, double shift
         if (!make_geom(a.gx64[d], AX_X, kind, n, 8) || !make_geom(a.gx32[d], AX_X, kind, n, 4) ||
             !make_geom(a.gy64[d], AX_Y, kind, n, 8) || !make_geom(a.gy32[d], AX_Y, kind, n, 4))
             return CANS_ERR_UNSUPPORTED;
+    a.gxr32 = a.gx32[1];
     std::vector<cx<double>> t64 = twiddles(fft_len(kind, n));
     std::vector<cx<float>> t32(t64.size());
     for (size_t i = 0; i < t64.size(); ++i) t32[i] = mk((float)t64[i].re, (float)t64[i].im);
@@ -239,9 +240,13 @@ int autotune(cans_plan_s *pl, Problem &pb)
             if (!pb.ax.dense) {
                 // the forward tile is also the residual kernel's: only candidates
                 // whose residual LDS fits
-                tune(pb.ax.gx32[1], AX_X, pb.ax, 4, [&] {
-                    if (resid_xfwd_lds(pb, pb.ax.gx32[1]) > kResidLdsMax) return (int)CANS_ERR_UNSUPPORTED;
-                    return launch_x_fwd_32(pb, pb.ws, s64, pb.ws.a32, nullptr, st);
+                tune(pb.ax.gx32[1], AX_X, pb.ax, 4,
+                     [&] { return launch_x_fwd_32(pb, pb.ws, s64, pb.ws.a32, nullptr, st); });
+                // the residual's fused transform: its own tile, timed as the
+                // fused kernel (f = p = the scratch field)
+                tune(pb.ax.gxr32, AX_X, pb.ax, 4, [&] {
+                    if (resid_xfwd_lds(pb, pb.ax.gxr32) > kResidLdsMax) return (int)CANS_ERR_UNSUPPORTED;
+                    return launch_resid_xfwd(pb, pb.ws, s64, s64, pb.ws.a32, pb.ws.flag, st);
                 });
                 tune(pb.ax.gx32[0], AX_X, pb.ax, 4,
                      [&] { return launch_x_inv_32(pb, pb.ws, pb.ws.a32, s64, false, nullptr, st); });
