@@ -161,12 +161,50 @@ __device__ __forceinline__ void xform_y_body(const Tio *in, Tio *out, int nx, in
         const int i = i0 + l;
         if (i < nx) out[base + (size_t)q * nx + i] = (Tio)v;
     };
-    // y tiles read their rows directly (staging through LDS measured slower)
-    auto src = [&](int e, int l) -> T {
-        const int i = i0 + l;
-        return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
-    };
-    tile_transform<KIND, FWD, AX_Y, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    constexpr int V = 16 / sizeof(Tio);  // reals of one 16-byte load
+    if (reads_twice(KIND, FWD) && g.L % V == 0 && nx % V == 0) {
+        // transforms that read each input twice (the syntheses, the extended
+        // face lines) stage the tile's row segments in LDS: 16-byte loads,
+        // every one in flight before the first LDS write (measured: the
+        // forward transforms gain nothing from it and read their rows
+        // directly)
+        using VT = typename std::conditional<sizeof(Tio) == 4, float4, double2>::type;
+        const int vpr = g.L / V;              // vectors of a row segment
+        const int nv = g.nl * vpr;            // vectors of the tile
+        const int lg = vpr == 1 ? 0 : (vpr == 2 ? 1 : (vpr == 4 ? 2 : (vpr == 8 ? 3 : 4)));
+        constexpr int SV = 8;                 // vectors a thread per round (tile capacity / kThreads)
+        for (int b0 = 0; b0 < nv; b0 += SV * kThreads) {
+            VT v[SV];
+#pragma unroll
+            for (int u = 0; u < SV; ++u) {
+                const int idx = min(b0 + (int)threadIdx.x + u * kThreads, nv - 1);
+                const int e = idx >> lg, c = (idx - (e << lg)) * V;
+                const int i = min(i0 + c, nx - V);  // a segment past the last column: any in-range load
+                v[u] = *reinterpret_cast<const VT *>(in + base + (size_t)e * nx + i);
+            }
+#pragma unroll
+            for (int u = 0; u < SV; ++u) {
+                const int idx = b0 + (int)threadIdx.x + u * kThreads;
+                if (idx < nv) {
+                    const int e = idx >> lg, c = (idx - (e << lg)) * V;
+                    const bool in_x = i0 + c < nx;
+                    const Tio *w = reinterpret_cast<const Tio *>(&v[u]);
+#pragma unroll
+                    for (int q = 0; q < V; ++q) tile_real(tile, e, c + q) = in_x ? (T)w[q] : T(0);
+                }
+            }
+        }
+        __syncthreads();
+        auto src = [&](int e, int l) -> T { return tile_real(tile, e, l); };
+        tile_transform<KIND, FWD, AX_Y, true, true>(threadIdx.x, kThreads, g, src, put, tile, tile, tw, BlockSync());
+    } else {
+        auto src = [&](int e, int l) -> T {
+            const int i = i0 + l;
+            return i < nx ? (T)in[base + (size_t)e * nx + i] : T(0);
+        };
+        tile_transform<KIND, FWD, AX_Y, true, false>(threadIdx.x, kThreads, g, src, put, tile, tile, tw,
+                                                     BlockSync());
+    }
 }
 
 template <int KIND, bool FWD, typename T, typename Tio>
