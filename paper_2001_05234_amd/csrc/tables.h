@@ -72,14 +72,15 @@ inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // Tile of L lines for an n-point transform with elements of `elem` bytes:
 // lines per tile such that a tile holds at most 4096 complex values (2048 in
 // FP64), 3840 when M has a factor 3 or 5 (the in-place stages hold at most
-// 16 complex values per thread of a 256-thread block); y tiles at most 32
-// (FP32) / 16 (FP64) columns.
+// 16 complex values per thread of a 256-thread block); x tiles at most 256
+// lines (short lines fill a tile with many), y tiles at most 32 (FP32) / 16
+// (FP64) columns.
 inline int tile_lines(int axis, int n, int elem)
 {
     const int M = n / 2 > 0 ? n / 2 : 1;
     long cap = elem == 8 ? 2048 : 4096;
     if (!is_pow2(M)) cap = std::min<long>(cap, 3840);
-    const int lmax = axis == AX_X ? 64 : (elem == 8 ? 16 : 32);
+    const int lmax = axis == AX_X ? 256 : (elem == 8 ? 16 : 32);
     return std::max(1, std::min(lmax, pow2floor(std::max<long>(1, cap / M))));
 }
 
@@ -98,7 +99,7 @@ inline bool make_geom(XGeom &g, int axis, int kind, int nl, int elem, int L = 0,
     g.nl = nl;
     g.M = n / 2;
     g.L = L > 0 ? L : tile_lines(axis, n, elem);
-    if (!is_pow2(g.L) || g.L > (axis == AX_X ? 64 : 32)) return false;
+    if (!is_pow2(g.L) || g.L > (axis == AX_X ? 256 : 32)) return false;
     g.lgL = 0;
     while ((1 << g.lgL) < g.L) ++g.lgL;
     g.psh = elem == 8 ? 4 : 5;  // 256-byte LDS rows of 16-byte / 8-byte slots
