@@ -126,8 +126,32 @@ static __device__ inline double vel_at(const RateArgs &r, int comp, int i, int j
     return sgn * f[(size_t)idx[0] + (size_t)r.nx * ((size_t)idx[1] + (size_t)r.ny * idx[2])];
 }
 
+// an interior cell (every neighbour the rates use exists): the same loads and
+// arithmetic as below by direct offsets
+static __device__ inline double cell_rate_interior(const RateArgs &r, size_t e, int k)
+{
+    const size_t sy = (size_t)r.nx, sz = (size_t)r.nx * r.ny;
+    const double *u = r.u + e, *v = r.v + e, *w = r.w + e;
+    const double idz = 1.0 / r.dzf[k];
+    const double ux = fabs(u[0]);
+    const double vx = 0.25 * fabs(v[0] + v[-(ptrdiff_t)sy] + v[1] + v[1 - (ptrdiff_t)sy]);
+    const double wx = 0.25 * fabs(w[0] + w[-(ptrdiff_t)sz] + w[1] + w[1 - (ptrdiff_t)sz]);
+    const double rx = ux * r.idx + vx * r.idy + wx * idz;
+    const double uy = 0.25 * fabs(u[0] + u[-1] + u[sy] + u[sy - 1]);
+    const double vy = fabs(v[0]);
+    const double wy = 0.25 * fabs(w[0] + w[-(ptrdiff_t)sz] + w[sy] + w[(ptrdiff_t)sy - (ptrdiff_t)sz]);
+    const double ry = uy * r.idx + vy * r.idy + wy * idz;
+    const double uz = 0.25 * fabs(u[0] + u[-1] + u[sz] + u[sz - 1]);
+    const double vz = 0.25 * fabs(v[0] + v[-(ptrdiff_t)sy] + v[sz] + v[sz - sy]);
+    const double wz = fabs(w[0]);
+    const double rz = uz * r.idx + vz * r.idy + wz / r.dzc[k];
+    return fmax(rx, fmax(ry, rz));
+}
+
 static __device__ inline double cell_rate(const RateArgs &r, int i, int j, int k)
 {
+    if (i > 0 && i < r.nx - 1 && j > 0 && j < r.ny - 1 && k > 0 && k < r.nz - 1)
+        return cell_rate_interior(r, (size_t)i + (size_t)r.nx * ((size_t)j + (size_t)r.ny * k), k);
     const double idz = 1.0 / r.dzf[k];
     const double ux = fabs(vel_at(r, 0, i, j, k));
     const double vx = 0.25 * fabs(vel_at(r, 1, i, j, k) + vel_at(r, 1, i, j - 1, k) + vel_at(r, 1, i + 1, j, k) +
