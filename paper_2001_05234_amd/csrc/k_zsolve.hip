@@ -133,12 +133,26 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part_grp(const ZJob *__restric
 // the rhs is read from LDS in the reduction and again in the finish.  !DB (one
 // buffer): the rhs is copied to registers first and the next fetch starts
 // after that.  lambda of the next tile is loaded after the stores, so the only
-// wait for global memory is the one at the top of an iteration.
+// wait for global memory is the one at the top of an iteration.  The barriers
+// inside an iteration order LDS traffic only (pipe_lds_barrier): a full
+// __syncthreads there would also wait for the next tile's fetch, which writes
+// LDS under the vector memory counter.  The next tile is claimed after the
+// stores for the same reason: reading the atomic's result waits for every
+// vector memory operation issued before it.
 // Levels beyond nz (the segments cover S * MMAX >= nz) are the decoupled
 // padding rows of zpad_row; their loads are clamped to a real level and
 // replaced by zero, their stores skipped.
 
 typedef __attribute__((address_space(3))) void lds_void;
+
+// Workgroup barrier for LDS data: waits for this wave's LDS operations only,
+// not for its vector memory operations (global loads into LDS still in flight
+// target the other tile buffer).  The memory clobber keeps the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void pipe_lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 template <typename T>
 struct PipeGeom {
@@ -268,10 +282,9 @@ __global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag,
         } else {
 #pragma unroll
             for (int q = 0; q < MMAX; ++q) f[q] = raw(cur, q);
-            __syncthreads();
+            pipe_lds_barrier();
             if (tn < ntiles) fetch(tn, buf0);
         }
-        if (threadIdx.x == 0 && tn < ntiles) claim = (int)atomicAdd(&ctr[0], 1u);
         auto fv = [&](int q) -> double {
             if constexpr (DB) return scale * (double)raw(cur, q);
             else return scale * (double)f[q];
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag,
         zp_sweep_reduce<MMAX>(fv, za, zb, zc, lam, r, out);
 #pragma unroll
         for (int q = 0; q < 6; ++q) C(q, seg, c) = out[q];
-        __syncthreads();
+        pipe_lds_barrier();
         if (w == 0) {
             // lanes [0, 32): top role, [32, 64): bottom role of column lane & 31
             const bool bot = lane >= 32;
@@ -291,7 +304,7 @@ __global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag,
             const double y2o = __shfl_xor(y2, 32, 64), g2o = __shfl_xor(g2, 32, 64);
             zp_ends_backward<4>(S, bot, Cc, zp_ends_meet(y2, g2, y2o, g2o));
         }
-        __syncthreads();
+        pipe_lds_barrier();
         const double xL = seg > 0 ? C(5, seg - 1, c) : 0.0;
         const double xR = seg < S - 1 ? C(4, seg + 1, c) : 0.0;
         double x[MMAX];
@@ -309,6 +322,7 @@ __global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag,
                 ptr += plane;
             }
         }
+        if (threadIdx.x == 0 && tn < ntiles) claim = (int)atomicAdd(&ctr[0], 1u);
         if (tn < ntiles) lamload(tn);
         t = tn;
         ++it;
