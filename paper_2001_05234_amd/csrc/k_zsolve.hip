@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NTMAX) void k_zsolve_part_grp(const ZJob *__restric
 // registers), so the next tile's fetch is in flight while the current one is
 // solved.  Per tile: each lane (one column, one segment of MMAX levels) runs
 // the single-sweep reduction (zp_sweep_reduce), wave 0 solves the interface
-// system of every column from both ends (zp_ends_*), each lane finishes its
+// system of every column from both ends (pipe_interface), each lane finishes its
 // segment and stores it.
 // DB (two tile buffers): the next fetch starts at the top of an iteration and
 // the rhs is read from LDS in the reduction and again in the finish.  !DB (one
@@ -152,6 +152,77 @@ typedef __attribute__((address_space(3))) void lds_void;
 __device__ __forceinline__ void pipe_lds_barrier()
 {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// The interface system of the pipelined solve in one layout for both roles.
+// Wave 0 solves it: lane L < 32 takes the top role of column L (segments 0,
+// 1, .. S/2-1), lane L + 32 the bottom role of the same column (segments S-1,
+// S-2, .. S/2), as zp_ends_forward / zp_ends_backward do, with the same
+// arithmetic.  Step i of a lane's role sits at R[(6 i + q) 64] (R = coef + L):
+// a segment of the lower half stores its coefficients (A,B,C,D,E,F) there in
+// order, one of the upper half in the bottom role's order (E,C,B,F,A,D), so
+// every access is the lane's base plus a constant offset.  Results: slot 4
+// of step i takes the unknown next to the role's start (u_s for the top role,
+// v_s for the bottom one), slot 5 the other.
+constexpr int kPipeRow = 2 * kPipeCols;  // doubles per coefficient row (both roles)
+constexpr int kPipeRole[6] = {4, 2, 1, 5, 0, 3};
+
+template <int NB>
+__device__ __forceinline__ void pipe_interface(double *R, int n)
+{
+    auto at = [&](int i, int q) -> double & { return R[(6 * i + q) * kPipeRow]; };
+    double y2p = 0, g2p = 0;
+#pragma unroll 1
+    for (int b0 = 0; b0 < n; b0 += NB) {
+        double A[NB], B[NB], Cc[NB], D[NB], E[NB], F[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = b0 + j < n ? b0 + j : n - 1;
+            A[j] = at(i, 0); B[j] = at(i, 1); Cc[j] = at(i, 2);
+            D[j] = at(i, 3); E[j] = at(i, 4); F[j] = at(i, 5);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = b0 + j;
+            if (i < n) {
+                const double inv = rcp64(1.0 - A[j] * g2p);
+                const double y1 = (D[j] - A[j] * y2p) * inv;
+                const double cg = Cc[j] * g2p;
+                const double y2 = (F[j] - Cc[j] * y2p) + cg * y1;
+                const double g1 = B[j] * inv;
+                const double g2 = E[j] + cg * g1;
+                at(i, 0) = y1;
+                at(i, 1) = y2;
+                at(i, 2) = g1;
+                at(i, 3) = g2;
+                g2p = g2;
+                y2p = y2;
+            }
+        }
+    }
+    const double y2o = __shfl_xor(y2p, 32, 64), g2o = __shfl_xor(g2p, 32, 64);
+    double prev = zp_ends_meet(y2p, g2p, y2o, g2o);
+#pragma unroll 1
+    for (int b0 = 0; b0 < n; b0 += NB) {
+        double Y1[NB], Y2[NB], G1[NB], G2[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i0 = n - 1 - (b0 + j);
+            const int i = i0 >= 0 ? i0 : 0;
+            Y1[j] = at(i, 0); Y2[j] = at(i, 1); G1[j] = at(i, 2); G2[j] = at(i, 3);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = n - 1 - (b0 + j);
+            if (i >= 0) {
+                const double o1 = Y1[j] - G1[j] * prev;
+                const double o2 = Y2[j] - G2[j] * prev;
+                at(i, 4) = o1;
+                at(i, 5) = o2;
+                prev = o1;
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -200,7 +271,15 @@ __global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag,
     const size_t plane = (size_t)ag.nx * ag.ny;
     // the six coefficients of a segment sit kPipeCols doubles apart, so one
     // base address per segment and column serves all of them
-    auto C = [&](int q, int s, int cc) -> double & { return coef[(s * 6 + q) * kPipeCols + cc]; };
+    // this lane's slot of the interface layout (pipe_interface), and where
+    // the unknowns beside its segment land: v of segment seg-1, u of seg+1
+    const int half = S / 2;
+    const bool upper = seg >= half;
+    double *cme = coef + (upper ? S - 1 - seg : seg) * 6 * kPipeRow + c + (upper ? kPipeCols : 0);
+    auto unk = [&](int s2, bool want_v) -> const double & {
+        const bool up = s2 >= half;
+        return coef[((up ? S - 1 - s2 : s2) * 6 + (up == want_v ? 4 : 5)) * kPipeRow + c + (up ? kPipeCols : 0)];
+    };
     // global->LDS: lane = (level in the group, 16-byte chunk of the level)
     constexpr int CHUNK = 16 / (int)sizeof(T);
     const int lrow = lane / (64 / G::RPI);
@@ -292,21 +371,12 @@ __global__ __launch_bounds__(kPipeThreads) void k_zsolve_pipe(T *data, ZArgs ag,
         double r[MMAX], out[6];
         zp_sweep_reduce<MMAX>(fv, za, zb, zc, lam, r, out);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) C(q, seg, c) = out[q];
+        for (int q = 0; q < 6; ++q) cme[q * kPipeRow] = upper ? out[kPipeRole[q]] : out[q];
         pipe_lds_barrier();
-        if (w == 0) {
-            // lanes [0, 32): top role, [32, 64): bottom role of column lane & 31
-            const bool bot = lane >= 32;
-            const int cc = lane & 31;
-            auto Cc = [&](int q, int s) -> double & { return C(q, s, cc); };
-            double y2, g2;
-            zp_ends_forward<4>(S, bot, Cc, y2, g2);
-            const double y2o = __shfl_xor(y2, 32, 64), g2o = __shfl_xor(g2, 32, 64);
-            zp_ends_backward<4>(S, bot, Cc, zp_ends_meet(y2, g2, y2o, g2o));
-        }
+        if (w == 0) pipe_interface<4>(coef + lane, half);
         pipe_lds_barrier();
-        const double xL = seg > 0 ? C(5, seg - 1, c) : 0.0;
-        const double xR = seg < S - 1 ? C(4, seg + 1, c) : 0.0;
+        const double xL = seg > 0 ? unk(seg - 1, true) : 0.0;
+        const double xR = seg < S - 1 ? unk(seg + 1, false) : 0.0;
         double x[MMAX];
         zp_sweep_finish<MMAX>(fv, za, zc, r, xL, xR, x);
         const size_t col = (size_t)t * kPipeCols + c;
