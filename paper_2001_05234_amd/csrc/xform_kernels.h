@@ -80,6 +80,8 @@ __device__ __forceinline__ void xform_x_body(const Tin *in, Tout *out, long nlin
         const long left = nlines - line0;
         const int avail = (int)((left < g.L ? left : (long)g.L) * M);
         const V2 *src2 = reinterpret_cast<const V2 *>(in + (size_t)line0 * n);
+        // every line of the tile on level k0: plain sums, weighted once
+        const bool one_level = j0 + g.L <= ny;
         for (int base = 0; base < P; base += SP * kThreads) {  // one round for the default tiles
             V2 v[SP];
 #pragma unroll
@@ -94,11 +96,15 @@ __device__ __forceinline__ void xform_x_body(const Tin *in, Tout *out, long nlin
                     const int l = (int)udiv((unsigned)idx, (unsigned)M, g.magM), m = idx - l * M;
                     const bool ok = idx < avail;
                     tile.at(m, l) = ok ? mk((T)v[u].x, (T)v[u].y) : mk(T(0), T(0));
-                    if (wsum_part && ok)
-                        acc += dzf[line_level(line0 + l, line0, k0, j0, ny)] * ((double)v[u].x + (double)v[u].y);
+                    if (wsum_part && ok) {
+                        const double s2 = (double)v[u].x + (double)v[u].y;
+                        if (one_level) acc += s2;
+                        else acc += dzf[line_level(line0 + l, line0, k0, j0, ny)] * s2;
+                    }
                 }
             }
         }
+        if (wsum_part && one_level) acc *= dzf[k0];
     } else {
         for (int idx = threadIdx.x; idx < n * g.L; idx += kThreads) {
             const int l = (int)udiv((unsigned)idx, (unsigned)n, g.magN), e = idx - l * n;
