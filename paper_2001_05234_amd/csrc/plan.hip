@@ -49,6 +49,10 @@ struct BatchGraph {
     // checks one block reduces
     FTable f_all, f_mean, f_x, f_n;
     std::vector<int> fin_solo_x, fin_solo_n, mean_solo;  // the others: their own launches
+    // capture branches: a step's groups touch disjoint problems and are
+    // captured side by side, one stream each, forked from and joined to cap
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
 };
 
 struct cans_plan_s {
@@ -365,6 +369,10 @@ void free_graph(BatchGraph &g)
     g.exec = nullptr;
     if (g.cap) (void)hipStreamDestroy(g.cap);
     g.cap = nullptr;
+    for (hipStream_t b : g.side) (void)hipStreamDestroy(b);
+    g.side.clear();
+    for (hipEvent_t e : g.ev) (void)hipEventDestroy(e);
+    g.ev.clear();
     if (g.d_tab) (void)hipFree(g.d_tab);
     g.d_tab = nullptr;
     g.tab_bytes = 0;
@@ -687,10 +695,46 @@ int build_groups(cans_plan_s *pl, const double *const *rhs, double *const *p)
     return CANS_OK;
 }
 
+// The groups of one step on their capture branches: fork from s, one side
+// stream a group, join back to s (one group: on s itself).  `evi` cycles
+// through the plan's events; each is waited on before it is recorded again.
 template <typename F>
-int each_group(const GroupStep &st, F launch)
+int each_group(const BatchGraph &bg, const GroupStep &st, hipStream_t s, size_t &evi, F launch)
 {
-    for (const GroupLaunch &gl : st.grp) CANS_TRY(launch(gl));
+    const size_t n = st.grp.size();
+    if (n <= 1 || bg.side.size() < n || bg.ev.empty()) {
+        for (const GroupLaunch &gl : st.grp) CANS_TRY(launch(gl, s));
+        return CANS_OK;
+    }
+    hipEvent_t fork = bg.ev[evi++ % bg.ev.size()];
+    if (hipEventRecord(fork, s) != hipSuccess) return CANS_ERR_HIP;
+    for (size_t i = 0; i < n; ++i) {
+        if (hipStreamWaitEvent(bg.side[i], fork, 0) != hipSuccess) return CANS_ERR_HIP;
+        CANS_TRY(launch(st.grp[i], bg.side[i]));
+    }
+    for (size_t i = 0; i < n; ++i) {
+        hipEvent_t join = bg.ev[evi++ % bg.ev.size()];
+        if (hipEventRecord(join, bg.side[i]) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess)
+            return CANS_ERR_HIP;
+    }
+    return CANS_OK;
+}
+
+// side streams and events for the widest step (before a capture)
+int make_branches(BatchGraph &bg)
+{
+    size_t w = 0;
+    for (const GroupStep *st : {&bg.xf, &bg.xi, &bg.yf, &bg.yi, &bg.z, &bg.rx, &bg.rn}) w = std::max(w, st->grp.size());
+    while (bg.side.size() < w) {
+        hipStream_t b = nullptr;
+        if (hipStreamCreateWithFlags(&b, hipStreamNonBlocking) != hipSuccess) return CANS_ERR_HIP;
+        bg.side.push_back(b);
+    }
+    while (bg.ev.size() < 16) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return CANS_ERR_HIP;
+        bg.ev.push_back(e);
+    }
     return CANS_OK;
 }
 
@@ -700,33 +744,43 @@ int enqueue_grouped(cans_plan_s *pl, const double *const *rhs, double *const *p,
 {
     const BatchGraph &bg = pl->g;
     const std::vector<Problem> &P = pl->probs;
+    size_t evi = 0;
     if (pl->opts.precision == CANS_PREC_FP64) {
-        CANS_TRY(each_group(bg.xf, [&](const GroupLaunch &g) { return launch_x_f64_grp(g, true, s); }));
-        CANS_TRY(each_group(bg.yf, [&](const GroupLaunch &g) { return launch_y_f64_grp(g, true, s); }));
-        CANS_TRY(each_group(bg.z, [&](const GroupLaunch &g) { return launch_zsolve_grp(g, false, s); }));
+        CANS_TRY(each_group(bg, bg.xf, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_x_f64_grp(g, true, b); }));
+        CANS_TRY(each_group(bg, bg.yf, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_y_f64_grp(g, true, b); }));
+        CANS_TRY(each_group(bg, bg.z, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_zsolve_grp(g, false, b); }));
         for (int i : bg.z.solo) CANS_TRY(launch_zsolve_f64(P[i], P[i].ws, p[i], P[i].ws.info + I_REMOVED, s));
-        CANS_TRY(each_group(bg.yi, [&](const GroupLaunch &g) { return launch_y_f64_grp(g, false, s); }));
-        CANS_TRY(each_group(bg.xi, [&](const GroupLaunch &g) { return launch_x_f64_grp(g, false, s); }));
+        CANS_TRY(each_group(bg, bg.yi, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_y_f64_grp(g, false, b); }));
+        CANS_TRY(each_group(bg, bg.xi, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_x_f64_grp(g, false, b); }));
         return CANS_OK;
     }
     const cans_opts &o = pl->opts;
     auto ystep = [&](bool fwd) {
-        return each_group(fwd ? bg.yf : bg.yi, [&](const GroupLaunch &g) { return launch_y_32_grp(g, fwd, s); });
+        return each_group(bg, fwd ? bg.yf : bg.yi, s, evi,
+                          [&](const GroupLaunch &g, hipStream_t b) { return launch_y_32_grp(g, fwd, b); });
     };
     auto zstep = [&](bool first) {
-        CANS_TRY(each_group(bg.z, [&](const GroupLaunch &g) { return launch_zsolve_grp(g, true, s); }));
+        CANS_TRY(each_group(bg, bg.z, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_zsolve_grp(g, true, b); }));
         for (int i : bg.z.solo)
             CANS_TRY(launch_zsolve_32(P[i], P[i].ws, P[i].ws.a32, nullptr, first ? nullptr : P[i].ws.flag, s));
         return (int)CANS_OK;
     };
     auto xinv = [&](bool update) {
-        CANS_TRY(each_group(bg.xi, [&](const GroupLaunch &g) { return launch_x_inv_32_grp(g, update, s); }));
+        CANS_TRY(each_group(bg, bg.xi, s, evi,
+                            [&](const GroupLaunch &g, hipStream_t b) { return launch_x_inv_32_grp(g, update, b); }));
         for (int i : bg.xi.solo)
             CANS_TRY(launch_x_inv_32(P[i], P[i].ws, P[i].ws.a32, p[i], update, update ? P[i].ws.flag : nullptr, s));
         return (int)CANS_OK;
     };
     auto rxstep = [&]() {
-        CANS_TRY(each_group(bg.rx, [&](const GroupLaunch &g) { return launch_resid_xfwd_grp(g, s); }));
+        CANS_TRY(each_group(bg, bg.rx, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_resid_xfwd_grp(g, b); }));
         for (int i : bg.rx.solo) CANS_TRY(launch_resid_xfwd(P[i], P[i].ws, rhs[i], p[i], P[i].ws.a32, P[i].ws.flag, s));
         return (int)CANS_OK;
     };
@@ -739,7 +793,8 @@ int enqueue_grouped(cans_plan_s *pl, const double *const *rhs, double *const *p,
         return (int)CANS_OK;
     };
     CANS_TRY(launch_reset_grp(bg.f_all.jobs, bg.f_all.n, s));
-    CANS_TRY(each_group(bg.xf, [&](const GroupLaunch &g) { return launch_x_fwd_32_grp(g, s); }));
+    CANS_TRY(each_group(bg, bg.xf, s, evi,
+                        [](const GroupLaunch &g, hipStream_t b) { return launch_x_fwd_32_grp(g, b); }));
     for (int i : bg.xf.solo) CANS_TRY(launch_x_fwd_32(P[i], P[i].ws, rhs[i], P[i].ws.a32, nullptr, s));
     if (bg.f_mean.n) CANS_TRY(launch_mean_rhs_grp(bg.f_mean.jobs, bg.f_mean.n, s));
     for (int i : bg.mean_solo) CANS_TRY(launch_mean_rhs(P[i], P[i].ws, s));
@@ -755,7 +810,8 @@ int enqueue_grouped(cans_plan_s *pl, const double *const *rhs, double *const *p,
         CANS_TRY(zstep(false));
         CANS_TRY(ystep(false));
         CANS_TRY(xinv(true));
-        CANS_TRY(each_group(bg.rn, [&](const GroupLaunch &g) { return launch_resid_norm_grp(g, s); }));
+        CANS_TRY(each_group(bg, bg.rn, s, evi,
+                            [](const GroupLaunch &g, hipStream_t b) { return launch_resid_norm_grp(g, b); }));
         CANS_TRY(check(1, it));
         if (it < o.max_iter) CANS_TRY(rxstep());
     }
@@ -939,6 +995,7 @@ int cans_poisson_solve_batched(cans_plan_t plan, const double *const *rhs, doubl
         g.key.clear();
         if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess) return CANS_ERR_HIP;
         CANS_TRY(build_groups(plan, rhs, p));
+        CANS_TRY(make_branches(g));
         if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return CANS_ERR_HIP;
         const int rc = enqueue_grouped(plan, rhs, p, g.cap);
         hipGraph_t graph = nullptr;
