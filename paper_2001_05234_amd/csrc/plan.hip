@@ -188,7 +188,8 @@ __global__ void k_fill_unit(double *a, size_t n)
 // Plan-time tuning of the transform tiles: for every transform kernel the
 // plan uses (x/y, forward/inverse, its precision), time the default tile and
 // the candidates with a quarter .. four times the lines per tile, each with
-// radix-8-first and radix-4-first plans, on a scratch field; keep the fastest.
+// radix-8-first and radix-4-first plans, on a scratch field, twice each; keep
+// the fastest.
 // Then, for a refinement plan whose x form is left to the library (AUTO) and
 // whose x axis the dense matrix-core form takes, time whole refined solves of
 // a scratch rhs with the FFT and with the dense x form and keep the faster
@@ -217,22 +218,28 @@ int autotune(cans_plan_s *pl, Problem &pb)
         (void)hipEventElapsedTime(&ms, e0, e1);
         return ms;
     };
+    // the default tile first, then the candidates; every one is timed in two
+    // passes over all of them and keeps its faster time (the first pass also
+    // brings the clocks up, so the first candidates timed are not handicapped)
     auto tune = [&](XGeom &slot, int axis, const Axis &ax, int elem, auto launch) {
-        XGeom best = slot;
-        float tbest = timeit(launch);
+        std::vector<XGeom> cand{slot};
         const int L0 = slot.L;
         for (int L : {L0 / 4, L0 / 2, L0, L0 * 2, L0 * 4})
             for (int rmax : {8, 4}) {
                 XGeom g;
                 if (L < 1 || (L == L0 && rmax == 8) || !make_geom(g, axis, ax.kind, ax.n, elem, L, rmax)) continue;
-                slot = g;
-                const float t = timeit(launch);
-                if (t < tbest) {
-                    tbest = t;
-                    best = g;
-                }
+                cand.push_back(g);
             }
-        slot = best;
+        std::vector<float> t(cand.size(), 1e30f);
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t i = 0; i < cand.size(); ++i) {
+                slot = cand[i];
+                t[i] = std::min(t[i], timeit(launch));
+            }
+        size_t best = 0;
+        for (size_t i = 1; i < cand.size(); ++i)
+            if (t[i] < t[best]) best = i;
+        slot = cand[best];
     };
     if (rc == CANS_OK) {
         if (pl->opts.precision == CANS_PREC_FP64) {
