@@ -49,8 +49,17 @@ static inline int rslice_blocks(const Problem &pb, const RSlice &rs)
     return 8 * pb.nz * rs.bpp;
 }
 
-// rows of the norm-only kernel (x lines per block)
-static inline int norm_rows(const Problem &pb) { return pb.nx <= kFlatMaxN ? flat_group(pb.nx) : 2; }
+// rows of the norm-only kernel (x lines per block): two of a long row; of
+// short rows (the flat form) four groups when the problem still has 1024
+// blocks or more (a block's closing reduction then serves four groups), else
+// one
+static inline int norm_rows(const Problem &pb)
+{
+    if (pb.nx > kFlatMaxN) return 2;
+    const int G = flat_group(pb.nx);
+    const long groups = ((long)pb.ny * pb.nz + G - 1) / G;
+    return groups >= 4096 ? 4 * G : G;
+}
 
 // rows of exactly one chunk take the kernels' exact form
 static inline bool exact_rows(const Problem &pb) { return pb.nx == kResidChunk; }
